@@ -1,0 +1,122 @@
+"""Pins of the oracle's reduce and scan against closed forms, brute force and
+library routines (none of which re-types the oracle's own loop).
+
+Sum reduction and inclusive scan are the "block-wide parallel reduction" and
+"scan" benchmarks of the paper's evaluation (Sec. 5).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+# ------------------------------------------------------------------ reduce
+@pytest.mark.parametrize("n,a,d", [(1, 5, 0), (1000, -500, 1), (4097, 1024, -1),
+                                   (1 << 16, -1024, 0), (123457, 3, 0)])
+def test_reduce_arithmetic_closed_form(n, a, d):
+    x = workloads.arithmetic_i32(n, a, d)
+    assert oracle.reduce_i32(x) == n * a + d * n * (n - 1) // 2
+
+
+def test_reduce_periodic_closed_form():
+    # x_i = (i mod 2049) - 1024: each full period sums to 0, the tail is an
+    # arithmetic run starting at -1024.
+    n = 3 * 2049 + 700
+    x = ((np.arange(n) % 2049) - 1024).astype(np.int32)
+    t = n % 2049
+    assert oracle.reduce_i32(x) == t * -1024 + t * (t - 1) // 2
+
+
+def test_reduce_bruteforce_tiny():
+    vals = (-2, -1, 0, 1, 2)
+    for length in range(0, 5):
+        for xs in itertools.product(vals, repeat=length):
+            assert oracle.reduce_i32(np.array(xs, dtype=np.int32)) == sum(xs)
+
+
+def test_reduce_no_int32_overflow():
+    # 2^20 copies of INT32_MAX / INT32_MIN: the exact total needs 51 bits.
+    n = 1 << 20
+    assert oracle.reduce_i32(np.full(n, 2**31 - 1, np.int32)) == n * (2**31 - 1)
+    assert oracle.reduce_i32(np.full(n, -2**31, np.int32)) == n * -2**31
+
+
+def test_reduce_matches_numpy_and_is_additive():
+    x = workloads.int_uniform(1 << 22, seed=1)
+    total = oracle.reduce_i32(x)
+    assert total == int(x.sum(dtype=np.int64))
+    cut = 1234567
+    assert total == oracle.reduce_i32(x[:cut]) + oracle.reduce_i32(x[cut:])
+
+
+def test_reduce_empty():
+    assert oracle.reduce_i32(np.zeros(0, np.int32)) == 0
+
+
+# ------------------------------------------------------------------ scan
+def _wrap32(v: int) -> int:
+    v &= 0xFFFFFFFF
+    return v - (1 << 32) if v >= (1 << 31) else v
+
+
+@pytest.mark.parametrize("n,a,d", [(1, -7, 0), (1000, -500, 1), (5000, 1024, -1), (70000, 3, 2)])
+def test_scan_arithmetic_closed_form(n, a, d):
+    x = workloads.arithmetic_i32(n, a, d)
+    y = oracle.scan_i32(x)
+    i = np.arange(n, dtype=object)
+    expect = [(_wrap32(int(k + 1) * a + d * int(k) * int(k + 1) // 2)) for k in i]
+    assert y.tolist() == expect
+
+
+def test_scan_bruteforce_tiny():
+    vals = (-2, 0, 1, 2)
+    for length in range(0, 5):
+        for xs in itertools.product(vals, repeat=length):
+            y = oracle.scan_i32(np.array(xs, dtype=np.int32))
+            assert y.tolist() == [sum(xs[: k + 1]) for k in range(length)]
+
+
+def test_scan_invariants_random():
+    x = workloads.int_uniform(1 << 20, seed=2)
+    y, wrapped, m = oracle.scan_i32(x, return_info=True)
+    assert not wrapped and m < 2**31
+    # last element == reduction (mod 2^32; no wrap here)
+    assert int(y[-1]) == oracle.reduce_i32(x)
+    # differences recover the input
+    d = np.diff(y.astype(np.int64))
+    assert np.array_equal(d, x[1:].astype(np.int64)) and y[0] == x[0]
+    # library cumsum
+    assert np.array_equal(y, np.cumsum(x, dtype=np.int64).astype(np.int32))
+
+
+def test_scan_wraps_modulo_2_32():
+    n = 4
+    x = np.full(n, 2**31 - 1, np.int32)
+    y, wrapped, m = oracle.scan_i32(x, return_info=True)
+    assert wrapped and m == n * (2**31 - 1)
+    assert y.tolist() == [_wrap32(k * (2**31 - 1)) for k in range(1, n + 1)]
+    # wrap arithmetic still recovers the input from differences
+    d = (y.astype(np.int64)[1:] - y.astype(np.int64)[:-1]) & 0xFFFFFFFF
+    assert np.array_equal(d.astype(np.uint32).view(np.int32), x[1:])
+
+
+def test_scan_last_equals_reduce_mod_2_32_under_wrap():
+    x = np.full(3000, 2**30 + 12345, np.int32)
+    y = oracle.scan_i32(x)
+    assert int(y[-1]) == _wrap32(oracle.reduce_i32(x))
+
+
+def test_scan_empty():
+    assert oracle.scan_i32(np.zeros(0, np.int32)).size == 0
+
+
+def test_scan_workload_never_wraps():
+    # The 2^28 workload keeps every prefix far inside int32, so the wrapped
+    # and exact scans coincide.  Checked on a 2^24 prefix of the same stream
+    # here (the full size is covered by the GPU parity test).
+    x = workloads.int_uniform(1 << 24, seed=2)
+    _, wrapped, m = oracle.scan_i32(x, return_info=True)
+    assert not wrapped and m < 2**28
