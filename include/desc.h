@@ -1,0 +1,110 @@
+/*
+ * desc.h -- C ABI of the MI355X (gfx950) data-parallel kernel library.
+ *
+ * The operations are the four computations the Descend paper evaluates
+ * (Sec. 5: block-wide parallel reduction, matrix transposition, scan and
+ * matrix multiplication) and their segmented / batched forms.  The argument
+ * conventions follow the paper's statement of a GPU function (Sec. 1,
+ * Listing 2; Sec. 3.3-3.4):
+ *
+ *   - inputs are shared, read-only references and outputs are unique
+ *     references: an output must not overlap any input (DESC_ERR_ALIAS);
+ *   - every array lives in GPU memory: a pointer the GPU would reach through
+ *     host memory is rejected (DESC_ERR_HOST_POINTER), the error the paper's
+ *     separation of cpu.mem and gpu.global rules out statically;
+ *   - sizes are element counts, never bytes, and the library derives the
+ *     launch shape itself, so a caller cannot launch more threads than there
+ *     are elements (the bytes-versus-elements mistake of Sec. 2);
+ *   - memory is owned by the caller; the library frees nothing it did not
+ *     allocate and allocates nothing in these calls.
+ *
+ * Every call is asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ * the default stream); none reads device memory from the host, allocates or
+ * synchronises, so a call may be captured into a HIP graph.  Arguments are
+ * checked in the order null -> size -> host pointer -> alias -> workspace,
+ * and a failed check returns before anything is launched.
+ *
+ * Workspace contract.  Calls that take `ws` keep a little state in it
+ * between calls (a generation number and counters) so that each runs as a
+ * single launch without a clearing pass.  A workspace must be filled with
+ * zero bytes once before its first use; after that the library leaves it
+ * ready for the next call.  Calls that share one workspace must be ordered
+ * (one stream, or synchronised): overlapping calls on one workspace race.
+ * The required size comes from the matching *_workspace() query.
+ */
+#ifndef DESC_H
+#define DESC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DESC_OK = 0,
+  DESC_ERR_NULL = -1,          /* a required pointer is NULL */
+  DESC_ERR_SIZE = -2,          /* negative size, or bytes overflow int64 */
+  DESC_ERR_HOST_POINTER = -3,  /* pointer is host memory or unknown to HIP */
+  DESC_ERR_ALIAS = -4,         /* an output overlaps an input */
+  DESC_ERR_WORKSPACE = -5,     /* workspace smaller than the query returned */
+  DESC_ERR_UNSUPPORTED = -6,   /* mode or shape the library does not provide */
+  DESC_ERR_HIP = -7,           /* a HIP call failed; see desc_last_hip_error() */
+  DESC_ERR_ALIGNMENT = -8      /* pointer not aligned to its element size */
+} desc_status;
+
+/* Human-readable name of a status code (static storage). */
+const char* desc_status_string(desc_status s);
+
+/* Raw hipError_t behind the last DESC_ERR_HIP returned to this thread. */
+int desc_last_hip_error(void);
+
+/* Library version, as MAJOR * 10000 + MINOR * 100 + PATCH. */
+int desc_version(void);
+
+/*
+ * Pointer classifier hook, for embedding and for exercising the argument
+ * checks on a machine without a GPU.  `fn(p)` returns 0 if `p` is GPU
+ * memory, 1 if it is host memory and -1 if it is unknown.  NULL restores the
+ * default classifier (hipPointerGetAttributes).  Process-wide.
+ */
+typedef int (*desc_pointer_classifier)(const void* p);
+void desc_set_pointer_classifier(desc_pointer_classifier fn);
+
+/* ------------------------------------------------------------------------
+ * Reduction (Sec. 5, "block-wide parallel reduction", read as the full sum).
+ * out[0] = sum of in[0..n), exact: int32 values are summed in int64.  n = 0
+ * writes 0.  `in` int32[n] (may be NULL when n = 0), `out` int64[1].
+ * ---------------------------------------------------------------------- */
+size_t desc_reduce_i32_workspace(int64_t n);
+desc_status desc_reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Inclusive scan (Sec. 5, "scan"): out[i] = in[0] + ... + in[i] modulo 2^32
+ * (two's-complement wrap), int32 in and out, out-of-place.  n = 0 launches
+ * nothing.
+ * ---------------------------------------------------------------------- */
+size_t desc_scan_i32_workspace(int64_t n);
+desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Transposition (Sec. 1, Listings 1-2; Sec. 5, "matrix transposition"):
+ * `in` is a row-major rows x cols matrix of 32-bit words, `out` receives
+ * the row-major cols x rows matrix with out[c][r] = in[r][c].  The words are
+ * moved as bit patterns.  The batched form transposes `batch` matrices
+ * stored one after another in both arrays.  Any size is accepted (ragged
+ * edges included); rows = 0 or cols = 0 launches nothing.
+ * ---------------------------------------------------------------------- */
+desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols,
+                               void* stream);
+desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batch,
+                                       int64_t rows, int64_t cols, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DESC_H */

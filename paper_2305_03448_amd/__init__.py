@@ -1,0 +1,197 @@
+"""Python binding of the MI355X kernel library (``libdesc.so``).
+
+Argument marshalling only: each function has the name of the C entry point it
+calls (declared in ``include/desc.h``), takes ``torch.Tensor`` arguments that
+live in GPU memory, passes their addresses, sizes and the current HIP stream,
+and turns a non-zero status into :class:`DescError`.  Every step of the
+computation runs in the library's HIP kernels; there is no other path, and
+importing this module fails loudly when the library has not been built.
+
+Workspaces: calls that keep state in a workspace get one from a per-device
+cache when ``ws`` is omitted.  The cache hands out zero-filled buffers and
+keeps them for later calls, which is the contract the library expects (zero
+before the first use, reused by ordered calls afterwards).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdesc.so")
+
+__all__ = [
+    "DescError", "lib", "desc_status_string", "desc_version",
+    "desc_reduce_i32_workspace", "desc_reduce_i32",
+    "desc_scan_i32_workspace", "desc_scan_i32",
+    "desc_transpose_f32", "desc_transpose_batched_f32",
+]
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_ST = ctypes.c_int
+
+# name -> (restype, argtypes) of every exported entry point.
+SIGNATURES = {
+    "desc_status_string": (ctypes.c_char_p, [_ST]),
+    "desc_last_hip_error": (ctypes.c_int, []),
+    "desc_version": (ctypes.c_int, []),
+    "desc_set_pointer_classifier": (None, [_P]),
+    "desc_reduce_i32_workspace": (_SZ, [_I64]),
+    "desc_reduce_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
+    "desc_scan_i32_workspace": (_SZ, [_I64]),
+    "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
+    "desc_transpose_f32": (_ST, [_P, _P, _I64, _I64, _P]),
+    "desc_transpose_batched_f32": (_ST, [_P, _P, _I64, _I64, _I64, _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it first (python -c "
+                "'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DescError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().desc_status_string(status).decode()
+        if status == -7:
+            msg += f" (hipError {lib().desc_last_hip_error()})"
+        super().__init__(f"{where}: {msg}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise DescError(status, where)
+
+
+def desc_status_string(status: int) -> str:
+    return lib().desc_status_string(status).decode()
+
+
+def desc_version() -> int:
+    return lib().desc_version()
+
+
+# ------------------------------------------------------------------ plumbing
+def _stream(t: torch.Tensor, stream):
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be in GPU memory (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() > 0 else 0)
+
+
+_ws_cache: dict = {}
+
+
+def workspace(kind: str, nbytes: int, device) -> torch.Tensor:
+    """A zero-filled workspace of at least ``nbytes`` kept per (device, kind)."""
+    device = torch.device(device)
+    key = (device.index if device.index is not None else torch.cuda.current_device(), kind)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _ws(kind, nbytes, ref: torch.Tensor, ws):
+    if ws is None:
+        return workspace(kind, nbytes, ref.device)
+    return _dev(ws, torch.uint8, "ws")
+
+
+# ------------------------------------------------------------------ reduce
+def desc_reduce_i32_workspace(n: int) -> int:
+    return lib().desc_reduce_i32_workspace(n)
+
+
+def desc_reduce_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """out[0] = exact int64 sum of int32 ``x``."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int64, "out")
+    if out.numel() != 1:
+        raise ValueError("out must hold one int64")
+    n = x.numel()
+    w = _ws("reduce_i32", desc_reduce_i32_workspace(n), x, ws)
+    _check(lib().desc_reduce_i32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(), _stream(x, stream)),
+           "desc_reduce_i32")
+    return out
+
+
+# ------------------------------------------------------------------ scan
+def desc_scan_i32_workspace(n: int) -> int:
+    return lib().desc_scan_i32_workspace(n)
+
+
+def desc_scan_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """Inclusive scan of int32 ``x`` into ``out`` (wrapping modulo 2^32)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many elements as x")
+    n = x.numel()
+    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
+    _check(lib().desc_scan_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
+           "desc_scan_i32")
+    return out
+
+
+# ------------------------------------------------------------------ transpose
+def _as_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dtype in (torch.int32, torch.uint32) and t.device.type == "cuda":
+        t = t.view(torch.float32)
+    return _dev(t, torch.float32, name)
+
+
+def desc_transpose_f32(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out (cols x rows) = transpose of the row-major rows x cols ``x``."""
+    x = _as_f32(x, "x"); o = _as_f32(out, "out")
+    if x.dim() != 2 or o.dim() != 2 or tuple(o.shape) != (x.shape[1], x.shape[0]):
+        raise ValueError("x must be (rows, cols) and out (cols, rows)")
+    _check(lib().desc_transpose_f32(_ptr(x), _ptr(o), x.shape[0], x.shape[1],
+                                    _stream(x, stream)), "desc_transpose_f32")
+    return out
+
+
+def desc_transpose_batched_f32(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[b] = transpose of x[b] for a (batch, rows, cols) ``x``."""
+    x = _as_f32(x, "x"); o = _as_f32(out, "out")
+    if x.dim() != 3 or tuple(o.shape) != (x.shape[0], x.shape[2], x.shape[1]):
+        raise ValueError("x must be (batch, rows, cols) and out (batch, cols, rows)")
+    _check(lib().desc_transpose_batched_f32(_ptr(x), _ptr(o), x.shape[0], x.shape[1],
+                                            x.shape[2], _stream(x, stream)),
+           "desc_transpose_batched_f32")
+    return out

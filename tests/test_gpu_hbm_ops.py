@@ -1,0 +1,183 @@
+"""Parity of the HIP reduce, scan and transpose with the CPU oracle, bit for
+bit, called through the C ABI (the Python binding marshals arguments only).
+
+Sizes span one wave, one tile, many tiles and ragged tails; the full
+workload sizes (2^22 reduce, 2^28 scan, 8192 x 8192 transpose) run in the
+same launch configuration as the benchmark."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2305_03448_amd as desc
+import workloads
+from gpu_util import case, dev, needs_gpu, to_dev
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+EDGE_SIZES = [1, 2, 3, 4, 5, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4095, 4096, 4097,
+              8191, 8192, 8193, 12289, 65535, 65536, 65537, 1_000_003, (1 << 20) + 7]
+
+
+# ------------------------------------------------------------------ reduce
+@pytest.mark.parametrize("n", [0] + EDGE_SIZES)
+def test_reduce_edge_sizes(n):
+    case(f"reduce n={n}")
+    x = workloads.int_uniform(n, seed=100 + n % 97)
+    out = torch.full((1,), -1, dtype=torch.int64, device=dev())
+    desc.desc_reduce_i32(to_dev(x), out)
+    assert int(out.item()) == oracle.reduce_i32(x)
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+@pytest.mark.parametrize("n", [5, 4097, 300_001])
+def test_reduce_unaligned(n, offset):
+    case(f"reduce unaligned n={n} offset={offset}")
+    x = workloads.int_uniform(n, seed=7)
+    out = torch.empty(1, dtype=torch.int64, device=dev())
+    desc.desc_reduce_i32(to_dev(x, offset), out)
+    assert int(out.item()) == oracle.reduce_i32(x)
+
+
+def test_reduce_extremes_exact():
+    n = (1 << 20) + 3
+    for v in (2**31 - 1, -2**31):
+        case(f"reduce extremes v={v}")
+        x = np.full(n, v, np.int32)
+        out = torch.empty(1, dtype=torch.int64, device=dev())
+        desc.desc_reduce_i32(to_dev(x), out)
+        assert int(out.item()) == oracle.reduce_i32(x) == n * v
+
+
+def test_reduce_workload_and_reuse():
+    # the 2^22 workload (seed 1), then repeated calls on the same workspace
+    x = workloads.int_uniform(1 << 22, seed=1)
+    xt = to_dev(x)
+    want = oracle.reduce_i32(x)
+    out = torch.empty(1, dtype=torch.int64, device=dev())
+    for rep in range(5):
+        case(f"reduce 2^22 rep {rep}")
+        desc.desc_reduce_i32(xt, out)
+        assert int(out.item()) == want
+    small = xt[:1000]
+    desc.desc_reduce_i32(small, out)
+    assert int(out.item()) == oracle.reduce_i32(x[:1000])
+
+
+def test_reduce_large_2_28():
+    case("reduce 2^28")
+    x = workloads.int_uniform(1 << 28, seed=2)
+    out = torch.empty(1, dtype=torch.int64, device=dev())
+    desc.desc_reduce_i32(to_dev(x), out)
+    assert int(out.item()) == oracle.reduce_i32(x)
+
+
+# ------------------------------------------------------------------ scan
+@pytest.mark.parametrize("n", EDGE_SIZES)
+def test_scan_edge_sizes(n):
+    case(f"scan n={n}")
+    x = workloads.int_uniform(n, seed=200 + n % 89)
+    y = torch.full((n,), 7, dtype=torch.int32, device=dev())
+    desc.desc_scan_i32(to_dev(x), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_i32(x))
+
+
+@pytest.mark.parametrize("offset", [1, 3])
+@pytest.mark.parametrize("n", [7, 4097, 300_001])
+def test_scan_unaligned(n, offset):
+    case(f"scan unaligned n={n} offset={offset}")
+    x = workloads.int_uniform(n, seed=9)
+    y = torch.empty(n + offset, dtype=torch.int32, device=dev())[offset:]
+    desc.desc_scan_i32(to_dev(x, offset), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_i32(x))
+
+
+def test_scan_wraps_modulo_2_32():
+    case("scan wrap")
+    n = 1 << 20
+    x = np.full(n, 2**31 - 1000, np.int32)
+    y = torch.empty(n, dtype=torch.int32, device=dev())
+    desc.desc_scan_i32(to_dev(x), y)
+    want, wrapped, _ = oracle.scan_i32(x, return_info=True)
+    assert wrapped
+    assert np.array_equal(y.cpu().numpy(), want)
+
+
+def test_scan_workspace_reuse_varying_sizes():
+    # generation tags: consecutive calls of different sizes on one workspace
+    ws = torch.zeros(desc.desc_scan_i32_workspace(1 << 22), dtype=torch.uint8, device=dev())
+    for rep, n in enumerate([1 << 22, 5000, (1 << 21) + 17, 1, 1 << 22, 123457]):
+        case(f"scan reuse rep={rep} n={n}")
+        x = workloads.int_uniform(n, seed=300 + rep)
+        y = torch.empty(n, dtype=torch.int32, device=dev())
+        desc.desc_scan_i32(to_dev(x), y, ws=ws)
+        assert np.array_equal(y.cpu().numpy(), oracle.scan_i32(x))
+
+
+def test_scan_workload_2_28():
+    case("scan 2^28 (seed 2)")
+    x = workloads.int_uniform(1 << 28, seed=2)
+    y = torch.empty(1 << 28, dtype=torch.int32, device=dev())
+    xt = to_dev(x)
+    desc.desc_scan_i32(xt, y)
+    want = oracle.scan_i32(x)
+    assert np.array_equal(y.cpu().numpy(), want)
+    # again on the same workspace (the benchmark calls it back to back)
+    y.fill_(0)
+    desc.desc_scan_i32(xt, y)
+    assert np.array_equal(y.cpu().numpy(), want)
+
+
+# ------------------------------------------------------------------ transpose
+SHAPES = [(1, 1), (1, 37), (37, 1), (4, 4), (64, 64), (65, 129), (300, 7), (128, 256),
+          (256, 64), (63, 65), (1000, 4), (4, 1000), (129, 4100)]
+
+
+@pytest.mark.parametrize("rows,cols", SHAPES)
+def test_transpose_self_describing(rows, cols):
+    case(f"transpose {rows}x{cols}")
+    m = workloads.self_describing_u32(rows, cols)
+    t = torch.empty((cols, rows), dtype=torch.int32, device=dev())
+    desc.desc_transpose_f32(to_dev(m.view(np.int32)), t)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), oracle.transpose_u32(m))
+
+
+def test_transpose_bits_and_involution():
+    case("transpose bit patterns")
+    g = workloads.rng(5)
+    m = g.integers(0, 2**32, size=(192, 320), dtype=np.uint64).astype(np.uint32)
+    m[0, :6] = [0x7FC00001, 0xFFBADBAD, 0x80000000, 0x00000001, 0x7F800000, 0xFF800000]
+    a = to_dev(m.view(np.float32))
+    t = torch.empty((320, 192), dtype=torch.float32, device=dev())
+    desc.desc_transpose_f32(a, t)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), oracle.transpose_u32(m))
+    back = torch.empty_like(a)
+    desc.desc_transpose_f32(t, back)
+    assert np.array_equal(back.cpu().numpy().view(np.uint32), m)
+
+
+@pytest.mark.parametrize("offset", [1, 2])
+def test_transpose_unaligned(offset):
+    case(f"transpose unaligned offset={offset}")
+    m = workloads.matrix_f32(200, 136, seed=3)
+    t = torch.empty(136 * 200 + offset, dtype=torch.float32, device=dev())[offset:].view(136, 200)
+    desc.desc_transpose_f32(to_dev(m, offset), t)
+    assert np.array_equal(t.cpu().numpy(), oracle.transpose_u32(m))
+
+
+def test_transpose_batched():
+    case("transpose batched 5 x 130 x 70")
+    ms = workloads.matrix_f32(5 * 130, 70, seed=4).reshape(5, 130, 70)
+    t = torch.empty((5, 70, 130), dtype=torch.float32, device=dev())
+    desc.desc_transpose_batched_f32(to_dev(ms), t)
+    got = t.cpu().numpy()
+    for b in range(5):
+        assert np.array_equal(got[b], oracle.transpose_u32(ms[b]))
+
+
+def test_transpose_workload_8192():
+    case("transpose 8192x8192 (seed 3)")
+    m = workloads.matrix_f32(8192, 8192, seed=3)
+    t = torch.empty((8192, 8192), dtype=torch.float32, device=dev())
+    desc.desc_transpose_f32(to_dev(m), t)
+    assert np.array_equal(t.cpu().numpy(), oracle.transpose_u32(m))
