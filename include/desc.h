@@ -103,6 +103,44 @@ desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_
 desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batch,
                                        int64_t rows, int64_t cols, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Copy of n 32-bit words: the plain bandwidth ceiling the HBM-bound
+ * operations are measured against.  `in` and `out` must not overlap.
+ * ---------------------------------------------------------------------- */
+desc_status desc_copy_32(const void* in, void* out, int64_t n, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Configurations.  Tile shapes are compile-time parameters of the kernels
+ * (the paper keeps sizes as nats in the types); each operation is compiled
+ * for a few shapes and a table picks one per problem-size class.  The
+ * built-in table can be overridden per class, or from a text file written
+ * by the offline tuner with lines "<op name> <size class> <config name>"
+ * ('#' starts a comment).  Process-wide; changing it while calls are in
+ * flight only affects later calls.
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  DESC_OP_REDUCE_I32 = 0,
+  DESC_OP_SCAN_I32 = 1,
+  DESC_OP_TRANSPOSE_32 = 2,
+  DESC_OP_COPY_32 = 3,
+  DESC_OP_GEMM_F32 = 4,
+  DESC_OP_GEMM_BF16X3 = 5,
+  DESC_OP_GEMM_FP8 = 6,
+  DESC_OP_SEG_REDUCE_I32 = 7,
+  DESC_OP_SEG_SCAN_I32 = 8,
+  DESC_OP_GEMM_GROUPED = 9
+} desc_op;
+
+int desc_config_count(desc_op op);                     /* 0 for an op not built */
+const char* desc_config_name(desc_op op, int cfg);     /* NULL if out of range */
+const char* desc_op_name(desc_op op);                  /* NULL if not built */
+/* Size class (0..3) of a problem: element count, or M*N*K for GEMM. */
+int desc_size_class(desc_op op, int64_t size);
+/* cfg < 0 restores the built-in choice; DESC_ERR_UNSUPPORTED if out of range. */
+desc_status desc_config_set(desc_op op, int size_class, int cfg);
+int desc_config_get(desc_op op, int size_class);       /* -1 if out of range */
+desc_status desc_config_load(const char* path);
+
 #ifdef __cplusplus
 }
 #endif

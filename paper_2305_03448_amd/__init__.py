@@ -26,7 +26,9 @@ __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
     "desc_scan_i32_workspace", "desc_scan_i32",
-    "desc_transpose_f32", "desc_transpose_batched_f32",
+    "desc_transpose_f32", "desc_transpose_batched_f32", "desc_copy_32",
+    "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
+    "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
 ]
 
 _P = ctypes.c_void_p
@@ -46,7 +48,21 @@ SIGNATURES = {
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_transpose_f32": (_ST, [_P, _P, _I64, _I64, _P]),
     "desc_transpose_batched_f32": (_ST, [_P, _P, _I64, _I64, _I64, _P]),
+    "desc_copy_32": (_ST, [_P, _P, _I64, _P]),
+    "desc_config_count": (ctypes.c_int, [ctypes.c_int]),
+    "desc_config_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
+    "desc_op_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "desc_size_class": (ctypes.c_int, [ctypes.c_int, _I64]),
+    "desc_config_set": (_ST, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "desc_config_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "desc_config_load": (_ST, [ctypes.c_char_p]),
 }
+
+# desc_op values (include/desc.h)
+OPS = {"reduce_i32": 0, "scan_i32": 1, "transpose_32": 2, "copy_32": 3, "gemm_f32": 4,
+       "gemm_bf16x3": 5, "gemm_fp8": 6, "seg_reduce_i32": 7, "seg_scan_i32": 8,
+       "gemm_grouped": 9}
+TUNE_FILE = os.path.join(HERE, "tune_gfx950.txt")
 
 _lib = None
 
@@ -65,6 +81,8 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        if os.path.exists(TUNE_FILE):
+            _check(L.desc_config_load(TUNE_FILE.encode()), "desc_config_load")
     return _lib
 
 
@@ -195,3 +213,52 @@ def desc_transpose_batched_f32(x: torch.Tensor, out: torch.Tensor, stream=None) 
                                             x.shape[2], _stream(x, stream)),
            "desc_transpose_batched_f32")
     return out
+
+
+# ------------------------------------------------------------------ copy
+def desc_copy_32(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out = x, for tensors of 32-bit elements (the bandwidth ceiling)."""
+    if x.device.type != "cuda" or out.device.type != "cuda":
+        raise ValueError("x and out must be in GPU memory")
+    if x.element_size() != 4 or out.element_size() != 4 or x.numel() != out.numel():
+        raise ValueError("x and out must hold the same number of 32-bit elements")
+    if not (x.is_contiguous() and out.is_contiguous()):
+        raise ValueError("x and out must be contiguous")
+    _check(lib().desc_copy_32(_ptr(x), _ptr(out), x.numel(), _stream(x, stream)),
+           "desc_copy_32")
+    return out
+
+
+# ------------------------------------------------------------------ configurations
+def _op(op) -> int:
+    return OPS[op] if isinstance(op, str) else int(op)
+
+
+def desc_config_count(op) -> int:
+    return lib().desc_config_count(_op(op))
+
+
+def desc_config_name(op, cfg: int):
+    r = lib().desc_config_name(_op(op), cfg)
+    return r.decode() if r else None
+
+
+def desc_op_name(op):
+    r = lib().desc_op_name(_op(op))
+    return r.decode() if r else None
+
+
+def desc_size_class(op, size: int) -> int:
+    return lib().desc_size_class(_op(op), size)
+
+
+def desc_config_set(op, size_class: int, cfg: int) -> None:
+    _check(lib().desc_config_set(_op(op), size_class, cfg), "desc_config_set")
+
+
+def desc_config_get(op, size_class: int) -> int:
+    return lib().desc_config_get(_op(op), size_class)
+
+
+def desc_config_load(path: str) -> None:
+    _check(lib().desc_config_load(path.encode()), "desc_config_load")

@@ -10,6 +10,10 @@
 
 #include "../../include/desc.h"
 #include "launch.hpp"
+#include "tuning.hpp"
+
+#include <stdio.h>
+#include <string.h>
 
 namespace {
 
@@ -106,10 +110,7 @@ void desc_set_pointer_classifier(desc_pointer_classifier fn) {
 }
 
 // ----------------------------------------------------------------- reduce
-size_t desc_reduce_i32_workspace(int64_t n) {
-  (void)n;
-  return desc::launch::reduce_i32_workspace();
-}
+size_t desc_reduce_i32_workspace(int64_t n) { return desc::launch::reduce_i32_workspace(n); }
 
 desc_status desc_reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws,
                             size_t ws_bytes, void* stream) {
@@ -156,7 +157,7 @@ desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batc
   if (nb < 0) return DESC_ERR_SIZE;
   if (nb > 0 && (in == nullptr || out == nullptr)) return DESC_ERR_NULL;
   if (nb == 0) return DESC_OK;
-  if (rows > (int64_t)65535 * 64 || batch > 65535 || (cols + 63) / 64 > INT32_MAX)
+  if (rows > desc::launch::transpose_max_rows() || batch > 65535 || cols > INT32_MAX)
     return DESC_ERR_UNSUPPORTED;
   DESC_TRY(check_device({in, out}));
   if (misaligned(in, 4) || misaligned(out, 4)) return DESC_ERR_ALIGNMENT;
@@ -168,6 +169,60 @@ desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batc
 desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols,
                                void* stream) {
   return desc_transpose_batched_f32(in, out, 1, rows, cols, stream);
+}
+
+// ----------------------------------------------------------------- copy
+desc_status desc_copy_32(const void* in, void* out, int64_t n, void* stream) {
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (nb > 0 && (in == nullptr || out == nullptr)) return DESC_ERR_NULL;
+  if (nb == 0) return DESC_OK;
+  DESC_TRY(check_device({in, out}));
+  if (misaligned(in, 4) || misaligned(out, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb})) return DESC_ERR_ALIAS;
+  return hip_status(
+      desc::launch::copy_32((const uint32_t*)in, (uint32_t*)out, n, (hipStream_t)stream));
+}
+
+// ----------------------------------------------------------------- configurations
+int desc_config_count(desc_op op) { return desc::tune::config_count((int)op); }
+
+const char* desc_config_name(desc_op op, int cfg) { return desc::tune::config_name((int)op, cfg); }
+
+const char* desc_op_name(desc_op op) { return desc::tune::op_name((int)op); }
+
+int desc_size_class(desc_op op, int64_t size) { return desc::tune::size_class((int)op, size); }
+
+desc_status desc_config_set(desc_op op, int size_class, int cfg) {
+  return desc::tune::set((int)op, size_class, cfg) ? DESC_OK : DESC_ERR_UNSUPPORTED;
+}
+
+int desc_config_get(desc_op op, int size_class) {
+  if ((int)op < 0 || (int)op >= desc::tune::kNumOps || size_class < 0 ||
+      size_class >= desc::tune::kClasses)
+    return -1;
+  return desc::tune::get((int)op, size_class);
+}
+
+desc_status desc_config_load(const char* path) {
+  if (path == nullptr) return DESC_ERR_NULL;
+  FILE* f = fopen(path, "r");
+  if (f == nullptr) return DESC_ERR_UNSUPPORTED;
+  char line[256];
+  desc_status st = DESC_OK;
+  while (fgets(line, sizeof line, f)) {
+    char op[64], cfg[64];
+    int cls = -1;
+    if (line[0] == '#' || sscanf(line, "%63s %d %63s", op, &cls, cfg) != 3) continue;
+    int o = -1, c = -1;
+    for (int i = 0; i < desc::tune::kNumOps; ++i)
+      if (desc::tune::op_name(i) && strcmp(desc::tune::op_name(i), op) == 0) o = i;
+    for (int j = 0; o >= 0 && j < desc::tune::config_count(o); ++j)
+      if (strcmp(desc::tune::config_name(o, j), cfg) == 0) c = j;
+    if (o < 0 || c < 0 || !desc::tune::set(o, cls, c)) st = DESC_ERR_UNSUPPORTED;
+  }
+  fclose(f);
+  return st;
 }
 
 }  // extern "C"

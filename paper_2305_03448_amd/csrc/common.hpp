@@ -34,23 +34,28 @@ __device__ __forceinline__ void store_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wait until every global memory access this wave issued has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).  After it a
+// device-scope atomic store is visible to every agent-scope reader.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Workspace header shared by the single-launch kernels that keep state
 // between calls (see the workspace contract in desc.h): a generation number
-// that tags every status word written in one call, a dynamic work counter
-// and a count of finished blocks.  The block that finishes last resets the
-// counters and advances the generation, so the next call on the same
-// workspace needs no clearing pass.
+// that tags every status word written in one call.  The block that finishes
+// the call advances it, once every other block of the call has read it, so
+// the next call on the same workspace needs no clearing pass.  No counter is
+// shared between blocks: same-address device-scope atomics serialise in the
+// memory-side atomic unit (tens of ns each), which would cap the tile rate.
 struct WsHeader {
   uint32_t gen;
-  uint32_t next;
-  uint32_t done;
   uint32_t error;     // set non-zero when a call found the workspace inconsistent
-  uint32_t pad[12];
+  uint32_t pad[14];
 };
 
-// Upper bound on the polls of one look-back wait.  A wait that exceeds it can
-// only come from a workspace that was not zeroed before its first use; the
-// kernel then records the error and finishes instead of spinning forever.
+// Upper bound on the polls of one wait for another block.  A wait that
+// exceeds it can only come from a workspace that was not zeroed before its
+// first use; the kernel then records the error and finishes instead of
+// spinning forever.
 constexpr uint32_t kSpinLimit = 1u << 20;
 static_assert(sizeof(WsHeader) == 64, "header is one 64-byte line");
 

@@ -1,14 +1,19 @@
 // reduce.hip -- exact sum of int32 values into an int64 (the "block-wide
 // parallel reduction" benchmark of Sec. 5, read as the full sum).
 //
-// One launch.  The grid is at most kReduceMaxBlocks blocks; block b takes
-// the 16-byte-vector tiles b, b + grid, b + 2*grid, ... ([tiles][UNROLL]
-// [BLOCK] int32x4, so every load instruction of a wave reads 1 KiB of
-// consecutive memory).  Each lane sums into an int64, the wave sums with
-// shuffles, the block's waves meet in LDS, and thread 0 publishes the block
-// sum.  The block that finishes last (counted in the workspace header) adds
-// the published sums in a fixed order, writes the result and resets the
-// counter, so the workspace is ready for the next call.
+// One launch.  Block b takes the 16-byte-vector tiles b, b + grid,
+// b + 2*grid, ... ([tiles][UNROLL][BLOCK] int32x4, so every load instruction
+// of a wave reads 1 KiB of consecutive memory).  Each lane sums into an
+// int64, the wave sums with shuffles, the block's waves meet in LDS, and
+// thread 0 publishes the block sum in the block's slot of the workspace as
+// one 64-bit word {tag:13, value:51}, the tag naming the call's generation.
+// The last block of the grid waits until every slot carries the current tag,
+// adds the slots in a fixed order, writes the result and advances the
+// generation.  No block waits on a later one and no counter is shared, so
+// there are no same-address atomics and no fences.
+//
+// The grid is sized so that no block sums more than 2^19 elements, which
+// bounds a block sum by 2^50 in magnitude and fits the 51-bit field.
 //
 // Integer addition is associative, so the result is the exact sum whatever
 // the order.  The head (up to 3 elements before the first 16-byte boundary)
@@ -16,6 +21,7 @@
 // grid with scalar loads.
 #include "common.hpp"
 #include "launch.hpp"
+#include "tuning.hpp"
 #include "view.hpp"
 #include "wave.hpp"
 
@@ -26,6 +32,18 @@ constexpr int kBlock = 256;
 constexpr int kUnroll = 4;                        // int32x4 per lane per tile
 constexpr int kTileVec = kBlock * kUnroll;        // int32x4 per tile
 constexpr int kTile = kTileVec * 4;               // int32 per tile
+
+constexpr int kValueBits = 51;
+constexpr uint64_t kValueMask = (1ull << kValueBits) - 1;
+constexpr uint32_t kTagPeriod = 8191;             // tags 1..8191; 0 never valid
+
+__device__ __forceinline__ uint64_t tag_of(uint32_t gen) { return 1u + gen % kTagPeriod; }
+__device__ __forceinline__ uint64_t pack_sum(int64_t v, uint32_t gen) {
+  return (tag_of(gen) << kValueBits) | ((uint64_t)v & kValueMask);
+}
+__device__ __forceinline__ int64_t unpack_sum(uint64_t w) {   // sign-extend 51 bits
+  return (int64_t)(w << (64 - kValueBits)) >> (64 - kValueBits);
+}
 
 __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
   constexpr int NW = kBlock / kWave;
@@ -47,9 +65,10 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
     int64_t nhead, const int32_t* __restrict__ tail, int64_t ntail, int64_t* __restrict__ out,
     WsHeader* __restrict__ hdr, uint64_t* __restrict__ partials) {
   __shared__ int64_t lds[kBlock / kWave];
-  __shared__ uint32_t s_last;
+  __shared__ uint32_t s_gen;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
+  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
 
   // tiles -> rounds -> threads: [ntiles][kUnroll][kBlock]
   auto tiles = array(body, ntiles * kTileVec).group<kBlock>().group<kUnroll>();
@@ -64,42 +83,66 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
     for (int u = 0; u < kUnroll; ++u)
       acc += (int64_t)q[u].x + (int64_t)q[u].y + (int64_t)q[u].z + (int64_t)q[u].w;
   }
-  if (block.index() == block.count() - 1) {
+  const bool last = block.index() == block.count() - 1;
+  if (last) {
     auto h = array(head, nhead);
     auto tl = array(tail, ntail);
     for (idx_t i = thread.index(); i < nhead; i += kBlock) acc += h[i];
     for (idx_t i = thread.index(); i < ntail; i += kBlock) acc += tl[i];
   }
-  const int64_t s = block_sum(acc, lds);
-
-  // Publish; the release orders the block sum before the count.
-  if (thread.index() == 0) {
-    store_status(&partials[block.index()], (uint64_t)s);
-    const uint32_t prev =
-        __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (uint32_t)(block.count() - 1));
-  }
-  sync(thread);
-  if (!s_last) return;
-
-  // Last block: sum the published block sums.
+  const int64_t s = block_sum(acc, lds);   // (its barrier also publishes s_gen)
+  const uint32_t gen = s_gen;
   auto parts = array(partials, block.count());
-  int64_t acc2 = 0;
-  for (idx_t b = thread.index(); b < parts.extent(); b += kBlock)
-    acc2 += (int64_t)load_status(&parts[b]);
+  if (!last) {
+    if (thread.index() == 0) store_status(&parts[block.index()], pack_sum(s, gen));
+    return;
+  }
+
+  // Last block: wait for every slot of this generation, then add them.
+  const uint64_t want = tag_of(gen);
+  int64_t acc2 = thread.index() == 0 ? s : 0;
+  for (idx_t b = thread.index(); b < parts.extent() - 1; b += kBlock) {
+    uint64_t w = load_status(&parts[b]);
+    for (uint32_t polls = 0; (w >> kValueBits) != want; ++polls) {
+      if (polls == kSpinLimit) {     // inconsistent workspace
+        store_u32(&hdr->error, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      w = load_status(&parts[b]);
+    }
+    acc2 += unpack_sum(w);
+  }
   sync(thread);   // lds is reused
   const int64_t total = block_sum(acc2, lds);
   if (thread.index() == 0) {
     out[0] = total;
-    store_u32(&hdr->done, 0u);
+    store_u32(&hdr->gen, gen + 1u);
   }
 }
+
+constexpr const char* kNames[] = {"b256_u4_nt"};
+constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
+const bool kRegistered =
+    (tune::register_op(tune::kReduceI32, "reduce_i32", 1, kNames, kDefaults), true);
 
 }  // namespace
 
 namespace launch {
 
-size_t reduce_i32_workspace() { return sizeof(WsHeader) + sizeof(uint64_t) * kReduceMaxBlocks; }
+// Grid: one block per tile up to kReduceMaxBlocks, more when needed to keep
+// a block's share at most 2^19 elements.
+static int64_t reduce_grid(int64_t n) {
+  const int64_t ntiles = n / kTile;
+  int64_t grid = ntiles < kReduceMaxBlocks ? ntiles : kReduceMaxBlocks;
+  const int64_t need = (n + (1 << 19) - 1) >> 19;
+  if (grid < need) grid = need;
+  return grid < 1 ? 1 : grid;
+}
+
+size_t reduce_i32_workspace(int64_t n) {
+  return sizeof(WsHeader) + sizeof(uint64_t) * (size_t)reduce_grid(n < 0 ? 0 : n);
+}
 
 hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipStream_t s) {
   // Split the input at the first 16-byte boundary and after the last full tile.
@@ -109,8 +152,8 @@ hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipS
   const int64_t rest = n - nhead;
   const int64_t ntiles = rest / kTile;
   const int64_t ntail = rest - ntiles * kTile;
-  int64_t grid = ntiles < kReduceMaxBlocks ? ntiles : kReduceMaxBlocks;
-  if (grid < 1) grid = 1;
+  const int64_t grid = reduce_grid(n);
+  (void)kRegistered;
   WsHeader* hdr = (WsHeader*)ws;
   uint64_t* partials = (uint64_t*)((char*)ws + sizeof(WsHeader));
   hipLaunchKernelGGL(reduce_i32_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s,

@@ -4,17 +4,23 @@
 // The paper's scan runs as two kernels; here it is one pass over the data
 // (read n, write n) with decoupled look-back between tiles:
 //
-//   * A block takes the next tile id from a counter in the workspace, so a
-//     tile only ever waits on tiles whose blocks are already running.
+//   * Block b scans tile b.  Blocks are dispatched in the order of their ids
+//     (round-robin over the XCDs, in order within each), so a tile only
+//     waits on tiles whose blocks are already running; no shared counter is
+//     needed to hand out tile ids.
 //   * A tile is [waves][rounds][64 lanes][4] int32: each wave owns a
 //     contiguous sub-tile and reads it with 16-byte loads, a whole wave
 //     covering 1 KiB per round.  Per round a lane adds its 4 values in order,
 //     the wave scans the lane totals with DPP, and the running wave total
 //     carries into the next round.
-//   * Wave totals meet in LDS; the tile aggregate is published at once in
-//     the tile's status word, then wave 0 walks back over the predecessors'
-//     words 64 at a time until it meets an inclusive prefix, and publishes
-//     the tile's own inclusive prefix.
+//   * The tile aggregate is formed first (lane sums, a DPP wave sum, LDS
+//     across waves) and published in the tile's status word at once.  Wave 0
+//     then walks back over the predecessors' words, 256 per poll (four per
+//     lane), until it meets an inclusive prefix, and publishes the tile's own
+//     inclusive prefix; meanwhile the other waves scan their sub-tiles.
+//   * Tiles are large (8192 elements) so that the prefixes travel faster than
+//     the tiles are consumed: a poll takes about a microsecond across XCDs,
+//     and a tile must usually find a published prefix within one window.
 //   * A status word holds {flag:2, generation tag:30, value:32} and is read
 //     and written with single 64-bit relaxed atomics, so no fence is needed
 //     to make the value visible to blocks on other XCDs.  Words whose tag is
@@ -25,145 +31,159 @@
 // sequential definition bit for bit.
 #include "common.hpp"
 #include "launch.hpp"
+#include "tuning.hpp"
 #include "view.hpp"
 #include "wave.hpp"
 
 namespace desc {
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kRounds = 4;
-constexpr int kWaves = kBlock / kWave;
-constexpr int kSub = kWave * 4 * kRounds;        // int32 per wave
-constexpr int kTile = kWaves * kSub;             // int32 per tile
-
 constexpr uint64_t kFlagAggregate = 1, kFlagPrefix = 2;
 constexpr uint32_t kTagMask = 0x3fffffffu;
+constexpr int kLookWords = 4;                     // status words per lane per poll
+constexpr int kWindow = kWave * kLookWords;       // tiles per poll
 
 __device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t gen, uint32_t v) {
   return (flag << 62) | ((uint64_t)(gen & kTagMask) << 32) | (uint64_t)v;
 }
 
 // Exclusive prefix of tile `tile` from the status words of its predecessors.
-// Called by one whole wave; the result is valid in every lane.
+// Called by one whole wave; the result is valid in every lane.  Window
+// position p = q * 64 + lane (q < kLookWords) reads tile pos - p, so the
+// window runs backwards from `pos` in order of p.
 __device__ __forceinline__ uint32_t look_back(const uint64_t* __restrict__ status, idx_t tile,
                                               uint32_t gen, WsHeader* __restrict__ hdr) {
   const int lane = wave::lane_id();
   const uint32_t tag = gen & kTagMask;
   uint32_t excl = 0;
   idx_t pos = tile - 1;
+  auto st = array(status, tile);
   for (uint32_t polls = 0;; ++polls) {
     if (polls == kSpinLimit) {     // inconsistent workspace: give up, flag it
       if (lane == 0) store_u32(&hdr->error, 1u);
       break;
     }
-    const idx_t j = pos - lane;
-    const uint64_t s = j >= 0 ? load_status(&status[j]) : pack(kFlagPrefix, gen, 0u);
-    const uint32_t flag = (uint32_t)(s >> 62);
-    const bool valid = flag != 0 && (uint32_t)((s >> 32) & kTagMask) == tag;
-    const uint64_t pmask = __ballot(valid && flag == kFlagPrefix);
-    const uint64_t imask = __ballot(!valid);
-    const int first_p = pmask ? __builtin_ctzll(pmask) : 63;
-    const uint64_t need = first_p == 63 ? ~0ull : ((2ull << first_p) - 1);
-    if (imask & need) {            // a predecessor we need has not published yet
-      __builtin_amdgcn_s_sleep(1);
+    uint64_t w[kLookWords];
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) {
+      const idx_t j = pos - (q * kWave + lane);
+      w[q] = j >= 0 ? load_status(&st[j]) : pack(kFlagPrefix, gen, 0u);
+    }
+    // First window position holding an inclusive prefix, and whether every
+    // position up to it has published.
+    int first_p = kWindow;         // none
+    bool missing = false;
+#pragma unroll
+    for (int q = kLookWords - 1; q >= 0; --q) {
+      const uint32_t flag = (uint32_t)(w[q] >> 62);
+      const bool valid = flag != 0 && (uint32_t)((w[q] >> 32) & kTagMask) == tag;
+      const uint64_t pm = __ballot(valid && flag == kFlagPrefix);
+      if (pm) first_p = q * kWave + __builtin_ctzll(pm);
+    }
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) {
+      const uint32_t flag = (uint32_t)(w[q] >> 62);
+      const bool valid = flag != 0 && (uint32_t)((w[q] >> 32) & kTagMask) == tag;
+      missing |= __ballot(!valid && q * kWave + lane <= first_p) != 0;
+    }
+    if (missing) {                 // a predecessor we need has not published yet
+      __builtin_amdgcn_s_sleep(2);
       continue;
     }
-    excl += wave::sum_u32(lane <= first_p ? (uint32_t)s : 0u);
-    if (pmask) break;
-    pos -= kWave;
+    uint32_t part = 0;
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) part += (q * kWave + lane <= first_p) ? (uint32_t)w[q] : 0u;
+    excl += wave::sum_u32(part);
+    if (first_p < kWindow) break;
+    pos -= kWindow;
   }
   return excl;
 }
 
-// The block that finishes last prepares the workspace for the next call.
-__device__ __forceinline__ void finish(WsHeader* hdr, uint32_t gen, idx_t ntiles) {
-  const uint32_t d = fetch_add_u32(&hdr->done, 1u);
-  if (d == (uint32_t)(ntiles - 1)) {
-    store_u32(&hdr->next, 0u);
-    store_u32(&hdr->done, 0u);
-    store_u32(&hdr->gen, gen + 1u);
-  }
+// A tile is kBlock threads x kRounds rounds x 4 int32; kNt selects
+// non-temporal (streaming) global loads and stores.
+template <int kBlock, int kRounds, bool kNt>
+struct ScanCfg {
+  static constexpr int block = kBlock;
+  static constexpr int rounds = kRounds;
+  static constexpr bool nt = kNt;
+  static constexpr int waves = kBlock / kWave;
+  static constexpr int tile = waves * kWave * 4 * kRounds;   // int32 per tile
+};
+constexpr int kMinTile = 8192;   // smallest tile of any configuration below
+
+template <bool kNt, class T>
+__device__ __forceinline__ T load16(const T* p) {
+  if constexpr (kNt) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool kNt, class T>
+__device__ __forceinline__ void store16(T v, T* p) {
+  if constexpr (kNt) __builtin_nontemporal_store(v, p);
+  else *p = v;
 }
 
-template <bool kVec>
-__global__ __launch_bounds__(kBlock) void scan_i32_kernel(const int32_t* __restrict__ in,
-                                                          int32_t* __restrict__ out, int64_t n,
-                                                          WsHeader* __restrict__ hdr,
-                                                          uint64_t* __restrict__ status) {
-  __shared__ uint32_t s_tile, s_gen, s_prefix;
-  __shared__ uint32_t s_wtot[kWaves];
-  auto thread = thread_x<kBlock>();
-  auto wv = wave_of_block<kBlock>();
+template <class C, bool kVec>
+__global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __restrict__ in,
+                                                            int32_t* __restrict__ out, int64_t n,
+                                                            WsHeader* __restrict__ hdr,
+                                                            uint64_t* __restrict__ status) {
+  constexpr int R = C::rounds, NW = C::waves, TILE = C::tile;
+  __shared__ uint32_t s_gen, s_prefix;
+  __shared__ uint32_t s_wtot[NW];
+  auto tile_res = block_x();
+  auto thread = thread_x<C::block>();
+  auto wv = wave_of_block<C::block>();
   auto lane = lane_of_wave();
-  const idx_t ntiles = block_x().count();
+  const idx_t ntiles = tile_res.count();
+  const idx_t tile = tile_res.index();
 
-  if (thread.index() == 0) {
-    s_tile = fetch_add_u32(&hdr->next, 1u);
-    s_gen = load_u32(&hdr->gen);
-  }
+  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
   sync(thread);
-  const idx_t tile = s_tile;
   const uint32_t gen = s_gen;
-  if (tile >= ntiles) {          // only possible with a workspace that was not zeroed
-    if (thread.index() == 0) {
-      store_u32(&hdr->error, 1u);
-      finish(hdr, gen, ntiles);
-    }
-    return;
-  }
 
   // [tiles][waves][rounds][lanes] of 4-element groups; the last tile may be
   // partial, so the nominal extent is rounded up and positions >= n guarded.
-  const bool full = kVec && (tile + 1) * kTile <= n;
-  uint32_t x[kRounds][4];
+  const bool full = kVec && (tile + 1) * TILE <= n;
+  uint32_t x[R][4];
   if (full) {
-    auto mine = array((const i32x4*)in, ntiles * (kTile / 4))
-                    .group<kWave>().group<kRounds>().group<kWaves>()
+    auto mine = array((const i32x4*)in, ntiles * (TILE / 4))
+                    .group<kWave>().template group<R>().template group<NW>()
                     .idx(tile).select(wv).transpose().select(lane);     // [rounds]
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const i32x4 q = __builtin_nontemporal_load(&mine[r]);
+    for (int r = 0; r < R; ++r) {
+      const i32x4 q = load16<C::nt>(&mine[r]);
       x[r][0] = (uint32_t)q.x; x[r][1] = (uint32_t)q.y;
       x[r][2] = (uint32_t)q.z; x[r][3] = (uint32_t)q.w;
     }
   } else {
-    auto mine = array(in, ntiles * kTile)
-                    .group<4>().group<kWave>().group<kRounds>().group<kWaves>()
+    auto mine = array(in, ntiles * TILE)
+                    .group<4>().group<kWave>().template group<R>().template group<NW>()
                     .idx(tile).select(wv).transpose().select(lane);     // [rounds][4]
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       auto grp = mine.idx(r);
 #pragma unroll
       for (int k = 0; k < 4; ++k) x[r][k] = grp.pos(k) < n ? (uint32_t)grp[k] : 0u;
     }
   }
 
-  // Scan inside the wave's sub-tile, round by round.
-  uint32_t carry = 0;
+  // Tile aggregate first, so that it can be published before the scan.
+  uint32_t lsum = 0;
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    x[r][1] += x[r][0];
-    x[r][2] += x[r][1];
-    x[r][3] += x[r][2];
-    const uint32_t t = x[r][3];
-    const uint32_t incl = wave::inclusive_add_u32(t);
-    const uint32_t ex = carry + incl - t;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[r][k] += ex;
-    carry += wave::lane_read_u32(incl, kWave - 1);
-  }
-  if (lane.index() == 0) s_wtot[wv.index()] = carry;
+  for (int r = 0; r < R; ++r) lsum += x[r][0] + x[r][1] + x[r][2] + x[r][3];
+  const uint32_t wsum = wave::sum_u32(lsum);
+  if (lane.index() == 0) s_wtot[wv.index()] = wsum;
   sync(thread);
   uint32_t wex = 0, agg = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
+  for (int w = 0; w < NW; ++w) {
     const uint32_t v = s_wtot[w];
     wex += (w < wv.index()) ? v : 0u;
     agg += v;
   }
 
-  // Publish and look back (wave 0).
+  // Wave 0 publishes and looks back while the other waves scan.
   auto st = array(status, ntiles);
   if (wv.index() == 0) {
     uint32_t excl = 0;
@@ -174,60 +194,96 @@ __global__ __launch_bounds__(kBlock) void scan_i32_kernel(const int32_t* __restr
       excl = look_back(status, tile, gen, hdr);
       if (lane.index() == 0) store_status(&st[tile], pack(kFlagPrefix, gen, excl + agg));
     }
-    if (lane.index() == 0) s_prefix = excl;
+    if (lane.index() == 0) {
+      s_prefix = excl;
+      // Every tile before the last has published, so every block of this
+      // call has read the generation: the last tile may advance it.
+      if (tile == ntiles - 1) store_u32(&hdr->gen, gen + 1u);
+    }
+  }
+
+  // Scan inside the wave's sub-tile, round by round.
+  uint32_t carry = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    x[r][1] += x[r][0];
+    x[r][2] += x[r][1];
+    x[r][3] += x[r][2];
+    const uint32_t t = x[r][3];
+    const uint32_t incl = wave::inclusive_add_u32(t);
+    const uint32_t ex = carry + incl - t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[r][k] += ex;
+    carry += wave::lane_read_u32(incl, kWave - 1);
   }
   sync(thread);
   const uint32_t add = s_prefix + wex;
 
   if (full) {
-    auto mine = array((i32x4*)out, ntiles * (kTile / 4))
-                    .group<kWave>().group<kRounds>().group<kWaves>()
+    auto mine = array((i32x4*)out, ntiles * (TILE / 4))
+                    .group<kWave>().template group<R>().template group<NW>()
                     .idx(tile).select(wv).transpose().select(lane);
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       i32x4 q;
       q.x = (int32_t)(x[r][0] + add); q.y = (int32_t)(x[r][1] + add);
       q.z = (int32_t)(x[r][2] + add); q.w = (int32_t)(x[r][3] + add);
-      __builtin_nontemporal_store(q, &mine[r]);
+      store16<C::nt>(q, &mine[r]);
     }
   } else {
-    auto mine = array(out, ntiles * kTile)
-                    .group<4>().group<kWave>().group<kRounds>().group<kWaves>()
+    auto mine = array(out, ntiles * TILE)
+                    .group<4>().group<kWave>().template group<R>().template group<NW>()
                     .idx(tile).select(wv).transpose().select(lane);
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       auto grp = mine.idx(r);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (grp.pos(k) < n) grp[k] = (int32_t)(x[r][k] + add);
     }
   }
-
-  if (thread.index() == 0) finish(hdr, gen, ntiles);
 }
+
+template <class C>
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+  const int64_t ntiles = (n + C::tile - 1) / C::tile;
+  WsHeader* hdr = (WsHeader*)ws;
+  uint64_t* status = (uint64_t*)((char*)ws + sizeof(WsHeader));
+  const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL((scan_i32_kernel<C, true>), dim3((unsigned)ntiles), dim3(C::block), 0, s,
+                       in, out, n, hdr, status);
+  else
+    hipLaunchKernelGGL((scan_i32_kernel<C, false>), dim3((unsigned)ntiles), dim3(C::block), 0, s,
+                       in, out, n, hdr, status);
+  return hipGetLastError();
+}
+
+constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
+                                   "b1024_r4_nt", "b512_r4_nt"};
+constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
+const bool kRegistered = (tune::register_op(tune::kScanI32, "scan_i32", 6, kNames, kDefaults), true);
 
 }  // namespace
 
 namespace launch {
 
 size_t scan_i32_workspace(int64_t n) {
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  const int64_t ntiles = (n + kMinTile - 1) / kMinTile;
   return sizeof(WsHeader) + sizeof(uint64_t) * (size_t)(ntiles > 0 ? ntiles : 1);
 }
 
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const int64_t ntiles = (n + kTile - 1) / kTile;
-  WsHeader* hdr = (WsHeader*)ws;
-  uint64_t* status = (uint64_t*)((char*)ws + sizeof(WsHeader));
-  const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
-  if (vec)
-    hipLaunchKernelGGL(scan_i32_kernel<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in, out,
-                       n, hdr, status);
-  else
-    hipLaunchKernelGGL(scan_i32_kernel<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, s, in,
-                       out, n, hdr, status);
-  return hipGetLastError();
+  (void)kRegistered;
+  switch (tune::get(tune::kScanI32, tune::size_class(tune::kScanI32, n))) {
+    case 1: return launch_scan<ScanCfg<256, 8, false>>(in, out, n, ws, s);
+    case 2: return launch_scan<ScanCfg<512, 8, true>>(in, out, n, ws, s);
+    case 3: return launch_scan<ScanCfg<256, 16, true>>(in, out, n, ws, s);
+    case 4: return launch_scan<ScanCfg<1024, 4, true>>(in, out, n, ws, s);
+    case 5: return launch_scan<ScanCfg<512, 4, true>>(in, out, n, ws, s);
+    default: return launch_scan<ScanCfg<256, 8, true>>(in, out, n, ws, s);
+  }
 }
 
 }  // namespace launch

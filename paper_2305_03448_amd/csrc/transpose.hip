@@ -5,112 +5,161 @@
 // The structure is the paper's: every block owns one tile, its threads copy
 // the tile from the input into an LDS buffer, the block synchronises, and
 // the threads copy the tile back out transposed, so both the global reads
-// and the global writes run along rows.  On CDNA the tile is 64 x 64 words
-// and a block is 256 threads seen as a [16][16] block (Listing 2 uses a
-// 32 x 32 tile and [8][32] threads):
+// and the global writes run along rows.  On CDNA a tile is T x T words
+// (T = 32, 64 or 128; Listing 2 uses 32) and a block is 256 threads seen as
+// a [256/(T/4)][T/4] block, every thread moving 16 bytes per row:
 //
-//   read  : thread (y, x) copies rows y, y+16, y+32, y+48 of the tile, 16
-//           bytes per row (group_by_tile::<64,16> over int32x4 columns, then
-//           group_by_row::<64,4>);
-//   write : the same thread writes rows y, y+16, ... of the transposed tile,
+//   read  : thread (y, x) copies rows y, y+TY, y+2TY, ... of the tile, words
+//           4x..4x+3 of each (group_by_tile::<T,T/4> over int32x4 columns,
+//           then group_by_row::<T,T/TY>);
+//   write : the same thread writes rows y, y+TY, ... of the transposed tile,
 //           each four consecutive words being one 16-byte store, and reads
-//           them from column y+16i, rows 4x..4x+3 of the LDS tile.
+//           them from column y+TY*i, rows 4x..4x+3 of the LDS tile.
 //
-// The LDS tile has a row pitch of 65 words, so that both the row-wise
-// writes and the column-wise reads of a wave fall into distinct banks.
+// The LDS tile has a row pitch of T+1 words, so that the column-wise reads
+// of a wave spread over the banks.
 // Tiles on the ragged right or bottom edge (and unaligned matrices) go
 // through a guarded element-by-element copy with the same tile and barrier.
 // The kernel moves bit patterns only: NaN payloads, signed zeros and
 // subnormals pass unchanged.
 #include "common.hpp"
 #include "launch.hpp"
+#include "tuning.hpp"
 #include "view.hpp"
 
 namespace desc {
 namespace {
 
-constexpr int kT = 64;            // tile edge (words)
-constexpr int kPitch = kT + 1;    // LDS row pitch (words)
 constexpr int kBlock = 256;
-constexpr int kTY = 16, kTX = 16; // threads as [16][16]
 
-template <bool kVec>
+template <int kT, bool kNt>
+struct TransposeCfg {
+  static constexpr int t = kT;               // tile edge (words)
+  static constexpr int pitch = kT + 1;       // LDS row pitch (words)
+  static constexpr int tx = kT / 4;          // threads along a row (16 bytes each)
+  static constexpr int ty = kBlock / tx;     // threads along a column
+  static constexpr int items = kT / ty;      // rows per thread
+  static constexpr bool nt = kNt;
+  static_assert(ty * items == kT, "tile rows must divide among the thread rows");
+};
+
+template <bool kNt, class T>
+__device__ __forceinline__ T load16(const T* p) {
+  if constexpr (kNt) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool kNt, class T>
+__device__ __forceinline__ void store16(T v, T* p) {
+  if constexpr (kNt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <class C, bool kVec>
 __global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out,
                                                              int64_t rows, int64_t cols) {
-  __shared__ uint32_t lds[kT * kPitch];
+  constexpr int T = C::t, TY = C::ty, TX = C::tx, IT = C::items;
+  __shared__ uint32_t lds[T * C::pitch];
   auto bx = block_x();   // column tile of the input
   auto by = block_y();   // row tile of the input
   auto thread = thread_x<kBlock>();
   const Block bz{(idx_t)blockIdx.z, (idx_t)gridDim.z};   // matrix of the batch
 
-  // The LDS tile as [64][65] words with the padding column split off.
-  auto tile = matrix(lds, kT, kPitch).fst<1>(kT);            // [64][64]
+  // The LDS tile as [T][T+1] words with the padding column split off.
+  auto tile = matrix(lds, T, C::pitch).template fst<1>(T);            // [T][T]
 
-  const bool full = kVec && (by.index() + 1) * kT <= rows && (bx.index() + 1) * kT <= cols;
+  const bool full = kVec && (by.index() + 1) * T <= rows && (bx.index() + 1) * T <= cols;
   if (full) {
-    auto t2 = thread_yx<kTY, kTX>();
-    // input tile (by, bx), as [64 rows][16 groups of 4 words]
-    auto a = group_by_tile<kT, kT / 4>(
+    auto t2 = thread_yx<TY, TX>();
+    // input tile (by, bx), as [T rows][T/4 groups of 4 words]
+    auto a = group_by_tile<T, T / 4>(
                  matrices((const u32x4*)in, bz.count(), rows, cols / 4).select(bz))
                  .select(by).select(bx);
-    auto a_mine = group_by_row<kT, 4>(a).select(t2.y).select(t2.x);           // [4]
-    auto l_mine = group_by_row<kT, 4>(tile.group<4, 1>()).select(t2.y).select(t2.x);  // [4][4]
-    u32x4 v[4];
+    auto a_mine = group_by_row<T, IT>(a).select(t2.y).select(t2.x);                   // [IT]
+    auto l_mine = group_by_row<T, IT>(tile.template group<4, 1>()).select(t2.y).select(t2.x);
+    u32x4 v[IT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = __builtin_nontemporal_load(&a_mine[i]);
+    for (int i = 0; i < IT; ++i) v[i] = load16<C::nt>(&a_mine[i]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < IT; ++i) {
       auto l = l_mine.idx(i);
       l[0] = v[i].x; l[1] = v[i].y; l[2] = v[i].z; l[3] = v[i].w;
     }
     sync(thread);
     // output tile (bx, by) of the cols x rows result
-    auto b = group_by_tile<kT, kT / 4>(
+    auto b = group_by_tile<T, T / 4>(
                  matrices((u32x4*)out, bz.count(), cols, rows / 4).select(bz))
                  .select(bx).select(by);
-    auto b_mine = group_by_row<kT, 4>(b).select(t2.y).select(t2.x);            // [4]
+    auto b_mine = group_by_row<T, IT>(b).select(t2.y).select(t2.x);                   // [IT]
     // the LDS tile read column-wise: element (c, x, k) = tile[4x + k][c]
-    auto lt = group_by_row<kT, 4>(tile.transpose().group<4, 1>()).select(t2.y).select(t2.x);
+    auto lt = group_by_row<T, IT>(tile.transpose().template group<4, 1>())
+                  .select(t2.y).select(t2.x);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < IT; ++i) {
       auto l = lt.idx(i);
       u32x4 w;
       w.x = l[0]; w.y = l[1]; w.z = l[2]; w.w = l[3];
-      __builtin_nontemporal_store(w, &b_mine[i]);
+      store16<C::nt>(w, &b_mine[i]);
     }
   } else {
-    // Ragged edge: element e of the tile is (e / 64, e % 64); guard both sides.
+    // Ragged edge: element e of the tile is (e / T, e % T); guard both sides.
     auto a = matrices(in, bz.count(), rows, cols).select(bz);
     auto b = matrices(out, bz.count(), cols, rows).select(bz);
-    const idx_t r0 = by.index() * kT, c0 = bx.index() * kT;
-    for (idx_t e = thread.index(); e < kT * kT; e += kBlock) {
-      const idx_t r = e / kT, c = e % kT;
+    const idx_t r0 = by.index() * T, c0 = bx.index() * T;
+    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+      const idx_t r = e / T, c = e % T;
       if (r0 + r < rows && c0 + c < cols) tile.at(r, c) = a.at(r0 + r, c0 + c);
     }
     sync(thread);
-    for (idx_t e = thread.index(); e < kT * kT; e += kBlock) {
-      const idx_t c = e / kT, r = e % kT;
+    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+      const idx_t c = e / T, r = e % T;
       if (r0 + r < rows && c0 + c < cols) b.at(c0 + c, r0 + r) = tile.at(r, c);
     }
   }
 }
 
+template <class C>
+hipError_t launch_transpose(const uint32_t* in, uint32_t* out, int64_t batch, int64_t rows,
+                            int64_t cols, hipStream_t s) {
+  constexpr int T = C::t;
+  const dim3 grid((unsigned)((cols + T - 1) / T), (unsigned)((rows + T - 1) / T),
+                  (unsigned)batch);
+  const bool vec = rows % 4 == 0 && cols % 4 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL((transpose32_kernel<C, true>), grid, dim3(kBlock), 0, s, in, out, rows,
+                       cols);
+  else
+    hipLaunchKernelGGL((transpose32_kernel<C, false>), grid, dim3(kBlock), 0, s, in, out, rows,
+                       cols);
+  return hipGetLastError();
+}
+
+constexpr const char* kNames[] = {"t64_nt", "t64", "t32_nt", "t32", "t128_nt", "t128"};
+constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
+const bool kRegistered =
+    (tune::register_op(tune::kTranspose32, "transpose_32", 6, kNames, kDefaults), true);
+
 }  // namespace
 
 namespace launch {
 
+// Rows are tiled by at most 128 words, so a grid of 65535 row tiles covers
+// any row count this bound admits.
+int64_t transpose_max_rows() { return (int64_t)65535 * 32; }
+
 hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_t rows,
                         int64_t cols, hipStream_t s) {
   if (batch == 0 || rows == 0 || cols == 0) return hipSuccess;
-  const dim3 grid((unsigned)((cols + kT - 1) / kT), (unsigned)((rows + kT - 1) / kT),
-                  (unsigned)batch);
-  const bool vec = rows % 4 == 0 && cols % 4 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
-  if (vec)
-    hipLaunchKernelGGL(transpose32_kernel<true>, grid, dim3(kBlock), 0, s, in, out, rows, cols);
-  else
-    hipLaunchKernelGGL(transpose32_kernel<false>, grid, dim3(kBlock), 0, s, in, out, rows, cols);
-  return hipGetLastError();
+  (void)kRegistered;
+  const int64_t size = batch * rows * cols;
+  switch (tune::get(tune::kTranspose32, tune::size_class(tune::kTranspose32, size))) {
+    case 1: return launch_transpose<TransposeCfg<64, false>>(in, out, batch, rows, cols, s);
+    case 2: return launch_transpose<TransposeCfg<32, true>>(in, out, batch, rows, cols, s);
+    case 3: return launch_transpose<TransposeCfg<32, false>>(in, out, batch, rows, cols, s);
+    case 4: return launch_transpose<TransposeCfg<128, true>>(in, out, batch, rows, cols, s);
+    case 5: return launch_transpose<TransposeCfg<128, false>>(in, out, batch, rows, cols, s);
+    default: return launch_transpose<TransposeCfg<64, true>>(in, out, batch, rows, cols, s);
+  }
 }
 
 }  // namespace launch

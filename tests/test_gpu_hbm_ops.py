@@ -181,3 +181,58 @@ def test_transpose_workload_8192():
     t = torch.empty((8192, 8192), dtype=torch.float32, device=dev())
     desc.desc_transpose_f32(to_dev(m), t)
     assert np.array_equal(t.cpu().numpy(), oracle.transpose_u32(m))
+
+
+# ------------------------------------------------------------------ every configuration
+def _each_config(op):
+    for cfg in range(desc.desc_config_count(op)):
+        yield cfg, desc.desc_config_name(op, cfg)
+
+
+@pytest.fixture
+def restore_configs():
+    yield
+    for op in ("scan_i32", "transpose_32", "copy_32", "reduce_i32"):
+        for cls in range(4):
+            desc.desc_config_set(op, cls, -1)
+
+
+@pytest.mark.parametrize("n", [1, 4097, 8191, 8193, 16385, 300_001, (1 << 22) + 5])
+def test_scan_every_config(n, restore_configs):
+    x = workloads.int_uniform(n, seed=400 + n % 7)
+    want = oracle.scan_i32(x)
+    xt = to_dev(x)
+    cls = desc.desc_size_class("scan_i32", n)
+    for cfg, name in _each_config("scan_i32"):
+        case(f"scan config {name} n={n}")
+        desc.desc_config_set("scan_i32", cls, cfg)
+        y = torch.empty(n, dtype=torch.int32, device=dev())
+        desc.desc_scan_i32(xt, y)
+        assert np.array_equal(y.cpu().numpy(), want), name
+
+
+@pytest.mark.parametrize("rows,cols", [(37, 1), (64, 64), (200, 136), (130, 260), (1024, 516)])
+def test_transpose_every_config(rows, cols, restore_configs):
+    m = workloads.self_describing_u32(rows, cols)
+    want = oracle.transpose_u32(m)
+    mt = to_dev(m.view(np.int32))
+    cls = desc.desc_size_class("transpose_32", rows * cols)
+    for cfg, name in _each_config("transpose_32"):
+        case(f"transpose config {name} {rows}x{cols}")
+        desc.desc_config_set("transpose_32", cls, cfg)
+        t = torch.empty((cols, rows), dtype=torch.int32, device=dev())
+        desc.desc_transpose_f32(mt, t)
+        assert np.array_equal(t.cpu().numpy().view(np.uint32), want), name
+
+
+@pytest.mark.parametrize("n", [1, 5, 1023, 4096 * 4 + 3, 1_000_001])
+def test_copy_every_config(n, restore_configs):
+    x = workloads.int_uniform(n, seed=5)
+    xt = to_dev(x)
+    cls = desc.desc_size_class("copy_32", n)
+    for cfg, name in _each_config("copy_32"):
+        case(f"copy config {name} n={n}")
+        desc.desc_config_set("copy_32", cls, cfg)
+        y = torch.empty(n, dtype=torch.int32, device=dev())
+        desc.desc_copy_32(xt, y)
+        assert np.array_equal(y.cpu().numpy(), x), name
