@@ -104,6 +104,26 @@ desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batc
                                        int64_t rows, int64_t cols, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Matrix multiplication (Sec. 5, "matrix multiplication"; the paper fixes
+ * neither precision nor layout): C = A * B with A M x K, B K x N and C
+ * M x N, all row-major FP32 with row strides lda >= K, ldb >= N, ldc >= N
+ * (in elements).  C is overwritten (K = 0 writes zeros).  C must not overlap
+ * A or B.  Modes:
+ *   DESC_GEMM_F32         FP32 products, FP32 accumulation (matrix cores).
+ * The workspace query returns 0 for modes that need none (ws may be NULL).
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  DESC_GEMM_F32 = 0,
+  DESC_GEMM_BF16X3 = 1,
+  DESC_GEMM_FP8_ROWCOL = 2
+} desc_gemm_mode;
+
+size_t desc_gemm_workspace(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K);
+desc_status desc_gemm(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K, const float* A,
+                      int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Copy of n 32-bit words: the plain bandwidth ceiling the HBM-bound
  * operations are measured against.  `in` and `out` must not overlap.
  * ---------------------------------------------------------------------- */

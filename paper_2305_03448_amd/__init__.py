@@ -29,6 +29,7 @@ __all__ = [
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_copy_32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
     "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
+    "desc_gemm_workspace", "desc_gemm", "GEMM_MODES",
 ]
 
 _P = ctypes.c_void_p
@@ -56,7 +57,13 @@ SIGNATURES = {
     "desc_config_set": (_ST, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "desc_config_get": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
     "desc_config_load": (_ST, [ctypes.c_char_p]),
+    "desc_gemm_workspace": (_SZ, [ctypes.c_int, _I64, _I64, _I64]),
+    "desc_gemm": (_ST, [ctypes.c_int, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ,
+                        _P]),
 }
+
+# desc_gemm_mode values
+GEMM_MODES = {"f32": 0, "bf16x3": 1, "fp8": 2}
 
 # desc_op values (include/desc.h)
 OPS = {"reduce_i32": 0, "scan_i32": 1, "transpose_32": 2, "copy_32": 3, "gemm_f32": 4,
@@ -262,3 +269,39 @@ def desc_config_get(op, size_class: int) -> int:
 
 def desc_config_load(path: str) -> None:
     _check(lib().desc_config_load(path.encode()), "desc_config_load")
+
+
+# ------------------------------------------------------------------ GEMM
+def _mode(mode) -> int:
+    return GEMM_MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def desc_gemm_workspace(mode, M: int, N: int, K: int) -> int:
+    return lib().desc_gemm_workspace(_mode(mode), M, N, K)
+
+
+def _rows(t: torch.Tensor, name: str):
+    """(rows, cols, row stride) of a 2-D float32 GPU tensor with unit column stride."""
+    if t.device.type != "cuda" or t.dtype != torch.float32 or t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D float32 GPU tensor")
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    return t.shape[0], t.shape[1], t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+
+
+def desc_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, mode="f32",
+              ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """C = A @ B (row-major FP32 operands; strided rows allowed)."""
+    M, K, lda = _rows(A, "A")
+    K2, N, ldb = _rows(B, "B")
+    M2, N2, ldc = _rows(C, "C")
+    if K2 != K or M2 != M or N2 != N:
+        raise ValueError("shapes must be A (M,K), B (K,N), C (M,N)")
+    m = _mode(mode)
+    need = desc_gemm_workspace(m, M, N, K)
+    w = None
+    if need:
+        w = _ws(f"gemm{m}", need, A, ws) if ws is None else _dev(ws, torch.uint8, "ws")
+    _check(lib().desc_gemm(m, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _ptr(w),
+                           w.numel() if w is not None else 0, _stream(A, stream)), "desc_gemm")
+    return C

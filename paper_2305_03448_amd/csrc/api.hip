@@ -171,6 +171,40 @@ desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_
   return desc_transpose_batched_f32(in, out, 1, rows, cols, stream);
 }
 
+// ----------------------------------------------------------------- GEMM
+size_t desc_gemm_workspace(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K) {
+  if (M < 0 || N < 0 || K < 0) return 0;
+  switch (mode) {
+    case DESC_GEMM_F32: return 0;
+    default: return 0;
+  }
+}
+
+desc_status desc_gemm(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K, const float* A,
+                      int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (M < 0 || N < 0 || K < 0) return DESC_ERR_SIZE;
+  if (mode != DESC_GEMM_F32) return DESC_ERR_UNSUPPORTED;
+  if (M == 0 || N == 0) return DESC_OK;
+  if (C == nullptr || (K > 0 && (A == nullptr || B == nullptr))) return DESC_ERR_NULL;
+  // row-major with leading dimensions at least the row lengths
+  if (ldc < N || (K > 0 && (lda < K || ldb < N))) return DESC_ERR_SIZE;
+  const int64_t a_el = K > 0 ? bytes_of(M - 1, lda) : 0, b_el = K > 0 ? bytes_of(K - 1, ldb) : 0;
+  const int64_t c_el = bytes_of(M - 1, ldc);
+  if (a_el < 0 || b_el < 0 || c_el < 0) return DESC_ERR_SIZE;
+  const int64_t a_b = K > 0 ? bytes_of(a_el + K, 4) : 0, b_b = K > 0 ? bytes_of(b_el + N, 4) : 0;
+  const int64_t c_b = bytes_of(c_el + N, 4);
+  if (a_b < 0 || b_b < 0 || c_b < 0 || M * N > ((int64_t)1 << 46)) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({K > 0 ? (const void*)A : nullptr, K > 0 ? (const void*)B : nullptr, C,
+                         ws_bytes ? ws : nullptr}));
+  if (misaligned(A, 4) || misaligned(B, 4) || misaligned(C, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({C, c_b}, {A, a_b}) || overlap({C, c_b}, {B, b_b})) return DESC_ERR_ALIAS;
+  const size_t need = desc_gemm_workspace(mode, M, N, K);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return DESC_ERR_WORKSPACE;
+  return hip_status(
+      desc::launch::gemm_f32(A, lda, B, ldb, C, ldc, M, N, K, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- copy
 desc_status desc_copy_32(const void* in, void* out, int64_t n, void* stream) {
   const int64_t nb = bytes_of(n, 4);

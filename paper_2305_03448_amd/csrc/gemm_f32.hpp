@@ -1,0 +1,173 @@
+// gemm_f32.hpp -- the FP32 matrix-core tile routine shared by the plain and
+// the grouped GEMM.  See gemm_f32.hip for the scheme.
+#pragma once
+#include "common.hpp"
+#include "mfma.hpp"
+#include "view.hpp"
+
+namespace desc {
+
+struct GemmProblemF32 {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  float* C;
+  int64_t ldc;
+  int64_t M, N, K;
+};
+
+// Block tile BM x BN, K step BK; 256 threads as a 2 x 2 grid of waves.
+template <int kBM, int kBN, int kBK>
+struct GemmCfgF32 {
+  static constexpr int bm = kBM, bn = kBN, bk = kBK;
+  static constexpr int wtm = kBM / 2, wtn = kBN / 2;     // wave tile
+  static constexpr int fm = wtm / 32, fn = wtn / 32;     // 32 x 32 fragments per wave
+  static constexpr int pa = kBM + 4, pb = kBN + 4;       // LDS pitches (words)
+  static constexpr int a_vec = kBM * kBK / 4 / 256;      // float4 per thread per step
+  static constexpr int b_vec = kBK * kBN / 4 / 256;
+  static_assert(fm >= 1 && fn >= 1 && a_vec >= 1 && b_vec >= 1, "tile too small");
+  static_assert(kBK % 4 == 0 && kBN % 4 == 0, "16-byte rows");
+};
+
+namespace gemm_f32 {
+
+template <class C>
+constexpr int lds_floats() { return 2 * C::bk * C::pa + 2 * C::bk * C::pb; }
+
+inline bool vec_ok(const float* A, int64_t lda, const float* B, int64_t ldb) {
+  return ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && lda % 4 == 0 && ldb % 4 == 0;
+}
+
+// Tile order.  Blocks are dispatched round-robin over the 8 XCDs, each with
+// its own L2; the linear block id is first mapped so that each XCD receives a
+// contiguous run of tile ids, and tile ids are then laid out in groups of 8
+// tile rows (column-major inside a group), so the blocks running together on
+// one XCD cover a compact patch of C and share their A rows and B columns.
+__device__ __forceinline__ idx_t xcd_tile(const Block& b, idx_t tiles_m, idx_t tiles_n) {
+  const idx_t T = tiles_m * tiles_n;
+  idx_t u = b.index();
+  if (T % 8 == 0) u = (u % 8) * (T / 8) + u / 8;
+  constexpr idx_t kGroup = 8;
+  const idx_t per_group = kGroup * tiles_n;
+  const idx_t g = u / per_group;
+  const idx_t first_m = g * kGroup;
+  const idx_t gsize = tiles_m - first_m < kGroup ? tiles_m - first_m : kGroup;
+  const idx_t r = u - g * per_group;
+  return (first_m + r % gsize) * tiles_n + r / gsize;
+}
+
+// One BM x BN tile of C = A * B.  `lds` holds lds_floats<C>() floats.
+template <class C, bool kVec>
+__device__ __forceinline__ void tile(const GemmProblemF32& p, idx_t tm, idx_t tn, float* lds) {
+  constexpr int BM = C::bm, BN = C::bn, BK = C::bk;
+  auto thread = thread_x<256>();
+  auto wv = wave_of_block<256>();
+  const int lane = (int)lane_of_wave().index();
+  const int half = lane / 32, col32 = lane % 32;
+  const int wm = (int)wv.index() / 2, wn = (int)wv.index() % 2;
+  const idx_t m0 = tm * BM, n0 = tn * BN;
+
+  auto a_lds = matrices(lds, 2, BK, C::pa);                          // [buf][k][m]
+  auto b_lds = matrices(lds + 2 * BK * C::pa, 2, BK, C::pb);         // [buf][k][n]
+  auto a_g = matrix(p.A, p.M, p.lda);
+  auto b_g = matrix(p.B, p.K, p.ldb);
+
+  f32x4 ra[C::a_vec], rb[C::b_vec];
+
+  // A tile rows m0.., columns k0..: float4 q = t + 256 i -> (row q / (BK/4), group q % (BK/4))
+  auto load = [&](idx_t k0) {
+    const bool a_full = kVec && m0 + BM <= p.M && k0 + BK <= p.K;
+    const bool b_full = kVec && n0 + BN <= p.N && k0 + BK <= p.K;
+#pragma unroll
+    for (int i = 0; i < C::a_vec; ++i) {
+      const int q = (int)thread.index() + 256 * i;
+      const idx_t r = m0 + q / (BK / 4), c = k0 + 4 * (q % (BK / 4));
+      if (a_full) {
+        ra[i] = *(const f32x4*)&a_g.at(r, c);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ra[i][j] = (r < p.M && c + j < p.K) ? a_g.at(r, c + j) : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < C::b_vec; ++i) {
+      const int q = (int)thread.index() + 256 * i;
+      const idx_t r = k0 + q / (BN / 4), c = n0 + 4 * (q % (BN / 4));
+      if (b_full) {
+        rb[i] = *(const f32x4*)&b_g.at(r, c);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[i][j] = (r < p.K && c + j < p.N) ? b_g.at(r, c + j) : 0.f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    auto as = a_lds.idx(buf);
+    auto bs = b_lds.idx(buf);
+#pragma unroll
+    for (int i = 0; i < C::a_vec; ++i) {
+      const int q = (int)thread.index() + 256 * i;
+      const int r = q / (BK / 4), c = 4 * (q % (BK / 4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) as.at(c + j, r) = ra[i][j];
+    }
+#pragma unroll
+    for (int i = 0; i < C::b_vec; ++i) {
+      const int q = (int)thread.index() + 256 * i;
+      const int r = q / (BN / 4), c = 4 * (q % (BN / 4));
+      *(f32x4*)&bs.at(r, c) = rb[i];
+    }
+  };
+
+  mfma::f32x16 acc[C::fm][C::fn];
+#pragma unroll
+  for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const idx_t nk = (p.K + BK - 1) / BK;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  sync(thread);
+  for (idx_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nk) load((kt + 1) * BK);
+    auto as = a_lds.idx(buf);
+    auto bs = b_lds.idx(buf);
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int k = 2 * kk + half;
+      float a[C::fm], b[C::fn];
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i) a[i] = as.at(k, wm * C::wtm + i * 32 + col32);
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j) b[j] = bs.at(k, wn * C::wtn + j * 32 + col32);
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j) acc[i][j] = mfma::f32_32x32x2(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    sync(thread);
+  }
+
+  auto c_g = matrix(p.C, p.M, p.ldc);
+#pragma unroll
+  for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+        const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+        if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
+      }
+}
+
+}  // namespace gemm_f32
+}  // namespace desc

@@ -23,6 +23,10 @@ int64_t transpose_max_rows();
 hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_t rows,
                         int64_t cols, hipStream_t s);
 
+// gemm_f32.hip
+hipError_t gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,
+                    int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s);
+
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 
