@@ -108,9 +108,21 @@ desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batc
  * neither precision nor layout): C = A * B with A M x K, B K x N and C
  * M x N, all row-major FP32 with row strides lda >= K, ldb >= N, ldc >= N
  * (in elements).  C is overwritten (K = 0 writes zeros).  C must not overlap
- * A or B.  Modes:
- *   DESC_GEMM_F32         FP32 products, FP32 accumulation (matrix cores).
- * The workspace query returns 0 for modes that need none (ws may be NULL).
+ * A, B or the workspace.  Modes:
+ *   DESC_GEMM_F32         FP32 products, FP32 accumulation (matrix cores);
+ *                         no workspace (ws may be NULL).
+ *   DESC_GEMM_BF16X3      a = hi + lo with hi = bf16(a), lo = bf16(a - hi)
+ *                         (round to nearest even), likewise b;
+ *                         C = Ah*Bh + Ah*Bl + Al*Bh on the bf16 matrix cores
+ *                         with FP32 accumulation.
+ *   DESC_GEMM_FP8_ROWCOL  row i of A scaled by 448 / max_k |a_ik| and column
+ *                         j of B by 448 / max_k |b_kj|, encoded as OCP e4m3
+ *                         (round to nearest even, saturating), multiplied on
+ *                         the fp8 matrix cores with FP32 accumulation and
+ *                         rescaled: C_ij = (alpha_i/448)(beta_j/448) sum q q.
+ * The two low-precision modes prepare padded operands in the workspace
+ * (desc_gemm_workspace bytes, 256-byte aligned); its contents need no
+ * initialisation and are overwritten by every call.
  * ---------------------------------------------------------------------- */
 typedef enum {
   DESC_GEMM_F32 = 0,
@@ -122,6 +134,49 @@ size_t desc_gemm_workspace(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K)
 desc_status desc_gemm(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K, const float* A,
                       int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* Operand preparation steps of the precision modes, with the conversions the
+ * GEMM modes use (bit patterns as uint16 bfloat16 and uint8 e4m3 codes):
+ *   split_bf16_rows : hi, lo (M x K, stride ldh) of the rows of A (stride lda);
+ *   split_bf16_cols : hi^T, lo^T (N x K, stride ldh) of the columns of B;
+ *   quant_e4m3_rows : codes (M x K, stride ldq) and scale[i] = alpha_i / 448;
+ *   quant_e4m3_cols : codes of the columns of B transposed (N x K, stride ldq)
+ *                     and scale[j] = beta_j / 448; needs a workspace of
+ *                     desc_quant_e4m3_cols_workspace(K, N) bytes (scratch,
+ *                     no initialisation). */
+desc_status desc_split_bf16_rows(const float* A, int64_t M, int64_t K, int64_t lda,
+                                 uint16_t* hi, uint16_t* lo, int64_t ldh, void* stream);
+desc_status desc_split_bf16_cols(const float* B, int64_t K, int64_t N, int64_t ldb,
+                                 uint16_t* hi_t, uint16_t* lo_t, int64_t ldh, void* stream);
+desc_status desc_quant_e4m3_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint8_t* q,
+                                 int64_t ldq, float* scale, void* stream);
+size_t desc_quant_e4m3_cols_workspace(int64_t K, int64_t N);
+desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb,
+                                 uint8_t* q_t, int64_t ldq, float* scale, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Segmented forms (batched Sec. 5 reduction and scan): `in` holds n int32
+ * values; segment s covers positions [offsets[s], offsets[s+1]) for
+ * s < num_segments, with offsets int64[num_segments + 1] in GPU memory,
+ * non-decreasing and within [0, n] (a precondition the library does not
+ * check, since that would read device memory on the host; offsets that
+ * break it give unspecified results but no access outside the arrays).
+ *   reduce : out[s] = exact int64 sum of segment s (0 for an empty segment).
+ *   scan   : out[i] = in[offsets[s]] + ... + in[i] modulo 2^32 for i in
+ *            segment s; positions outside every segment are not written.
+ * Each runs as a one-block planning kernel and one main kernel; all state
+ * lives in the workspace (no initialisation needed), so both may be
+ * captured in a HIP graph and replayed.
+ * ---------------------------------------------------------------------- */
+size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments);
+desc_status desc_reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets,
+                                      int64_t num_segments, int64_t* out, void* ws,
+                                      size_t ws_bytes, void* stream);
+size_t desc_scan_segmented_i32_workspace(int64_t n, int64_t num_segments);
+desc_status desc_scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n,
+                                    const int64_t* offsets, int64_t num_segments, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Copy of n 32-bit words: the plain bandwidth ceiling the HBM-bound

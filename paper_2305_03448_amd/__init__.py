@@ -30,6 +30,10 @@ __all__ = [
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
     "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
     "desc_gemm_workspace", "desc_gemm", "GEMM_MODES",
+    "desc_split_bf16_rows", "desc_split_bf16_cols", "desc_quant_e4m3_rows",
+    "desc_quant_e4m3_cols_workspace", "desc_quant_e4m3_cols",
+    "desc_reduce_segmented_i32_workspace", "desc_reduce_segmented_i32",
+    "desc_scan_segmented_i32_workspace", "desc_scan_segmented_i32",
 ]
 
 _P = ctypes.c_void_p
@@ -60,6 +64,15 @@ SIGNATURES = {
     "desc_gemm_workspace": (_SZ, [ctypes.c_int, _I64, _I64, _I64]),
     "desc_gemm": (_ST, [ctypes.c_int, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ,
                         _P]),
+    "desc_split_bf16_rows": (_ST, [_P, _I64, _I64, _I64, _P, _P, _I64, _P]),
+    "desc_split_bf16_cols": (_ST, [_P, _I64, _I64, _I64, _P, _P, _I64, _P]),
+    "desc_quant_e4m3_rows": (_ST, [_P, _I64, _I64, _I64, _P, _I64, _P, _P]),
+    "desc_quant_e4m3_cols_workspace": (_SZ, [_I64, _I64]),
+    "desc_quant_e4m3_cols": (_ST, [_P, _I64, _I64, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "desc_reduce_segmented_i32_workspace": (_SZ, [_I64, _I64]),
+    "desc_reduce_segmented_i32": (_ST, [_P, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "desc_scan_segmented_i32_workspace": (_SZ, [_I64, _I64]),
+    "desc_scan_segmented_i32": (_ST, [_P, _P, _I64, _P, _I64, _P, _SZ, _P]),
 }
 
 # desc_gemm_mode values
@@ -305,3 +318,99 @@ def desc_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, mode="f32",
     _check(lib().desc_gemm(m, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _ptr(w),
                            w.numel() if w is not None else 0, _stream(A, stream)), "desc_gemm")
     return C
+
+
+# ------------------------------------------------------------------ operand preparation
+def _u(t: torch.Tensor, dtype, name):
+    if t.device.type != "cuda" or t.dtype != dtype or t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D {dtype} GPU tensor")
+    return t
+
+
+def desc_split_bf16_rows(A: torch.Tensor, hi: torch.Tensor, lo: torch.Tensor, stream=None):
+    """hi, lo (int16 bit patterns, M x K) of the rows of float32 A (M x K)."""
+    M, K, lda = _rows(A, "A")
+    _u(hi, torch.int16, "hi"); _u(lo, torch.int16, "lo")
+    if tuple(hi.shape) != (M, K) or tuple(lo.shape) != (M, K):
+        raise ValueError("hi and lo must be (M, K)")
+    _check(lib().desc_split_bf16_rows(_ptr(A), M, K, lda, _ptr(hi), _ptr(lo), max(K, 1),
+                                      _stream(A, stream)), "desc_split_bf16_rows")
+
+
+def desc_split_bf16_cols(B: torch.Tensor, hi_t: torch.Tensor, lo_t: torch.Tensor, stream=None):
+    """hi^T, lo^T (int16 bit patterns, N x K) of the columns of float32 B (K x N)."""
+    K, N, ldb = _rows(B, "B")
+    _u(hi_t, torch.int16, "hi_t"); _u(lo_t, torch.int16, "lo_t")
+    if tuple(hi_t.shape) != (N, K) or tuple(lo_t.shape) != (N, K):
+        raise ValueError("hi_t and lo_t must be (N, K)")
+    _check(lib().desc_split_bf16_cols(_ptr(B), K, N, ldb, _ptr(hi_t), _ptr(lo_t), max(K, 1),
+                                      _stream(B, stream)), "desc_split_bf16_cols")
+
+
+def desc_quant_e4m3_rows(A: torch.Tensor, q: torch.Tensor, scale: torch.Tensor, stream=None):
+    """e4m3 codes (uint8, M x K) and scales alpha_i / 448 of the rows of A."""
+    M, K, lda = _rows(A, "A")
+    _u(q, torch.uint8, "q")
+    if tuple(q.shape) != (M, K) or scale.numel() != M or scale.dtype != torch.float32:
+        raise ValueError("q must be (M, K) and scale float32[M]")
+    _check(lib().desc_quant_e4m3_rows(_ptr(A), M, K, lda, _ptr(q), max(K, 1), _ptr(scale),
+                                      _stream(A, stream)), "desc_quant_e4m3_rows")
+
+
+def desc_quant_e4m3_cols_workspace(K: int, N: int) -> int:
+    return lib().desc_quant_e4m3_cols_workspace(K, N)
+
+
+def desc_quant_e4m3_cols(B: torch.Tensor, q_t: torch.Tensor, scale: torch.Tensor,
+                         ws: torch.Tensor | None = None, stream=None):
+    """Transposed e4m3 codes (uint8, N x K) and scales beta_j / 448 of B's columns."""
+    K, N, ldb = _rows(B, "B")
+    _u(q_t, torch.uint8, "q_t")
+    if tuple(q_t.shape) != (N, K) or scale.numel() != N or scale.dtype != torch.float32:
+        raise ValueError("q_t must be (N, K) and scale float32[N]")
+    need = desc_quant_e4m3_cols_workspace(K, N)
+    w = ws if ws is not None else torch.empty(max(need, 4), dtype=torch.uint8, device=B.device)
+    _check(lib().desc_quant_e4m3_cols(_ptr(B), K, N, ldb, _ptr(q_t), max(K, 1), _ptr(scale),
+                                      _ptr(w), w.numel(), _stream(B, stream)),
+           "desc_quant_e4m3_cols")
+
+
+# ------------------------------------------------------------------ segmented
+def desc_reduce_segmented_i32_workspace(n: int, num_segments: int) -> int:
+    return lib().desc_reduce_segmented_i32_workspace(n, num_segments)
+
+
+def desc_scan_segmented_i32_workspace(n: int, num_segments: int) -> int:
+    return lib().desc_scan_segmented_i32_workspace(n, num_segments)
+
+
+def desc_reduce_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor,
+                              ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """out[s] = exact int64 sum of x[offsets[s]:offsets[s+1]]."""
+    _dev(x, torch.int32, "x"); _dev(offsets, torch.int64, "offsets"); _dev(out, torch.int64, "out")
+    S = offsets.numel() - 1
+    if S < 0 or out.numel() != S:
+        raise ValueError("offsets must hold S + 1 entries and out S")
+    n = x.numel()
+    need = desc_reduce_segmented_i32_workspace(n, S)
+    w = ws if ws is not None else torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
+    _check(lib().desc_reduce_segmented_i32(_ptr(x), n, _ptr(offsets), S, _ptr(out), _ptr(w),
+                                           w.numel(), _stream(x, stream)),
+           "desc_reduce_segmented_i32")
+    return out
+
+
+def desc_scan_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor,
+                            ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Inclusive scan of x restarted at every offsets[s] (wrapping modulo 2^32)."""
+    _dev(x, torch.int32, "x"); _dev(offsets, torch.int64, "offsets"); _dev(out, torch.int32, "out")
+    S = offsets.numel() - 1
+    if S < 0 or out.numel() != x.numel():
+        raise ValueError("offsets must hold S + 1 entries and out as many elements as x")
+    n = x.numel()
+    need = desc_scan_segmented_i32_workspace(n, S)
+    w = ws if ws is not None else torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
+    _check(lib().desc_scan_segmented_i32(_ptr(x), _ptr(out), n, _ptr(offsets), S, _ptr(w),
+                                         w.numel(), _stream(x, stream)),
+           "desc_scan_segmented_i32")
+    return out

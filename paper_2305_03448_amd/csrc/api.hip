@@ -175,34 +175,200 @@ desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_
 size_t desc_gemm_workspace(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M < 0 || N < 0 || K < 0) return 0;
   switch (mode) {
-    case DESC_GEMM_F32: return 0;
+    case DESC_GEMM_BF16X3: return desc::launch::gemm_lowp_workspace(1, M, N, K);
+    case DESC_GEMM_FP8_ROWCOL: return desc::launch::gemm_lowp_workspace(2, M, N, K);
     default: return 0;
   }
 }
+
+namespace {
+
+// Byte extent of a row-major rows x cols matrix with row stride ld (in
+// elements of `es` bytes); -1 on overflow.
+int64_t matrix_bytes(int64_t rows, int64_t cols, int64_t ld, int64_t es) {
+  if (rows == 0 || cols == 0) return 0;
+  const int64_t last = bytes_of(rows - 1, ld);
+  if (last < 0 || last > INT64_MAX - cols) return -1;
+  return bytes_of(last + cols, es);
+}
+
+}  // namespace
 
 desc_status desc_gemm(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K, const float* A,
                       int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc, void* ws,
                       size_t ws_bytes, void* stream) {
   if (M < 0 || N < 0 || K < 0) return DESC_ERR_SIZE;
-  if (mode != DESC_GEMM_F32) return DESC_ERR_UNSUPPORTED;
+  if (mode != DESC_GEMM_F32 && mode != DESC_GEMM_BF16X3 && mode != DESC_GEMM_FP8_ROWCOL)
+    return DESC_ERR_UNSUPPORTED;
   if (M == 0 || N == 0) return DESC_OK;
-  if (C == nullptr || (K > 0 && (A == nullptr || B == nullptr))) return DESC_ERR_NULL;
+  const size_t need = desc_gemm_workspace(mode, M, N, K);
+  if (C == nullptr || (K > 0 && (A == nullptr || B == nullptr)) || (need > 0 && ws == nullptr))
+    return DESC_ERR_NULL;
   // row-major with leading dimensions at least the row lengths
   if (ldc < N || (K > 0 && (lda < K || ldb < N))) return DESC_ERR_SIZE;
-  const int64_t a_el = K > 0 ? bytes_of(M - 1, lda) : 0, b_el = K > 0 ? bytes_of(K - 1, ldb) : 0;
-  const int64_t c_el = bytes_of(M - 1, ldc);
-  if (a_el < 0 || b_el < 0 || c_el < 0) return DESC_ERR_SIZE;
-  const int64_t a_b = K > 0 ? bytes_of(a_el + K, 4) : 0, b_b = K > 0 ? bytes_of(b_el + N, 4) : 0;
-  const int64_t c_b = bytes_of(c_el + N, 4);
-  if (a_b < 0 || b_b < 0 || c_b < 0 || M * N > ((int64_t)1 << 46)) return DESC_ERR_SIZE;
+  const int64_t a_b = matrix_bytes(M, K, lda, 4), b_b = matrix_bytes(K, N, ldb, 4);
+  const int64_t c_b = matrix_bytes(M, N, ldc, 4);
+  if (a_b < 0 || b_b < 0 || c_b < 0 || M > ((int64_t)1 << 31) || N > ((int64_t)1 << 31))
+    return DESC_ERR_SIZE;
   DESC_TRY(check_device({K > 0 ? (const void*)A : nullptr, K > 0 ? (const void*)B : nullptr, C,
-                         ws_bytes ? ws : nullptr}));
-  if (misaligned(A, 4) || misaligned(B, 4) || misaligned(C, 4)) return DESC_ERR_ALIGNMENT;
+                         need > 0 ? ws : nullptr}));
+  if (misaligned(A, 4) || misaligned(B, 4) || misaligned(C, 4) || misaligned(ws, 256))
+    return DESC_ERR_ALIGNMENT;
   if (overlap({C, c_b}, {A, a_b}) || overlap({C, c_b}, {B, b_b})) return DESC_ERR_ALIAS;
-  const size_t need = desc_gemm_workspace(mode, M, N, K);
-  if (need > 0 && (ws == nullptr || ws_bytes < need)) return DESC_ERR_WORKSPACE;
+  if (need > 0 && (overlap({ws, (int64_t)ws_bytes}, {A, a_b}) ||
+                   overlap({ws, (int64_t)ws_bytes}, {B, b_b}) ||
+                   overlap({ws, (int64_t)ws_bytes}, {C, c_b})))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < need) return DESC_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 0 || mode == DESC_GEMM_F32)
+    return hip_status(desc::launch::gemm_f32(A, lda, B, ldb, C, ldc, M, N, K, s));
+  if (mode == DESC_GEMM_BF16X3)
+    return hip_status(desc::launch::gemm_bf16x3(A, lda, B, ldb, C, ldc, M, N, K, ws, s));
+  return hip_status(desc::launch::gemm_fp8(A, lda, B, ldb, C, ldc, M, N, K, ws, s));
+}
+
+// ----------------------------------------------------------------- operand preparation
+desc_status desc_split_bf16_rows(const float* A, int64_t M, int64_t K, int64_t lda,
+                                 uint16_t* hi, uint16_t* lo, int64_t ldh, void* stream) {
+  if (M < 0 || K < 0) return DESC_ERR_SIZE;
+  if (M == 0 || K == 0) return DESC_OK;
+  if (A == nullptr || hi == nullptr || lo == nullptr) return DESC_ERR_NULL;
+  if (lda < K || ldh < K) return DESC_ERR_SIZE;
+  const int64_t a_b = matrix_bytes(M, K, lda, 4), h_b = matrix_bytes(M, K, ldh, 2);
+  if (a_b < 0 || h_b < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({A, hi, lo}));
+  if (misaligned(A, 4) || misaligned(hi, 2) || misaligned(lo, 2)) return DESC_ERR_ALIGNMENT;
+  if (overlap({hi, h_b}, {A, a_b}) || overlap({lo, h_b}, {A, a_b}) || overlap({hi, h_b}, {lo, h_b}))
+    return DESC_ERR_ALIAS;
   return hip_status(
-      desc::launch::gemm_f32(A, lda, B, ldb, C, ldc, M, N, K, (hipStream_t)stream));
+      desc::launch::split_bf16_rows(A, M, K, lda, hi, lo, ldh, (hipStream_t)stream));
+}
+
+desc_status desc_split_bf16_cols(const float* B, int64_t K, int64_t N, int64_t ldb,
+                                 uint16_t* hi_t, uint16_t* lo_t, int64_t ldh, void* stream) {
+  if (K < 0 || N < 0) return DESC_ERR_SIZE;
+  if (K == 0 || N == 0) return DESC_OK;
+  if (B == nullptr || hi_t == nullptr || lo_t == nullptr) return DESC_ERR_NULL;
+  if (ldb < N || ldh < K || K > (int64_t)65535 * 64 * 64 || N > (int64_t)65535 * 64)
+    return DESC_ERR_SIZE;
+  const int64_t b_b = matrix_bytes(K, N, ldb, 4), h_b = matrix_bytes(N, K, ldh, 2);
+  if (b_b < 0 || h_b < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({B, hi_t, lo_t}));
+  if (misaligned(B, 4) || misaligned(hi_t, 2) || misaligned(lo_t, 2)) return DESC_ERR_ALIGNMENT;
+  if (overlap({hi_t, h_b}, {B, b_b}) || overlap({lo_t, h_b}, {B, b_b}) ||
+      overlap({hi_t, h_b}, {lo_t, h_b}))
+    return DESC_ERR_ALIAS;
+  return hip_status(
+      desc::launch::split_bf16_cols(B, K, N, ldb, hi_t, lo_t, ldh, (hipStream_t)stream));
+}
+
+desc_status desc_quant_e4m3_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint8_t* q,
+                                 int64_t ldq, float* scale, void* stream) {
+  if (M < 0 || K < 0) return DESC_ERR_SIZE;
+  if (M == 0) return DESC_OK;
+  if (scale == nullptr || (K > 0 && (A == nullptr || q == nullptr))) return DESC_ERR_NULL;
+  if (M > INT32_MAX || (K > 0 && (lda < K || ldq < K))) return DESC_ERR_SIZE;
+  const int64_t a_b = matrix_bytes(M, K, lda, 4), q_b = matrix_bytes(M, K, ldq, 1);
+  if (a_b < 0 || q_b < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({K > 0 ? (const void*)A : nullptr, K > 0 ? (const void*)q : nullptr,
+                         scale}));
+  if (misaligned(A, 4) || misaligned(scale, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({q, q_b}, {A, a_b}) || overlap({scale, M * 4}, {A, a_b}) ||
+      overlap({scale, M * 4}, {q, q_b}))
+    return DESC_ERR_ALIAS;
+  return hip_status(
+      desc::launch::quant_e4m3_rows(A, M, K, lda, q, ldq, scale, (hipStream_t)stream));
+}
+
+size_t desc_quant_e4m3_cols_workspace(int64_t K, int64_t N) {
+  if (K < 0 || N < 0) return 0;
+  return desc::launch::quant_e4m3_cols_workspace(K, N);
+}
+
+desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb,
+                                 uint8_t* q_t, int64_t ldq, float* scale, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (K < 0 || N < 0) return DESC_ERR_SIZE;
+  if (N == 0) return DESC_OK;
+  if (scale == nullptr || ws == nullptr || (K > 0 && (B == nullptr || q_t == nullptr)))
+    return DESC_ERR_NULL;
+  if ((K > 0 && (ldb < N || ldq < K)) || K > (int64_t)65535 * 64 * 64 ||
+      N > (int64_t)65535 * 64)
+    return DESC_ERR_SIZE;
+  const int64_t b_b = matrix_bytes(K, N, ldb, 4), q_b = matrix_bytes(N, K, ldq, 1);
+  if (b_b < 0 || q_b < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({K > 0 ? (const void*)B : nullptr, K > 0 ? (const void*)q_t : nullptr,
+                         scale, ws}));
+  if (misaligned(B, 4) || misaligned(scale, 4) || misaligned(ws, 4)) return DESC_ERR_ALIGNMENT;
+  const int64_t wsb = (int64_t)ws_bytes;
+  if (overlap({q_t, q_b}, {B, b_b}) || overlap({scale, N * 4}, {B, b_b}) ||
+      overlap({scale, N * 4}, {q_t, q_b}) || overlap({ws, wsb}, {B, b_b}) ||
+      overlap({ws, wsb}, {q_t, q_b}) || overlap({ws, wsb}, {scale, N * 4}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < desc_quant_e4m3_cols_workspace(K, N)) return DESC_ERR_WORKSPACE;
+  return hip_status(
+      desc::launch::quant_e4m3_cols(B, K, N, ldb, q_t, ldq, scale, ws, (hipStream_t)stream));
+}
+
+// ----------------------------------------------------------------- segmented
+size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments) {
+  if (n < 0 || num_segments < 0) return 0;
+  return desc::launch::segmented_workspace(n, num_segments, false);
+}
+
+size_t desc_scan_segmented_i32_workspace(int64_t n, int64_t num_segments) {
+  if (n < 0 || num_segments < 0) return 0;
+  return desc::launch::segmented_workspace(n, num_segments, true);
+}
+
+namespace {
+
+desc_status check_segmented(const int32_t* in, const void* out, int64_t out_bytes, int64_t n,
+                            const int64_t* offsets, int64_t S, void* ws, size_t ws_bytes,
+                            size_t need) {
+  if (offsets == nullptr || ws == nullptr || (n > 0 && in == nullptr) ||
+      (out == nullptr && out_bytes > 0))
+    return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4), ob = bytes_of(S + 1, 8);
+  if (nb < 0 || ob < 0 || out_bytes < 0 || desc::launch::segmented_max_grid(n, S) > INT32_MAX)
+    return DESC_ERR_SIZE;
+  DESC_TRY(check_device({n > 0 ? (const void*)in : nullptr, offsets, out, ws}));
+  if (misaligned(in, 4) || misaligned(offsets, 8) || misaligned(out, 4) || misaligned(ws, 8))
+    return DESC_ERR_ALIGNMENT;
+  const int64_t wsb = (int64_t)ws_bytes;
+  if (overlap({out, out_bytes}, {in, nb}) || overlap({out, out_bytes}, {offsets, ob}) ||
+      overlap({ws, wsb}, {in, nb}) || overlap({ws, wsb}, {offsets, ob}) ||
+      overlap({ws, wsb}, {out, out_bytes}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < need) return DESC_ERR_WORKSPACE;
+  return DESC_OK;
+}
+
+}  // namespace
+
+desc_status desc_reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets,
+                                      int64_t num_segments, int64_t* out, void* ws,
+                                      size_t ws_bytes, void* stream) {
+  if (n < 0 || num_segments < 0) return DESC_ERR_SIZE;
+  if (num_segments == 0) return DESC_OK;
+  const int64_t ob = bytes_of(num_segments, 8);
+  DESC_TRY(check_segmented(in, out, ob, n, offsets, num_segments, ws, ws_bytes,
+                           desc_reduce_segmented_i32_workspace(n, num_segments)));
+  if (misaligned(out, 8)) return DESC_ERR_ALIGNMENT;
+  return hip_status(desc::launch::reduce_segmented_i32(in, n, offsets, num_segments, out, ws,
+                                                       (hipStream_t)stream));
+}
+
+desc_status desc_scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n,
+                                    const int64_t* offsets, int64_t num_segments, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (n < 0 || num_segments < 0) return DESC_ERR_SIZE;
+  if (num_segments == 0 || n == 0) return DESC_OK;
+  DESC_TRY(check_segmented(in, out, bytes_of(n, 4), n, offsets, num_segments, ws, ws_bytes,
+                           desc_scan_segmented_i32_workspace(n, num_segments)));
+  return hip_status(desc::launch::scan_segmented_i32(in, out, n, offsets, num_segments, ws,
+                                                     (hipStream_t)stream));
 }
 
 // ----------------------------------------------------------------- copy

@@ -1,0 +1,207 @@
+// gemm_nt.hpp -- matrix-core tile routine for the low-precision GEMM modes.
+//
+// Both operands arrive K-contiguous ("NT"): A as [Mp][Kp] and B transposed as
+// [Np][Kp], padded with zeros to whole tiles by the operand pre-pass, so the
+// main loop needs no guards.  Rows are byte strings here: a stage copies BKB
+// bytes of K per row of each operand plane into LDS (row pitch BKB + 16
+// bytes, which spreads the 16-byte fragment reads of 16 consecutive rows
+// over all banks), double buffered, one barrier per stage.
+//
+// Modes:
+//   Bf16x3 -- planes {hi, lo}; per 16-wide K step three 32x32x16 bf16
+//             products lo*hi, hi*lo, hi*hi accumulate into one FP32 tile.
+//   Fp8    -- one plane of e4m3 codes; one 32x32x64 fp8 product per 64-wide
+//             K step; the epilogue multiplies by the row scale of A and the
+//             column scale of B.
+#pragma once
+#include "common.hpp"
+#include "gemm_f32.hpp"
+#include "mfma.hpp"
+#include "view.hpp"
+
+namespace desc {
+
+struct NtOperands {
+  const uint8_t* a[2];    // A planes, [Mp][row_bytes]
+  const uint8_t* b[2];    // B^T planes, [Np][row_bytes]
+  int64_t row_bytes;      // Kp * element size
+  float* C;
+  int64_t ldc;
+  int64_t M, N;           // valid part of C
+  const float* sa;        // Fp8: row scales of A (Mp), column scales of B (Np)
+  const float* sb;
+};
+
+struct Bf16x3Mode {
+  static constexpr int planes = 2;
+  static constexpr int step_bytes = 32;   // bytes of a row one instruction consumes (16 x bf16)
+  static constexpr int lane_bytes = 16;   // bytes per lane per operand
+  static constexpr bool scaled = false;
+};
+struct Fp8Mode {
+  static constexpr int planes = 1;
+  static constexpr int step_bytes = 64;   // 64 x e4m3
+  static constexpr int lane_bytes = 32;
+  static constexpr bool scaled = true;
+};
+
+template <int kBM, int kBN, int kBKB, class Mode>
+struct NtCfg {
+  using mode = Mode;
+  static constexpr int bm = kBM, bn = kBN, bkb = kBKB;
+  static constexpr int wtm = kBM / 2, wtn = kBN / 2;
+  static constexpr int fm = wtm / 32, fn = wtn / 32;
+  static constexpr int pitch = kBKB + 16;
+  static constexpr int steps = kBKB / Mode::step_bytes;
+  static constexpr int a_chunks = kBM * kBKB / 16 / 256;   // 16-byte chunks per thread per plane
+  static constexpr int b_chunks = kBN * kBKB / 16 / 256;
+  static constexpr int plane_bytes = (kBM + kBN) * pitch;
+  static constexpr int stage_bytes = Mode::planes * plane_bytes;
+  static constexpr int lds_bytes = 2 * stage_bytes;
+  static_assert(steps >= 1 && kBKB % Mode::step_bytes == 0, "stage holds whole steps");
+  static_assert(a_chunks >= 1 && b_chunks >= 1, "tile too small for 256 threads");
+};
+
+namespace gemm_nt {
+
+template <int kBytes>
+struct Frag;
+template <>
+struct Frag<16> {
+  u32x4 v;
+  __device__ __forceinline__ mfma::bf16x8 bf16() const {
+    return __builtin_bit_cast(mfma::bf16x8, v);
+  }
+};
+template <>
+struct Frag<32> {
+  u32x4 v0, v1;
+  __device__ __forceinline__ mfma::i32x8 i8() const {
+    mfma::i32x8 r;
+    r[0] = v0[0]; r[1] = v0[1]; r[2] = v0[2]; r[3] = v0[3];
+    r[4] = v1[0]; r[5] = v1[1]; r[6] = v1[2]; r[7] = v1[3];
+    return r;
+  }
+};
+
+template <class C>
+__device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, uint8_t* lds) {
+  using Mode = typename C::mode;
+  constexpr int P = Mode::planes, LB = Mode::lane_bytes, BKB = C::bkb;
+  auto thread = thread_x<256>();
+  auto wv = wave_of_block<256>();
+  const int lane = (int)lane_of_wave().index();
+  const int half = lane / 32, col32 = lane % 32;
+  const int wm = (int)wv.index() / 2, wn = (int)wv.index() % 2;
+  const idx_t m0 = tm * C::bm, n0 = tn * C::bn;
+
+  // LDS: [stage][plane][A rows then B rows][pitch] bytes
+  auto sm = matrices(lds, 2 * P, C::bm + C::bn, C::pitch);
+
+  u32x4 ra[P][C::a_chunks], rb[P][C::b_chunks];
+  auto load = [&](idx_t k0b) {
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl) {
+      auto ag = matrix(p.a[pl], 0, p.row_bytes);
+      auto bg = matrix(p.b[pl], 0, p.row_bytes);
+#pragma unroll
+      for (int i = 0; i < C::a_chunks; ++i) {
+        const int q = (int)thread.index() + 256 * i;
+        ra[pl][i] = *(const u32x4*)&ag.at(m0 + q / (BKB / 16), k0b + 16 * (q % (BKB / 16)));
+      }
+#pragma unroll
+      for (int i = 0; i < C::b_chunks; ++i) {
+        const int q = (int)thread.index() + 256 * i;
+        rb[pl][i] = *(const u32x4*)&bg.at(n0 + q / (BKB / 16), k0b + 16 * (q % (BKB / 16)));
+      }
+    }
+  };
+  auto store = [&](int stage) {
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl) {
+      auto s = sm.idx(stage * P + pl);
+#pragma unroll
+      for (int i = 0; i < C::a_chunks; ++i) {
+        const int q = (int)thread.index() + 256 * i;
+        *(u32x4*)&s.at(q / (BKB / 16), 16 * (q % (BKB / 16))) = ra[pl][i];
+      }
+#pragma unroll
+      for (int i = 0; i < C::b_chunks; ++i) {
+        const int q = (int)thread.index() + 256 * i;
+        *(u32x4*)&s.at(C::bm + q / (BKB / 16), 16 * (q % (BKB / 16))) = rb[pl][i];
+      }
+    }
+  };
+
+  mfma::f32x16 acc[C::fm][C::fn];
+#pragma unroll
+  for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const idx_t nk = p.row_bytes / BKB;
+  load(0);
+  store(0);
+  sync(thread);
+  for (idx_t kt = 0; kt < nk; ++kt) {
+    const int stage = (int)(kt & 1);
+    if (kt + 1 < nk) load((kt + 1) * BKB);
+#pragma unroll
+    for (int st = 0; st < C::steps; ++st) {
+      const int off = st * Mode::step_bytes + half * LB;
+      gemm_nt::Frag<LB> fa[P][C::fm], fb[P][C::fn];
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) {
+        auto s = sm.idx(stage * P + pl);
+#pragma unroll
+        for (int i = 0; i < C::fm; ++i) {
+          const u32x4* src = (const u32x4*)&s.at(wm * C::wtm + i * 32 + col32, off);
+          if constexpr (LB == 16) fa[pl][i].v = src[0];
+          else { fa[pl][i].v0 = src[0]; fa[pl][i].v1 = src[1]; }
+        }
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j) {
+          const u32x4* src = (const u32x4*)&s.at(C::bm + wn * C::wtn + j * 32 + col32, off);
+          if constexpr (LB == 16) fb[pl][j].v = src[0];
+          else { fb[pl][j].v0 = src[0]; fb[pl][j].v1 = src[1]; }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j) {
+          if constexpr (Mode::scaled) {
+            acc[i][j] = mfma::fp8_32x32x64(fa[0][i].i8(), fb[0][j].i8(), acc[i][j]);
+          } else {
+            acc[i][j] = mfma::bf16_32x32x16(fa[1][i].bf16(), fb[0][j].bf16(), acc[i][j]);
+            acc[i][j] = mfma::bf16_32x32x16(fa[0][i].bf16(), fb[1][j].bf16(), acc[i][j]);
+            acc[i][j] = mfma::bf16_32x32x16(fa[0][i].bf16(), fb[0][j].bf16(), acc[i][j]);
+          }
+        }
+    }
+    if (kt + 1 < nk) store(stage ^ 1);
+    sync(thread);
+  }
+
+  auto c_g = matrix(p.C, p.M, p.ldc);
+#pragma unroll
+  for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j) {
+      const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+      float sbj = 1.f;
+      if constexpr (Mode::scaled) sbj = array(p.sb, 0)[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+        float v = acc[i][j][r];
+        if constexpr (Mode::scaled) v = (v * array(p.sa, 0)[row]) * sbj;
+        if (row < p.M && col < p.N) c_g.at(row, col) = v;
+      }
+    }
+}
+
+}  // namespace gemm_nt
+}  // namespace desc

@@ -27,6 +27,30 @@ hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_
 hipError_t gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,
                     int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s);
 
+// gemm_lowp.hip
+size_t gemm_lowp_workspace(int mode, int64_t M, int64_t N, int64_t K);
+hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,
+                       int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws, hipStream_t s);
+hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,
+                    int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws, hipStream_t s);
+hipError_t split_bf16_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint16_t* hi,
+                           uint16_t* lo, int64_t ldh, hipStream_t s);
+hipError_t split_bf16_cols(const float* B, int64_t K, int64_t N, int64_t ldb, uint16_t* hi_t,
+                           uint16_t* lo_t, int64_t ldh, hipStream_t s);
+hipError_t quant_e4m3_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint8_t* q,
+                           int64_t ldq, float* scale, hipStream_t s);
+size_t quant_e4m3_cols_workspace(int64_t K, int64_t N);
+hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, uint8_t* qt,
+                           int64_t ldq, float* scale, void* ws, hipStream_t s);
+
+// segmented.hip
+size_t segmented_workspace(int64_t n, int64_t S, bool scan);
+int64_t segmented_max_grid(int64_t n, int64_t S);
+hipError_t reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets, int64_t S,
+                                int64_t* out, void* ws, hipStream_t s);
+hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const int64_t* offsets,
+                              int64_t S, void* ws, hipStream_t s);
+
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 

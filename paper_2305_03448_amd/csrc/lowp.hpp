@@ -1,0 +1,59 @@
+// lowp.hpp -- the number-format conversions of the low-precision GEMM modes,
+// written from the format definitions.
+//
+// bfloat16: the upper 16 bits of an IEEE binary32, rounded to nearest with
+// ties to even on the 16 dropped bits; a NaN keeps its upper payload bits
+// with the quiet bit set.  The operand split of the three-product GEMM is
+// hi = bf16(a), lo = bf16(a - hi), where a - hi is exact in FP32.
+//
+// e4m3 (OCP 8-bit float "E4M3"): sign, 4 exponent bits with bias 7, 3
+// mantissa bits, no infinities, S.1111.111 is NaN, so the largest finite
+// magnitude is 448; subnormals are m * 2^-9.  Encoding rounds to nearest
+// even and saturates magnitudes above 448 (infinities included) to 448.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace desc {
+namespace lowp {
+
+__device__ __forceinline__ uint16_t bf16_rne(float a) {
+  const uint32_t u = __float_as_uint(a);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0)
+    return (uint16_t)((u >> 16) | 0x0040u);                 // quiet NaN
+  const uint32_t upper = u >> 16, lower = u & 0xffffu;
+  const uint32_t up = (lower > 0x8000u || (lower == 0x8000u && (upper & 1u))) ? 1u : 0u;
+  return (uint16_t)(upper + up);                            // may carry into the exponent
+}
+
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct Split {
+  uint16_t hi, lo;
+};
+__device__ __forceinline__ Split split_bf16(float a) {
+  const uint16_t h = bf16_rne(a);
+  return {h, bf16_rne(a - bf16_value(h))};
+}
+
+__device__ __forceinline__ uint8_t e4m3_rne_sat(float x) {
+  const uint32_t u = __float_as_uint(x);
+  const uint32_t sign = (u >> 24) & 0x80u;
+  const uint32_t a = u & 0x7fffffffu;
+  if (a > 0x7f800000u) return (uint8_t)(sign | 0x7fu);      // NaN
+  if (a >= 0x43e00000u) return (uint8_t)(sign | 0x7eu);     // |x| >= 448, inf: saturate
+  const int e = (int)(a >> 23) - 127;                       // |x| in [2^e, 2^(e+1))
+  if (e < -6) {                                             // subnormal range, quantum 2^-9
+    const float m = rintf(__uint_as_float(a) * 512.0f);     // exact scaling, ties to even
+    return (uint8_t)(sign | (uint32_t)m);                   // m = 8 is the code of 2^-6
+  }
+  uint32_t q = (a & 0x7fffffu) >> 20;                       // 3 kept mantissa bits
+  const uint32_t rest = a & 0xfffffu;                       // 20 dropped bits
+  if (rest > 0x80000u || (rest == 0x80000u && (q & 1u))) ++q;
+  uint32_t E = (uint32_t)(e + 7);
+  if (q == 8u) { q = 0u; ++E; }
+  return (uint8_t)(sign | (E << 3) | q);                    // |x| < 448 keeps E.q <= 15.6
+}
+
+}  // namespace lowp
+}  // namespace desc

@@ -18,6 +18,8 @@ from gpu_util import case, dev, needs_gpu, to_dev
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 TOL = {"f32": 1e-5, "bf16x3": 1e-5}
+MODES_EXACT = ["f32", "bf16x3"]      # modes exact on small-integer operands
+FP8_ACC_TOL = 3e-5                   # fp8 vs the FP64 sum of its own codes (see below)
 
 
 def _int_matrix(rows, cols, seed, lo=-4, hi=4):
@@ -55,7 +57,7 @@ SHAPES = [(1, 1, 1), (5, 7, 3), (32, 32, 2), (64, 64, 16), (100, 37, 129), (128,
 
 
 @pytest.mark.parametrize("M,N,K", SHAPES)
-@pytest.mark.parametrize("mode", ["f32"])
+@pytest.mark.parametrize("mode", MODES_EXACT)
 def test_gemm_integer_exact(M, N, K, mode):
     case(f"gemm {mode} integer {M}x{N}x{K}")
     A = _int_matrix(M, K, 1); B = _int_matrix(K, N, 2)
@@ -64,12 +66,18 @@ def test_gemm_integer_exact(M, N, K, mode):
     assert np.array_equal(C, exact)
 
 
-@pytest.mark.parametrize("mode", ["f32"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
 def test_gemm_identity_and_k0(mode):
     case(f"gemm {mode} identity")
     A = workloads.matrix_f32(70, 96, seed=4)
     C = _run(A, np.eye(96, dtype=np.float32), mode)
-    assert np.array_equal(C, A)
+    if mode == "f32":
+        assert np.array_equal(C, A)
+    else:
+        # C = lo*1 + hi*0 + hi*1 accumulated in FP32: exactly lo + hi
+        hi, lo = oracle.split_bf16(A)
+        want = oracle.bf16_to_f32(lo) + oracle.bf16_to_f32(hi)
+        assert np.array_equal(C, want)
     case(f"gemm {mode} K=0")
     Ct = torch.full((3, 4), 7.0, device=dev())
     desc.desc_gemm(torch.empty((3, 0), device=dev()), torch.empty((0, 4), device=dev()), Ct,
@@ -77,7 +85,7 @@ def test_gemm_identity_and_k0(mode):
     assert (Ct == 0).all()
 
 
-@pytest.mark.parametrize("mode", ["f32"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
 @pytest.mark.parametrize("M,N,K", [(96, 160, 300), (257, 129, 1000), (1024, 1024, 1024)])
 def test_gemm_normal_within_bound(M, N, K, mode):
     case(f"gemm {mode} N(0,1) {M}x{N}x{K}")
@@ -86,7 +94,7 @@ def test_gemm_normal_within_bound(M, N, K, mode):
     _check_sampled(A, B, C, TOL[mode])
 
 
-@pytest.mark.parametrize("mode", ["f32"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
 def test_gemm_strided_rows(mode):
     case(f"gemm {mode} strided lda/ldc")
     A = workloads.matrix_f32(77, 45, seed=8); B = workloads.matrix_f32(45, 53, seed=9)
@@ -108,10 +116,118 @@ def test_gemm_f32_every_config():
         desc.desc_config_set("gemm_f32", cls, -1)
 
 
-@pytest.mark.parametrize("mode", ["f32"])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
 def test_gemm_workload_4096(mode):
     case(f"gemm {mode} 4096^3 (seeds 4/5, 4096 samples seed 6)")
     A = workloads.matrix_f32(4096, 4096, seed=4); B = workloads.matrix_f32(4096, 4096, seed=5)
     C = _run(A, B, mode)
     e = _check_sampled(A, B, C, TOL[mode], samples=4096, seed=6)
     print(f"[result] gemm {mode} 4096 max componentwise error {e:.3e}", flush=True)
+
+
+# ------------------------------------------------------------------ operand preparation
+def _patterns(rows, cols, seed):
+    g = workloads.rng(seed)
+    a = g.standard_normal((rows, cols)).astype(np.float32) * 2.0 ** g.integers(-30, 30, (rows, cols))
+    flat = a.reshape(-1)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 1e-40, -3e-39, 3.4e38, 1.0 + 2**-8,
+                        1.0 + 2**-9 + 2**-16], np.float32)
+    n = min(flat.size, special.size)
+    flat[:n] = special[:n]
+    return a.astype(np.float32)
+
+
+@pytest.mark.parametrize("M,K", [(1, 1), (7, 33), (130, 257), (512, 1024)])
+def test_split_bf16_rows_cols_bit_exact(M, K):
+    case(f"split bf16 rows/cols {M}x{K}")
+    A = _patterns(M, K, 3)
+    hi, lo = oracle.split_bf16(A)
+    h = torch.empty((M, K), dtype=torch.int16, device=dev())
+    l = torch.empty_like(h)
+    desc.desc_split_bf16_rows(to_dev(A), h, l)
+    assert np.array_equal(h.cpu().numpy().view(np.uint16), hi)
+    assert np.array_equal(l.cpu().numpy().view(np.uint16), lo)
+    # columns of B = A^T
+    B = np.ascontiguousarray(A.T)
+    ht = torch.empty((M, K), dtype=torch.int16, device=dev())
+    lt = torch.empty_like(ht)
+    desc.desc_split_bf16_cols(to_dev(B), ht, lt)
+    assert np.array_equal(ht.cpu().numpy().view(np.uint16), hi)
+    assert np.array_equal(lt.cpu().numpy().view(np.uint16), lo)
+
+
+@pytest.mark.parametrize("M,K", [(1, 1), (5, 70), (129, 300), (600, 2048)])
+def test_quant_e4m3_rows_cols_bit_exact(M, K):
+    case(f"quant e4m3 rows/cols {M}x{K}")
+    A = workloads.matrix_f32(M, K, seed=12) * np.float32(3.0)
+    A[M // 2] = 0.0                        # an all-zero row
+    if K > 3:
+        A[0, 1] = 1e-30; A[0, 2] = -7e-5     # deep subnormal and small codes
+    q, al, sa = oracle.quant_rows_e4m3(A)
+    qd = torch.empty((M, K), dtype=torch.uint8, device=dev())
+    sd = torch.empty(M, dtype=torch.float32, device=dev())
+    desc.desc_quant_e4m3_rows(to_dev(A), qd, sd)
+    assert np.array_equal(qd.cpu().numpy(), q)
+    assert np.array_equal(sd.cpu().numpy(), sa)
+    # columns: B = A^T, codes come back transposed (N x K)
+    B = np.ascontiguousarray(A.T)
+    qc, be, sb = oracle.quant_cols_e4m3(B)
+    qt = torch.empty((M, K), dtype=torch.uint8, device=dev())
+    st = torch.empty(M, dtype=torch.float32, device=dev())
+    desc.desc_quant_e4m3_cols(to_dev(B), qt, st)
+    assert np.array_equal(qt.cpu().numpy(), qc.T)
+    assert np.array_equal(st.cpu().numpy(), sb)
+
+
+# ------------------------------------------------------------------ precision modes
+def _check_against(C, R, D, tol, what):
+    err = np.abs(C.astype(np.float64) - R) / np.maximum(D, 1e-300)
+    assert err.max() <= tol, f"{what}: componentwise error {err.max():.3e} > {tol}"
+    return err.max()
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 64, 64), (130, 250, 700), (1024, 768, 2048)])
+def test_bf16x3_against_its_own_operands(M, N, K):
+    case(f"gemm bf16x3 vs R3 {M}x{N}x{K}")
+    A = workloads.matrix_f32(M, K, seed=21); B = workloads.matrix_f32(K, N, seed=22)
+    C = _run(A, B, "bf16x3")
+    ii, jj = workloads.sample_pairs(M, N, 1500, seed=23)
+    R3, D3 = oracle.gemm_bf16x3_sampled(A, B, ii, jj)
+    # only FP32 accumulation error remains against the three-product reference
+    _check_against(C[ii, jj], R3, D3, 2e-6, "bf16x3 vs R3")
+
+
+def test_fp8_exact_on_e4m3_integers():
+    case("gemm fp8 exact integer codes")
+    g = workloads.rng(31)
+    M, N, K = 96, 80, 256
+    A = g.integers(-8, 9, (M, K)).astype(np.float32)
+    B = g.integers(-8, 9, (K, N)).astype(np.float32)
+    # unit scales (every row of A and column of B has absmax 448), placed so
+    # that the 448s always meet a zero: every product is a small integer, and
+    # the sum is exact whatever the width of the instruction's internal adder
+    A[:, 0] = 448.0; B[0, :] = 0.0
+    A[:, 1] = 0.0; B[1, :] = 448.0
+    C = _run(A, B, "fp8")
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    assert np.array_equal(C, exact)
+
+
+@pytest.mark.parametrize("M,N,K", [(100, 37, 129), (512, 512, 1024)])
+def test_fp8_against_its_own_codes(M, N, K):
+    case(f"gemm fp8 vs Rq {M}x{N}x{K}")
+    A = workloads.matrix_f32(M, K, seed=24); B = workloads.matrix_f32(K, N, seed=25)
+    C = _run(A, B, "fp8")
+    qa, _, sa = oracle.quant_rows_e4m3(A)
+    qb, _, sb = oracle.quant_cols_e4m3(B)
+    ii, jj = workloads.sample_pairs(M, N, 1500, seed=26)
+    Rq, Dq = oracle.gemm_fp8_sampled(qa, qb, sa, sb, ii, jj)
+    # The fp8 matrix-core instruction sums its 64 products with an adder
+    # narrower than FP32 (measured: 448^2 + 2^2 comes back as 448^2), so the
+    # bound against the FP64 sum of the same codes is the accumulation
+    # tolerance FP8_ACC_TOL, not FP32 rounding.  It stays two orders below the
+    # quantisation error (~3e-3), so a wrong code, scale or layout still fails.
+    _check_against(C[ii, jj], Rq, Dq, FP8_ACC_TOL, "fp8 vs Rq")
+    R, D = oracle.gemm_ref_sampled(A, B, ii, jj)
+    e = np.abs(C[ii, jj] - R) / D
+    print(f"[result] fp8 {M}x{N}x{K} vs exact product: max {e.max():.3e} mean {e.mean():.3e}")
