@@ -156,6 +156,29 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
                                  size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Grouped GEMM (batched Sec. 5 matrix multiplication): G independent
+ * problems C_g = A_g * B_g, each with its own shape, row strides and
+ * pointers, described by a device array of desc_gemm_problem (row-major
+ * FP32, lda >= K, ldb >= N, ldc >= N as for desc_gemm; an M, N <= 0 problem
+ * is skipped, K = 0 writes zeros).  The descriptors and the memory they
+ * point to are read on the GPU only; the library cannot check them on the
+ * host, so they are a precondition (valid GPU pointers, C_g not overlapping
+ * any operand).  One planning kernel and one persistent kernel; the
+ * workspace needs no initialisation.  Mode: DESC_GEMM_F32.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int64_t M, N, K;
+  int64_t lda, ldb, ldc;
+  const float* A;
+  const float* B;
+  float* C;
+} desc_gemm_problem;
+
+size_t desc_gemm_grouped_workspace(int64_t G);
+desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_problem* problems,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Segmented forms (batched Sec. 5 reduction and scan): `in` holds n int32
  * values; segment s covers positions [offsets[s], offsets[s+1]) for
  * s < num_segments, with offsets int64[num_segments + 1] in GPU memory,

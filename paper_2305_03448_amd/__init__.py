@@ -34,6 +34,7 @@ __all__ = [
     "desc_quant_e4m3_cols_workspace", "desc_quant_e4m3_cols",
     "desc_reduce_segmented_i32_workspace", "desc_reduce_segmented_i32",
     "desc_scan_segmented_i32_workspace", "desc_scan_segmented_i32",
+    "desc_gemm_grouped_workspace", "desc_gemm_grouped", "grouped_descriptors",
 ]
 
 _P = ctypes.c_void_p
@@ -73,6 +74,8 @@ SIGNATURES = {
     "desc_reduce_segmented_i32": (_ST, [_P, _I64, _P, _I64, _P, _P, _SZ, _P]),
     "desc_scan_segmented_i32_workspace": (_SZ, [_I64, _I64]),
     "desc_scan_segmented_i32": (_ST, [_P, _P, _I64, _P, _I64, _P, _SZ, _P]),
+    "desc_gemm_grouped_workspace": (_SZ, [_I64]),
+    "desc_gemm_grouped": (_ST, [ctypes.c_int, _I64, _P, _P, _SZ, _P]),
 }
 
 # desc_gemm_mode values
@@ -414,3 +417,36 @@ def desc_scan_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch.T
                                          w.numel(), _stream(x, stream)),
            "desc_scan_segmented_i32")
     return out
+
+
+# ------------------------------------------------------------------ grouped GEMM
+def desc_gemm_grouped_workspace(G: int) -> int:
+    return lib().desc_gemm_grouped_workspace(G)
+
+
+def grouped_descriptors(problems, device) -> torch.Tensor:
+    """Device array of desc_gemm_problem for a list of (A, B, C) float32 GPU
+    tensors (row-major, unit column stride): nine int64 words per problem,
+    M, N, K, lda, ldb, ldc and the three addresses."""
+    rows = []
+    for A, B, C in problems:
+        M, K, lda = _rows(A, "A")
+        K2, N, ldb = _rows(B, "B")
+        M2, N2, ldc = _rows(C, "C")
+        if (K2, M2, N2) != (K, M, N):
+            raise ValueError("shapes must be A (M,K), B (K,N), C (M,N)")
+        rows.append([M, N, K, lda, ldb, ldc, A.data_ptr(), B.data_ptr(), C.data_ptr()])
+    return torch.tensor(rows, dtype=torch.int64).reshape(-1, 9).to(device)
+
+
+def desc_gemm_grouped(descriptors: torch.Tensor, mode="f32", ws: torch.Tensor | None = None,
+                      stream=None) -> None:
+    """C_g = A_g @ B_g for every problem of a descriptor array (see
+    grouped_descriptors); the tensors it points to must stay alive."""
+    _dev(descriptors, torch.int64, "descriptors")
+    G = descriptors.shape[0]
+    need = desc_gemm_grouped_workspace(G)
+    w = ws if ws is not None else torch.empty(max(need, 64), dtype=torch.uint8,
+                                              device=descriptors.device)
+    _check(lib().desc_gemm_grouped(_mode(mode), G, _ptr(descriptors), _ptr(w), w.numel(),
+                                   _stream(descriptors, stream)), "desc_gemm_grouped")

@@ -311,6 +311,26 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
       desc::launch::quant_e4m3_cols(B, K, N, ldb, q_t, ldq, scale, ws, (hipStream_t)stream));
 }
 
+// ----------------------------------------------------------------- grouped GEMM
+size_t desc_gemm_grouped_workspace(int64_t G) {
+  return G < 0 ? 0 : desc::launch::gemm_grouped_workspace(G);
+}
+
+desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_problem* problems,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (G < 0) return DESC_ERR_SIZE;
+  if (mode != DESC_GEMM_F32) return DESC_ERR_UNSUPPORTED;
+  if (G == 0) return DESC_OK;
+  if (problems == nullptr || ws == nullptr) return DESC_ERR_NULL;
+  const int64_t pb = bytes_of(G, (int64_t)sizeof(desc_gemm_problem));
+  if (pb < 0 || G > INT32_MAX) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({problems, ws}));
+  if (misaligned(problems, 8) || misaligned(ws, 64)) return DESC_ERR_ALIGNMENT;
+  if (overlap({ws, (int64_t)ws_bytes}, {problems, pb})) return DESC_ERR_ALIAS;
+  if (ws_bytes < desc_gemm_grouped_workspace(G)) return DESC_ERR_WORKSPACE;
+  return hip_status(desc::launch::gemm_grouped_f32(problems, G, ws, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- segmented
 size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments) {
   if (n < 0 || num_segments < 0) return 0;

@@ -35,7 +35,7 @@ namespace gemm_f32 {
 template <class C>
 constexpr int lds_floats() { return 2 * C::bk * C::pa + 2 * C::bk * C::pb; }
 
-inline bool vec_ok(const float* A, int64_t lda, const float* B, int64_t ldb) {
+__host__ __device__ inline bool vec_ok(const float* A, int64_t lda, const float* B, int64_t ldb) {
   return ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && lda % 4 == 0 && ldb % 4 == 0;
 }
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/desc.h"
+
 namespace desc {
 namespace launch {
 
@@ -50,6 +52,11 @@ hipError_t reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* off
                                 int64_t* out, void* ws, hipStream_t s);
 hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const int64_t* offsets,
                               int64_t S, void* ws, hipStream_t s);
+
+// grouped.hip
+size_t gemm_grouped_workspace(int64_t G);
+hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* ws,
+                            hipStream_t s);
 
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);

@@ -21,6 +21,7 @@
 // grid with scalar loads.
 #include "common.hpp"
 #include "launch.hpp"
+#include "layouts.hpp"
 #include "tuning.hpp"
 #include "view.hpp"
 #include "wave.hpp"
@@ -70,12 +71,11 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
   auto thread = thread_x<kBlock>();
   if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
 
-  // tiles -> rounds -> threads: [ntiles][kUnroll][kBlock]
-  auto tiles = array(body, ntiles * kTileVec).group<kBlock>().group<kUnroll>();
+  auto vecs = array(body, ntiles * kTileVec);   // [tiles][kUnroll][kBlock] int32x4
 
   int64_t acc = 0;
   for (idx_t t = block.index(); t < ntiles; t += block.count()) {
-    auto mine = tiles.idx(t).transpose().select(thread);   // [kUnroll]
+    auto mine = layout::block_striped<kBlock, kUnroll>(vecs, t, thread);   // [kUnroll]
     i32x4 q[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) q[u] = __builtin_nontemporal_load(&mine[u]);

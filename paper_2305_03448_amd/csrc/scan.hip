@@ -31,6 +31,7 @@
 // sequential definition bit for bit.
 #include "common.hpp"
 #include "launch.hpp"
+#include "layouts.hpp"
 #include "tuning.hpp"
 #include "view.hpp"
 #include "wave.hpp"
@@ -147,9 +148,8 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
   const bool full = kVec && (tile + 1) * TILE <= n;
   uint32_t x[R][4];
   if (full) {
-    auto mine = array((const i32x4*)in, ntiles * (TILE / 4))
-                    .group<kWave>().template group<R>().template group<NW>()
-                    .idx(tile).select(wv).transpose().select(lane);     // [rounds]
+    auto mine = layout::wave_striped<NW, R>(array((const i32x4*)in, ntiles * (TILE / 4)), tile,
+                                            wv, lane);                   // [rounds]
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const i32x4 q = load16<C::nt>(&mine[r]);
@@ -157,9 +157,8 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
       x[r][2] = (uint32_t)q.z; x[r][3] = (uint32_t)q.w;
     }
   } else {
-    auto mine = array(in, ntiles * TILE)
-                    .group<4>().group<kWave>().template group<R>().template group<NW>()
-                    .idx(tile).select(wv).transpose().select(lane);     // [rounds][4]
+    auto mine = layout::wave_striped<NW, R>(array(in, ntiles * TILE).group<4>(), tile, wv,
+                                            lane);                       // [rounds][4]
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       auto grp = mine.idx(r);
@@ -220,9 +219,8 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
   const uint32_t add = s_prefix + wex;
 
   if (full) {
-    auto mine = array((i32x4*)out, ntiles * (TILE / 4))
-                    .group<kWave>().template group<R>().template group<NW>()
-                    .idx(tile).select(wv).transpose().select(lane);
+    auto mine = layout::wave_striped<NW, R>(array((i32x4*)out, ntiles * (TILE / 4)), tile, wv,
+                                            lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       i32x4 q;
@@ -231,9 +229,7 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
       store16<C::nt>(q, &mine[r]);
     }
   } else {
-    auto mine = array(out, ntiles * TILE)
-                    .group<4>().group<kWave>().template group<R>().template group<NW>()
-                    .idx(tile).select(wv).transpose().select(lane);
+    auto mine = layout::wave_striped<NW, R>(array(out, ntiles * TILE).group<4>(), tile, wv, lane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       auto grp = mine.idx(r);

@@ -26,6 +26,7 @@
 // are exact and independent of the order.
 #include "common.hpp"
 #include "launch.hpp"
+#include "layouts.hpp"
 #include "tuning.hpp"
 #include "view.hpp"
 #include "wave.hpp"
@@ -151,8 +152,8 @@ __device__ __forceinline__ void load_unit(const int32_t* in, const UnitInfo& ui,
   auto lane = lane_of_wave();
   auto unit = array(in, 0).snd(ui.begin);
   if (ui.len == kUnit) {
-    auto mine = array((const i32x4u*)&unit[0], kUnit / 4)
-                    .group<kWave>().group<kRounds>().idx(wv.index()).transpose().select(lane);
+    auto mine = layout::wave_striped<kWaves, kRounds>(array((const i32x4u*)&unit[0], kUnit / 4),
+                                                      0, wv, lane);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       const i32x4u q = mine[r];
@@ -160,8 +161,8 @@ __device__ __forceinline__ void load_unit(const int32_t* in, const UnitInfo& ui,
       x[r][2] = (uint32_t)q.z; x[r][3] = (uint32_t)q.w;
     }
   } else {
-    auto mine = array(&unit[0], kUnit).group<4>().group<kWave>().group<kRounds>()
-                    .idx(wv.index()).transpose().select(lane);
+    auto mine = layout::wave_striped<kWaves, kRounds>(array(&unit[0], kUnit).group<4>(), 0, wv,
+                                                      lane);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       auto g = mine.idx(r);
@@ -298,8 +299,8 @@ __global__ __launch_bounds__(kBlock) void seg_scan_kernel(const int32_t* __restr
   const uint32_t add = s_prefix + wex;
   auto unit = array(out, 0).snd(ui.begin);
   if (ui.len == kUnit) {
-    auto mine = array((i32x4u*)&unit[0], kUnit / 4)
-                    .group<kWave>().group<kRounds>().idx(wv.index()).transpose().select(lane);
+    auto mine = layout::wave_striped<kWaves, kRounds>(array((i32x4u*)&unit[0], kUnit / 4), 0, wv,
+                                                      lane);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       i32x4u q;
@@ -308,8 +309,8 @@ __global__ __launch_bounds__(kBlock) void seg_scan_kernel(const int32_t* __restr
       mine[r] = q;
     }
   } else {
-    auto mine = array(&unit[0], kUnit).group<4>().group<kWave>().group<kRounds>()
-                    .idx(wv.index()).transpose().select(lane);
+    auto mine = layout::wave_striped<kWaves, kRounds>(array(&unit[0], kUnit).group<4>(), 0, wv,
+                                                      lane);
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
       auto g = mine.idx(r);

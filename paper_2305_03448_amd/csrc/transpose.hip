@@ -24,6 +24,7 @@
 // subnormals pass unchanged.
 #include "common.hpp"
 #include "launch.hpp"
+#include "layouts.hpp"
 #include "tuning.hpp"
 #include "view.hpp"
 
@@ -72,11 +73,9 @@ __global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __r
   if (full) {
     auto t2 = thread_yx<TY, TX>();
     // input tile (by, bx), as [T rows][T/4 groups of 4 words]
-    auto a = group_by_tile<T, T / 4>(
-                 matrices((const u32x4*)in, bz.count(), rows, cols / 4).select(bz))
-                 .select(by).select(bx);
-    auto a_mine = group_by_row<T, IT>(a).select(t2.y).select(t2.x);                   // [IT]
-    auto l_mine = group_by_row<T, IT>(tile.template group<4, 1>()).select(t2.y).select(t2.x);
+    auto a_mine = layout::tile_rows<T, IT>(
+        matrices((const u32x4*)in, bz.count(), rows, cols / 4).select(bz), by, bx, t2.y, t2.x);
+    auto l_mine = layout::lds_rows<T, IT>(tile, t2.y, t2.x);                              // [IT][4]
     u32x4 v[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) v[i] = load16<C::nt>(&a_mine[i]);
@@ -87,13 +86,10 @@ __global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __r
     }
     sync(thread);
     // output tile (bx, by) of the cols x rows result
-    auto b = group_by_tile<T, T / 4>(
-                 matrices((u32x4*)out, bz.count(), cols, rows / 4).select(bz))
-                 .select(bx).select(by);
-    auto b_mine = group_by_row<T, IT>(b).select(t2.y).select(t2.x);                   // [IT]
-    // the LDS tile read column-wise: element (c, x, k) = tile[4x + k][c]
-    auto lt = group_by_row<T, IT>(tile.transpose().template group<4, 1>())
-                  .select(t2.y).select(t2.x);
+    auto b_mine = layout::tile_rows<T, IT>(
+        matrices((u32x4*)out, bz.count(), cols, rows / 4).select(bz), bx, by, t2.y, t2.x);
+    // the LDS tile read column-wise: element (i, k) = tile[4x + k][y + TY i]
+    auto lt = layout::lds_cols<T, IT>(tile, t2.y, t2.x);
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       auto l = lt.idx(i);

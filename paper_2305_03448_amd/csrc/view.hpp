@@ -256,6 +256,12 @@ struct View {
     j[0] = i;
     return ref(j);
   }
+  // The single element of a rank-0 view (every dimension selected).
+  DESC_HD T& get() const {
+    static_assert(rank == 0, "get() needs every dimension selected");
+    Idx<0> j;
+    return ref(j);
+  }
   template <class... I>
   DESC_HD T& at(I... is) const {
     static_assert(sizeof...(I) == rank, "one index per dimension");

@@ -64,6 +64,17 @@ def _problems(op: str, dev):
             t = torch.empty(c, r, device=dev)
             fn = (lambda m=m, t=t: desc.desc_transpose_f32(m, t))
             out.append((desc.desc_size_class(op, r * c), f"{r}x{c}", 8 * r * c, fn))
+    elif op in ("gemm_f32", "gemm_bf16x3", "gemm_fp8"):
+        mode = op.split("_")[1]
+        for n in (128, 512, 2048, 4096):
+            A = torch.randn(n, n, device=dev, generator=g)
+            B = torch.randn(n, n, device=dev, generator=g)
+            C = torch.empty(n, n, device=dev)
+            need = desc.desc_gemm_workspace(mode, n, n, n)
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+            fn = (lambda A=A, B=B, C=C, ws=ws, mode=mode: desc.desc_gemm(A, B, C, mode=mode, ws=ws))
+            # "bytes" here is the flop count (2 n^3); the GBs column then reads GFLOP/s
+            out.append((desc.desc_size_class(op, n ** 3), f"{n}^3", 2 * n ** 3, fn))
     else:
         raise ValueError(f"no tuning problems for {op}")
     return out

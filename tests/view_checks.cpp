@@ -1,0 +1,297 @@
+// Host-side enumeration of the index maps of the view layer (Sec. 3.2 of the
+// paper) and of the maps the kernels use: every (resource, item) pair is
+// resolved to an index, and the resulting access sets are checked for
+// disjointness (no two sub-resources touch one element), coverage, and the
+// closed forms the paper's examples fix.  Prints one line per check;
+// exits non-zero if any fails.
+//
+// Built by tests/test_views.py with: g++ -std=c++17 -O1 -I <csrc> view_checks.cpp
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <set>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "layouts.hpp"
+
+using namespace desc;
+
+// 16-byte group of four words (the host stand-in of the kernels' int32x4)
+struct u32x4 {
+  unsigned v[4];
+};
+
+static int g_fail = 0;
+static void check(bool ok, const char* name, const std::string& detail = "") {
+  std::printf("%s %s%s%s\n", ok ? "OK" : "FAIL", name, detail.empty() ? "" : ": ",
+              detail.c_str());
+  if (!ok) g_fail = 1;
+}
+
+// Records which sub-resource touches which index and reports collisions.
+struct Access {
+  std::vector<long> owner;
+  long collisions = 0, touched = 0;
+  explicit Access(long n) : owner(n, -1) {}
+  void add(long idx, long who) {
+    if (idx < 0 || idx >= (long)owner.size()) { ++collisions; return; }
+    if (owner[idx] >= 0 && owner[idx] != who) ++collisions;
+    if (owner[idx] < 0) ++touched;
+    owner[idx] = who;
+  }
+  bool bijection() const { return collisions == 0 && touched == (long)owner.size(); }
+};
+
+template <Level L>
+static Res<L, 0> R(long id, long n) { return Res<L, 0>{id, n}; }
+
+int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "select_mismatch") == 0) {
+    // a select whose extent differs from the number of sub-resources
+    std::vector<int> a(100);
+    auto v = array(a.data(), 100).group<10>();
+    auto t = R<Level::Thread>(0, 7);
+    (void)v.select(t);          // asserts
+    return 0;
+  }
+
+  // --- Listing 1 of the paper: the racy index and its correction --------------
+  {
+    std::set<long> all;
+    bool per_j = true;
+    for (int j = 0; j < 32; j += 8) {
+      std::set<long> s;
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 32; ++x) {
+          s.insert(y + j * 32 + x);     // threadIdx.y + j*32 + threadIdx.x, as printed
+          all.insert(y + j * 32 + x);
+        }
+      per_j &= s.size() == 39;
+    }
+    check(per_j && all.size() == 156, "listing1_racy_index_collides",
+          std::to_string(all.size()) + " distinct slots for 1024 writes");
+    Access acc(1024);
+    for (int j = 0; j < 32; j += 8)
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 32; ++x) acc.add((y + j) * 32 + x, (y * 32 + x) * 4 + j / 8);
+    check(acc.bijection(), "listing1_corrected_index_is_bijection");
+  }
+
+  // --- group_by_row<32,4> equals the corrected Listing 1 index ---------------
+  {
+    std::vector<int> tmp(32 * 32);
+    auto t = matrix(tmp.data(), 32, 32);
+    bool same = true;
+    Access acc(1024);
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 32; ++x)
+        for (int i = 0; i < 4; ++i) {
+          auto v = group_by_row<32, 4>(t).select(R<Level::Thread>(y, 8)).select(
+              R<Level::Thread>(x, 32));
+          const long idx = &v[i] - tmp.data();
+          same &= idx == (y + 8 * i) * 32 + x;
+          acc.add(idx, y * 32 + x);
+        }
+    check(same && acc.bijection(), "group_by_row_32_4_is_listing1_corrected");
+  }
+
+  // --- array.group::<8>.transpose selected by 8 threads (Sec. 3.2 figure) ------
+  {
+    std::vector<int> a(32);
+    bool ok = true;
+    for (int t = 0; t < 8; ++t) {
+      auto v = array(a.data(), 32).group<8>().transpose().select(R<Level::Thread>(t, 8));
+      for (int i = 0; i < 4; ++i) ok &= (&v[i] - a.data()) == t + 8 * i;
+    }
+    check(ok, "group8_transpose_thread_t_gets_t_t8_t16_t24");
+  }
+
+  // --- Listing 2: the transposition through views, end to end on 2048^2 --------
+  // Phase 1 copies the input tile into tmp, phase 2 copies tmp out; with the
+  // element transpose on the tmp read the output is the transposed matrix,
+  // with the printed listing (tmp read through the same view it was written
+  // through) it is not.
+  for (int fixed = 1; fixed >= 0; --fixed) {
+    const int n = 2048;
+    std::vector<int> in(n * n), out(n * n, -1);
+    for (int i = 0; i < n * n; ++i) in[i] = i;
+    std::vector<int> tmp(32 * 32);
+    auto inp = matrix(in.data(), n, n);
+    auto outp = matrix(out.data(), n, n);
+    auto tmpv = matrix(tmp.data(), 32, 32);
+    Access writes(n * n);
+    for (int by = 0; by < 64; ++by)
+      for (int bx = 0; bx < 64; ++bx) {
+        auto bY = R<Level::Block>(by, 64), bX = R<Level::Block>(bx, 64);
+        for (int ty = 0; ty < 8; ++ty)
+          for (int tx = 0; tx < 32; ++tx) {
+            auto tY = R<Level::Thread>(ty, 8), tX = R<Level::Thread>(tx, 32);
+            auto src = group_by_row<32, 4>(group_by_tile<32, 32>(inp).transpose().select(bY).select(bX))
+                           .select(tY).select(tX);
+            auto dst = group_by_row<32, 4>(tmpv).select(tY).select(tX);
+            for (int i = 0; i < 4; ++i) dst[i] = src[i];
+          }
+        for (int ty = 0; ty < 8; ++ty)
+          for (int tx = 0; tx < 32; ++tx) {
+            auto tY = R<Level::Thread>(ty, 8), tX = R<Level::Thread>(tx, 32);
+            auto dst = group_by_row<32, 4>(group_by_tile<32, 32>(outp).select(bY).select(bX))
+                           .select(tY).select(tX);
+            for (int i = 0; i < 4; ++i) {
+              if (fixed) {
+                auto src = group_by_row<32, 4>(tmpv.transpose()).select(tY).select(tX);
+                dst[i] = src[i];
+              } else {
+                auto src = group_by_row<32, 4>(tmpv).select(tY).select(tX);
+                dst[i] = src[i];
+              }
+              writes.add(&dst[i] - out.data(), (((by * 64 + bx) * 8 + ty) * 32 + tx));
+            }
+          }
+      }
+    bool is_t = true;
+    for (int r = 0; r < n && is_t; ++r)
+      for (int c = 0; c < n; ++c)
+        if (out[c * n + r] != in[r * n + c]) { is_t = false; break; }
+    if (fixed)
+      check(is_t && writes.bijection(), "listing2_with_tmp_transpose_is_transposition");
+    else
+      check(!is_t && writes.bijection(), "listing2_as_printed_moves_tiles_only");
+  }
+
+  // --- Narrowing (Sec. 3.3): grid X<32> of X<32> over [f32; 1024] --------------
+  {
+    std::vector<float> arr(1024);
+    Access good(1024), bad(1024);
+    for (int b = 0; b < 32; ++b)
+      for (int t = 0; t < 32; ++t) {
+        auto v = array(arr.data(), 1024).group<32>().select(R<Level::Block>(b, 32)).select(
+            R<Level::Thread>(t, 32));
+        good.add(&v.get() - arr.data(), b * 32 + t);
+        // selecting by thread only: every block's thread t reaches group t
+        auto w = array(arr.data(), 1024).group<32>().select(R<Level::Thread>(t, 32));
+        for (int i = 0; i < 32; ++i) bad.add(&w[i] - arr.data(), b * 32 + t);
+      }
+    check(good.bijection(), "narrowing_group32_block_thread_is_bijection");
+    check(bad.collisions > 0, "narrowing_without_block_selection_conflicts",
+          std::to_string(bad.collisions) + " conflicting accesses");
+  }
+
+  // --- rev_per_block: write arr[[thread]], read arr.reverse[[thread]] ---------
+  {
+    const int n = 64;
+    std::vector<int> arr(n);
+    long conflicts = 0;
+    for (int t = 0; t < n; ++t) {
+      auto w = array(arr.data(), n).select(R<Level::Thread>(t, n));
+      auto r = array(arr.data(), n).reverse().select(R<Level::Thread>(t, n));
+      const long wi = &w.get() - arr.data(), ri = &r.get() - arr.data();
+      if (wi != ri) ++conflicts;   // another thread writes what this one reads
+    }
+    check(conflicts == n, "reverse_per_block_read_write_conflict");
+  }
+
+  // --- execution resources: split(Y) at 1 of 2 blocks (Sec. 3.1 example) ------
+  {
+    int fst = 0, snd = 0;
+    bool ok = true;
+    for (int y = 0; y < 2; ++y)
+      split(R<Level::Block>(y, 2), 1,
+            [&](auto h) { ++fst; ok &= h.count() == 1 && h.index() == 0 && !decltype(h)::whole; },
+            [&](auto h) { ++snd; ok &= h.count() == 1 && h.index() == 0; });
+    check(ok && fst == 1 && snd == 1, "split_Y_at_1_gives_two_single_block_groups");
+  }
+
+  // --- the kernels' own maps ----------------------------------------------------
+  {
+    // scan / segmented: wave-striped tiles of int32x4 groups and of scalars
+    const int W = 4, Rr = 8, tiles = 3, per = W * Rr * 64;
+    std::vector<int> groups(tiles * per);
+    Access g(tiles * per), e(tiles * per * 4);
+    bool contiguous = true;
+    for (int t = 0; t < tiles; ++t)
+      for (int w = 0; w < W; ++w)
+        for (int l = 0; l < 64; ++l) {
+          auto v = layout::wave_striped<W, Rr>(array(groups.data(), tiles * per), t,
+                                               R<Level::Wave>(w, W), R<Level::Thread>(l, 64));
+          std::vector<int> sc(tiles * per * 4);
+          auto s = layout::wave_striped<W, Rr>(array(sc.data(), tiles * per * 4).group<4>(), t,
+                                               R<Level::Wave>(w, W), R<Level::Thread>(l, 64));
+          for (int r = 0; r < Rr; ++r) {
+            const long idx = &v[r] - groups.data();
+            g.add(idx, (t * W + w) * 64 + l);
+            contiguous &= idx == (long)t * per + w * Rr * 64 + r * 64 + l;
+            for (int k = 0; k < 4; ++k) e.add(s.idx(r).pos(k), (t * W + w) * 64 + l);
+          }
+        }
+    check(g.bijection() && contiguous, "scan_wave_striped_groups_bijection_and_coalesced");
+    check(e.bijection(), "scan_wave_striped_elements_bijection");
+
+    // reduce: block-striped tiles
+    const int B = 256, U = 4, T2 = 5;
+    std::vector<int> v(T2 * U * B);
+    Access rb(T2 * U * B);
+    for (int t = 0; t < T2; ++t)
+      for (int x = 0; x < B; ++x) {
+        auto m = layout::block_striped<B, U>(array(v.data(), T2 * U * B), t,
+                                             R<Level::Thread>(x, B));
+        for (int u = 0; u < U; ++u) rb.add(&m[u] - v.data(), t * B + x);
+      }
+    check(rb.bijection(), "reduce_block_striped_bijection");
+  }
+
+  // transposition kernel: tiles T = 32, 64, 128 on a 2T x 3T matrix
+  auto transpose_case = [&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    constexpr int TX = T / 4, TY = 256 / TX, IT = T / TY;
+    const int rows = 2 * T, cols = 3 * T;
+    std::vector<unsigned> in(rows * cols), out(rows * cols, 0xffffffffu), lds(T * (T + 1));
+    for (int i = 0; i < rows * cols; ++i) in[i] = i;
+    Access rd(rows * cols), wr(rows * cols), lw(T * T);
+    for (int by = 0; by < rows / T; ++by)
+      for (int bx = 0; bx < cols / T; ++bx) {
+        auto bY = R<Level::Block>(by, rows / T), bX = R<Level::Block>(bx, cols / T);
+        auto tile = matrix(lds.data(), T, T + 1).fst<1>(T);
+        auto inm = matrix((u32x4*)in.data(), rows, cols / 4);
+        auto outm = matrix((u32x4*)out.data(), cols, rows / 4);
+        Access lw1(T * (T + 1));
+        for (int y = 0; y < TY; ++y)
+          for (int x = 0; x < TX; ++x) {
+            auto tY = R<Level::Thread>(y, TY), tX = R<Level::Thread>(x, TX);
+            auto a = layout::tile_rows<T, IT>(inm, bY, bX, tY, tX);
+            auto l = layout::lds_rows<T, IT>(tile, tY, tX);
+            for (int i = 0; i < IT; ++i)
+              for (int k = 0; k < 4; ++k) {
+                const unsigned* src = (const unsigned*)&a[i] + k;
+                rd.add(src - in.data(), (by * 8 + bx) * 256 + y * TX + x);
+                l.idx(i)[k] = *src;
+                lw1.add(&l.idx(i)[k] - lds.data(), y * TX + x);
+              }
+          }
+        lw.collisions += lw1.collisions;
+        for (int y = 0; y < TY; ++y)
+          for (int x = 0; x < TX; ++x) {
+            auto tY = R<Level::Thread>(y, TY), tX = R<Level::Thread>(x, TX);
+            auto b = layout::tile_rows<T, IT>(outm, bX, bY, tY, tX);
+            auto l = layout::lds_cols<T, IT>(tile, tY, tX);
+            for (int i = 0; i < IT; ++i)
+              for (int k = 0; k < 4; ++k) {
+                unsigned* dst = (unsigned*)&b[i] + k;
+                *dst = l.idx(i)[k];
+                wr.add(dst - out.data(), (by * 8 + bx) * 256 + y * TX + x);
+              }
+          }
+      }
+    bool is_t = true;
+    for (int r = 0; r < rows; ++r)
+      for (int c = 0; c < cols; ++c) is_t &= out[c * rows + r] == in[r * cols + c];
+    const std::string name = "transpose_kernel_maps_T" + std::to_string(T);
+    check(is_t && rd.bijection() && wr.bijection() && lw.collisions == 0, name.c_str());
+  };
+  transpose_case(std::integral_constant<int, 32>{});
+  transpose_case(std::integral_constant<int, 64>{});
+  transpose_case(std::integral_constant<int, 128>{});
+
+  return g_fail;
+}
