@@ -1,19 +1,27 @@
 """Benchmark of the hot path on one MI355X.
 
 A step is one pass over the HBM-bound workload: the inclusive int32 scan of
-2^28 elements (seed 2) followed by the out-of-place FP32 transpose of an
-8192 x 8192 matrix (seed 3).  Inputs are resident in HBM before timing
-starts.  `value` is the algorithmic bytes of a step (read + write of both
-operations: 8 * 2^28 + 8 * 8192^2 bytes) divided by the mean step time.
+2^28 elements (uniform in [-1024, 1024], seed 2) followed by the
+out-of-place FP32 transpose of an 8192 x 8192 matrix (N(0,1), seed 3).
+Inputs are resident in HBM before timing starts.  `value` is the
+algorithmic bytes of a step (read + write of both operations:
+8 * 2^28 + 8 * 8192^2 bytes) divided by the mean step time.
 
 The JSON line also carries:
   roofline      the scan kernel (the dominant one): algorithmic bytes per
                 launch over its mean launch time, taken with HIP events on
                 the stream the kernel runs on, against the 8 TB/s HBM peak;
   cpu_baseline  the plain CPU oracle on the same workload, on this host;
-  ops           per-operation figures measured in the same run.
+  ops           the other rows of the path measured in the same run: the
+                copy ceiling, the 2^22 reduction, the GEMM modes (TFLOP/s
+                and error against the FP64 oracle on sampled entries), the
+                segmented reduce/scan and the grouped GEMM.
+
+Small kernels are timed as HIP-graph replays of many back-to-back launches,
+so that host launch overhead does not enter their time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--ops LIST]
+  --ops: comma list of copy,reduce,gemm,gemm8192,segmented,grouped ('' for none)
 """
 from __future__ import annotations
 
@@ -27,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 METRIC = "GB/s & % HBM peak (reduce/scan/transpose); GEMM TFLOP/s BF16x3 vs FP32"
 
 SCAN_N = 1 << 28
@@ -35,9 +44,15 @@ SCAN_BYTES = 8 * SCAN_N                   # read n int32 + write n int32
 TRANSPOSE_BYTES = 8 * T_ROWS * T_COLS     # read + write rows*cols words
 STEP_BYTES = SCAN_BYTES + TRANSPOSE_BYTES
 
-# rocprofv3 summaries whose FETCH_SIZE / WRITE_SIZE give the scan's HBM
-# traffic per launch (null until counters for the current kernel are taken).
-SCAN_TRAFFIC_BYTES = None
+# HBM traffic of one scan launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# each scaled by what the counter reads for the copy kernel of known size
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for the kernel ScanCfg<256, 16, nt>
+# as it stands; to be reset to None when the kernel changes.
+SCAN_TRAFFIC_BYTES = 2_167_600_000
+
+
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def _load_library():
@@ -71,6 +86,36 @@ class Timer:
         return sum(s.elapsed_time(e) for s, e in self.pairs) / max(1, len(self.pairs))
 
 
+def graph_time_ms(torch, fn, reps: int = 50, warm: int = 3) -> float:
+    """Mean time of fn() from a HIP graph holding `reps` back-to-back calls."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def events_time_ms(torch, fn, reps: int = 10, warm: int = 2) -> float:
+    for _ in range(warm):
+        fn()
+    t = Timer(torch)
+    for _ in range(reps):
+        s = t.start(); fn(); t.stop(s)
+    return t.mean_ms()
+
+
 def cpu_baseline(x_np, m_np, budget_s: float = 20.0):
     """Time the oracle's scan and transpose on the same workload (1 thread)."""
     import oracle
@@ -92,32 +137,127 @@ def cpu_baseline(x_np, m_np, budget_s: float = 20.0):
         "unit": "GB/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"full workload (scan 2^28 + transpose 8192^2), {reps} rep(s), "
-                  f"single-thread C oracle; scan {t_scan / reps:.3f} s, "
+        "sample": f"the full step workload (scan 2^28 + transpose 8192^2), {reps} rep(s), "
+                  f"single-thread C oracle: scan {t_scan / reps:.3f} s, "
                   f"transpose {t_tr / reps:.3f} s per rep",
         "host_cpus": os.cpu_count(),
     }
 
 
-def bench_reduce(desc, torch, workloads, reps=50):
-    """Reduce of 2^22 int32 (seed 1): warm (L2/MALL-resident) and cold."""
-    x = torch.from_numpy(workloads.int_uniform(1 << 22, seed=1)).cuda()
+# ------------------------------------------------------------------ per-op measurements
+def op_copy(desc, torch):
+    n = 1 << 28
+    x = torch.empty(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    ms = events_time_ms(torch, lambda: desc.desc_copy_32(x, y))
+    return {"n_words": n, "us": round(ms * 1e3, 2), "GBs": round(8 * n / ms / 1e6, 1),
+            "frac": round(8 * n / ms / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def op_reduce(desc, torch, workloads):
+    """Reduction of 2^22 int32 (seed 1): L2/MALL-resident (warm) and after a
+    512 MiB write that evicts it (cold), both as graph replays."""
+    x_np = workloads.int_uniform(1 << 22, seed=1)
+    x = torch.from_numpy(x_np).cuda()
     out = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.zeros(desc.desc_reduce_i32_workspace(x.numel()), dtype=torch.uint8, device="cuda")
     flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
-    for _ in range(5):
-        desc.desc_reduce_i32(x, out)
-    warm = Timer(torch)
-    for _ in range(reps):
-        s = warm.start(); desc.desc_reduce_i32(x, out); warm.stop(s)
-    cold = Timer(torch)
-    for _ in range(reps):
-        flush.fill_(1)
-        s = cold.start(); desc.desc_reduce_i32(x, out); cold.stop(s)
+    warm = graph_time_ms(torch, lambda: desc.desc_reduce_i32(x, out, ws=ws), reps=100)
+    both = graph_time_ms(torch, lambda: (flush.fill_(1), desc.desc_reduce_i32(x, out, ws=ws)),
+                         reps=20)
+    fl = graph_time_ms(torch, lambda: flush.fill_(1), reps=20)
+    cold = max(both - fl, 1e-6)
+    torch.cuda.synchronize()
+    ok = int(out.item()) == int(x_np.sum(dtype="int64"))
     nbytes = 4 * (1 << 22) + 8
-    w, c = warm.mean_ms(), cold.mean_ms()
-    return {"n": 1 << 22, "bytes": nbytes,
-            "warm_us": round(w * 1e3, 2), "warm_GBs": round(nbytes / w / 1e6, 1),
-            "cold_us": round(c * 1e3, 2), "cold_GBs": round(nbytes / c / 1e6, 1)}
+    return {"n": 1 << 22, "bytes": nbytes, "check": ok,
+            "warm_us": round(warm * 1e3, 2), "warm_GBs": round(nbytes / warm / 1e6, 1),
+            "cold_us": round(cold * 1e3, 2), "cold_GBs": round(nbytes / cold / 1e6, 1)}
+
+
+def op_gemm(desc, torch, workloads, oracle, n, seeds, modes):
+    import numpy as np
+    A_np = workloads.matrix_f32(n, n, seed=seeds[0])
+    B_np = workloads.matrix_f32(n, n, seed=seeds[1])
+    ii, jj = workloads.sample_pairs(n, n, 4096, seed=seeds[2])
+    R, D = oracle.gemm_ref_sampled(A_np, B_np, ii, jj)
+    A = torch.from_numpy(A_np).cuda()
+    B = torch.from_numpy(B_np).cuda()
+    C = torch.empty(n, n, device="cuda")
+    out = {}
+    for mode in modes:
+        need = desc.desc_gemm_workspace(mode, n, n, n)
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        ms = events_time_ms(torch, lambda: desc.desc_gemm(A, B, C, mode=mode, ws=ws), reps=5)
+        Cs = C.cpu().numpy()[ii, jj].astype(np.float64)
+        comp = np.abs(Cs - R) / D
+        rel = np.abs(Cs - R) / np.maximum(np.abs(R), 1e-300)
+        tflops = 2 * n ** 3 / ms / 1e9
+        peak = PEAK_TFLOPS["f32" if mode == "f32" else ("bf16" if mode == "bf16x3" else "fp8")]
+        issued = 3 * tflops if mode == "bf16x3" else tflops
+        out[mode] = {"us": round(ms * 1e3, 1), "TFLOPs": round(tflops, 2),
+                     "peak_TFLOPs": peak, "mfma_frac": round(issued / peak, 4),
+                     "err_componentwise_max": float(f"{comp.max():.3e}"),
+                     "err_componentwise_mean": float(f"{comp.mean():.3e}"),
+                     "err_elementwise_max": float(f"{rel.max():.3e}"),
+                     "err_elementwise_median": float(f"{np.median(rel):.3e}"),
+                     "err_normwise": float(f"{np.abs(Cs - R).max() / np.abs(R).max():.3e}"),
+                     "within_1e-5": bool(comp.max() <= 1e-5)}
+    del A, B, C
+    torch.cuda.empty_cache()
+    return out
+
+
+def op_segmented(desc, torch, workloads):
+    import numpy as np
+    x_np, off_np = workloads.segmented_input()
+    T, S = int(off_np[-1]), off_np.size - 1
+    x = torch.from_numpy(x_np).cuda()
+    off = torch.from_numpy(off_np).cuda()
+    r = torch.empty(S, dtype=torch.int64, device="cuda")
+    y = torch.empty_like(x)
+    wr = torch.empty(desc.desc_reduce_segmented_i32_workspace(T, S), dtype=torch.uint8,
+                     device="cuda")
+    wy = torch.empty(desc.desc_scan_segmented_i32_workspace(T, S), dtype=torch.uint8,
+                     device="cuda")
+    red = graph_time_ms(torch, lambda: desc.desc_reduce_segmented_i32(x, off, r, ws=wr), reps=10)
+    scn = graph_time_ms(torch, lambda: desc.desc_scan_segmented_i32(x, off, y, ws=wy), reps=10)
+    torch.cuda.synchronize()
+    # spot check against the definition on a few segments
+    r_h = r.cpu().numpy()
+    ok = all(int(r_h[s]) == int(x_np[off_np[s]:off_np[s + 1]].sum(dtype=np.int64))
+             for s in (0, 1, S // 2, S - 1))
+    rb = 4 * T + 8 * (S + 1) + 8 * S
+    sb = 8 * T + 8 * (S + 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"segments": S, "elements": T, "check": ok,
+            "reduce_us": round(red * 1e3, 1), "reduce_GBs": round(rb / red / 1e6, 1),
+            "reduce_frac": round(rb / red / 1e6 / HBM_PEAK_GBS, 4),
+            "scan_us": round(scn * 1e3, 1), "scan_GBs": round(sb / scn / 1e6, 1),
+            "scan_frac": round(sb / scn / 1e6 / HBM_PEAK_GBS, 4)}
+
+
+def op_grouped(desc, torch, workloads):
+    shapes = workloads.grouped_shapes()
+    pairs = workloads.grouped_operands(shapes)
+    dev_pairs = []
+    flops = 0
+    roof_s = 0.0
+    for (A, B), (M, N, K) in zip(pairs, shapes):
+        M, N, K = int(M), int(N), int(K)
+        dev_pairs.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                          torch.empty(M, N, device="cuda")))
+        flops += 2 * M * N * K
+        roof_s += max(2 * M * N * K / (PEAK_TFLOPS["f32"] * 1e12),
+                      4 * (M * K + K * N + M * N) / (HBM_PEAK_GBS * 1e9))
+    d = desc.grouped_descriptors(dev_pairs, torch.device("cuda"))
+    ws = torch.empty(desc.desc_gemm_grouped_workspace(len(pairs)), dtype=torch.uint8,
+                     device="cuda")
+    ms = graph_time_ms(torch, lambda: desc.desc_gemm_grouped(d, ws=ws), reps=5)
+    return {"problems": len(pairs), "flop": flops, "us": round(ms * 1e3, 1),
+            "TFLOPs": round(flops / ms / 1e9, 2), "roofline_us": round(roof_s * 1e6, 1),
+            "roofline_frac": round(roof_s * 1e3 / ms, 4)}
 
 
 def main(argv=None):
@@ -126,7 +266,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ops", default="reduce", help="extra per-op measurements ('' for none)")
+    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped",
+                    help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -141,7 +282,7 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    print("bench: generating inputs", file=sys.stderr, flush=True)
+    log("generating inputs")
     x_np = workloads.int_uniform(SCAN_N, seed=2)
     m_np = workloads.matrix_f32(T_ROWS, T_COLS, seed=3)
     x = torch.from_numpy(x_np).to(dev)
@@ -163,7 +304,7 @@ def main(argv=None):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    log(f"timing {args.steps} steps")
 
     t_scan, t_tr = Timer(torch), Timer(torch)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -179,7 +320,7 @@ def main(argv=None):
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     scan_ms, tr_ms = t_scan.mean_ms(), t_tr.mean_ms()
 
-    # the last step's outputs, checked on a sample against the definition
+    # the last step's outputs, checked on samples against the definitions
     ok_scan = bool(int(y[-1].item()) == int(np.int64(x_np.sum(dtype=np.int64)).astype(np.int32)))
     ok_tr = bool(torch.equal(mt[:64, :64].cpu(), m[:64, :64].t().cpu()))
 
@@ -216,11 +357,32 @@ def main(argv=None):
                                    "frac": round(tr_gbs / HBM_PEAK_GBS, 4), "check": ok_tr}},
     }
     extra = [o for o in args.ops.split(",") if o]
+    if extra:
+        import oracle
+        del x, y, m, mt, ws
+        torch.cuda.empty_cache()
+    if "copy" in extra:
+        log("copy ceiling")
+        result["ops"]["copy_2^28"] = op_copy(desc, torch)
     if "reduce" in extra:
-        print("bench: reduce 2^22", file=sys.stderr, flush=True)
-        result["ops"]["reduce_2^22"] = bench_reduce(desc, torch, workloads)
+        log("reduce 2^22")
+        result["ops"]["reduce_2^22"] = op_reduce(desc, torch, workloads)
+    if "gemm" in extra:
+        log("gemm 4096^3")
+        result["ops"]["gemm_4096"] = op_gemm(desc, torch, workloads, oracle, 4096, (4, 5, 6),
+                                             ("f32", "bf16x3", "fp8"))
+    if "gemm8192" in extra:
+        log("gemm 8192^3")
+        result["ops"]["gemm_8192"] = op_gemm(desc, torch, workloads, oracle, 8192, (7, 8, 9),
+                                             ("f32", "bf16x3", "fp8"))
+    if "segmented" in extra:
+        log("segmented 4096 segments")
+        result["ops"]["segmented_4096"] = op_segmented(desc, torch, workloads)
+    if "grouped" in extra:
+        log("grouped gemm 512 problems")
+        result["ops"]["grouped_512"] = op_grouped(desc, torch, workloads)
     if not args.no_cpu:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        log("CPU oracle baseline")
         result["cpu_baseline"] = cpu_baseline(x_np, m_np)
     print(json.dumps(result), flush=True)
     return 0

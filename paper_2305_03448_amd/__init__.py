@@ -300,9 +300,12 @@ def _rows(t: torch.Tensor, name: str):
     """(rows, cols, row stride) of a 2-D float32 GPU tensor with unit column stride."""
     if t.device.type != "cuda" or t.dtype != torch.float32 or t.dim() != 2:
         raise ValueError(f"{name} must be a 2-D float32 GPU tensor")
-    if t.stride(1) != 1 and t.shape[1] > 1:
+    rows, cols = t.shape
+    if t.numel() == 0:
+        return rows, cols, max(cols, 1)
+    if cols > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride (row-major)")
-    return t.shape[0], t.shape[1], t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return rows, cols, t.stride(0) if rows > 1 else max(cols, 1)
 
 
 def desc_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, mode="f32",
