@@ -46,9 +46,9 @@ STEP_BYTES = SCAN_BYTES + TRANSPOSE_BYTES
 
 # HBM traffic of one scan launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by what the counter reads for the copy kernel of known size
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for the kernel ScanCfg<256, 16, nt>
-# as it stands; to be reset to None when the kernel changes.
-SCAN_TRAFFIC_BYTES = 2_167_600_000
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for the scan kernel as it stands;
+# None when the kernel has changed since the counters were taken.
+SCAN_TRAFFIC_BYTES = None
 
 
 def log(msg: str) -> None:

@@ -17,7 +17,7 @@
 // B as partial maxima over K slices; an LDS-tiled transpose of B that
 // encodes with the column scales and writes q^T as [Np][Kp].
 //
-// Padding: Mp, Np are multiples of 128 and Kp a multiple of 128 elements;
+// Padding: Mp, Np are multiples of 256 and Kp a multiple of 128 elements;
 // the pre-pass writes zeros there, so the GEMM main loop has no guards.
 #include "common.hpp"
 #include "gemm_nt.hpp"
@@ -31,7 +31,7 @@ namespace desc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int64_t kPadMN = 128, kPadK = 128;
+constexpr int64_t kPadMN = 256, kPadK = 128;
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -261,12 +261,14 @@ unsigned grid_for(int64_t items) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-constexpr const char* kNamesBf16[] = {"m128n128k32"};
-constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64"};
+constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32",
+                                      "m256n256k32"};
+constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
+                                     "m128n256k128", "m256n128k64"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 1, kNamesBf16, kDefaults),
-     tune::register_op(tune::kGemmFp8, "gemm_fp8", 2, kNamesFp8, kDefaults), true);
+    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 4, kNamesBf16, kDefaults),
+     tune::register_op(tune::kGemmFp8, "gemm_fp8", 5, kNamesFp8, kDefaults), true);
 
 }  // namespace
 
@@ -327,7 +329,12 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
   NtOperands p{{(const uint8_t*)ah, (const uint8_t*)al},
                {(const uint8_t*)bh, (const uint8_t*)bl},
                L.Kp * 2, Cm, ldc, M, N, nullptr, nullptr};
-  return launch_nt<NtCfg<128, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+  switch (tune::get(tune::kGemmBf16x3, tune::size_class(tune::kGemmBf16x3, M * N * K))) {
+    case 1: return launch_nt<NtCfg<256, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+    case 2: return launch_nt<NtCfg<128, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+    case 3: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+    default: return launch_nt<NtCfg<128, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+  }
 }
 
 hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
@@ -348,6 +355,9 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
   NtOperands p{{qa, nullptr}, {qb, nullptr}, L.Kp, Cm, ldc, M, N, sa, sb};
   switch (tune::get(tune::kGemmFp8, tune::size_class(tune::kGemmFp8, M * N * K))) {
     case 1: return launch_nt<NtCfg<128, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
+    case 2: return launch_nt<NtCfg<256, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
+    case 3: return launch_nt<NtCfg<128, 256, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
+    case 4: return launch_nt<NtCfg<256, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
   }
 }

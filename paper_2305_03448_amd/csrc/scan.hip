@@ -18,9 +18,11 @@
 //     then walks back over the predecessors' words, 256 per poll (four per
 //     lane), until it meets an inclusive prefix, and publishes the tile's own
 //     inclusive prefix; meanwhile the other waves scan their sub-tiles.
-//   * Tiles are large (8192 elements) so that the prefixes travel faster than
-//     the tiles are consumed: a poll takes about a microsecond across XCDs,
-//     and a tile must usually find a published prefix within one window.
+//   * Tiles are large (8192 to 65536 elements, picked per size class by the
+//     tuning table) so that the prefixes travel faster than the tiles are
+//     consumed: a poll costs a device-coherent round trip across XCDs, and
+//     with the look-back removed every shape streams at the copy ceiling, so
+//     the look-back is what the tile size has to amortise.
 //   * A status word holds {flag:2, generation tag:30, value:32} and is read
 //     and written with single 64-bit relaxed atomics, so no fence is needed
 //     to make the value visible to blocks on other XCDs.  Words whose tag is
@@ -256,9 +258,11 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hip
 }
 
 constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
-                                   "b1024_r4_nt", "b512_r4_nt"};
+                                   "b1024_r4_nt", "b512_r4_nt", "b256_r32_nt", "b512_r16_nt",
+                                   "b1024_r8_nt", "b512_r32_nt"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
-const bool kRegistered = (tune::register_op(tune::kScanI32, "scan_i32", 6, kNames, kDefaults), true);
+const bool kRegistered =
+    (tune::register_op(tune::kScanI32, "scan_i32", 10, kNames, kDefaults), true);
 
 }  // namespace
 
@@ -278,6 +282,10 @@ hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStr
     case 3: return launch_scan<ScanCfg<256, 16, true>>(in, out, n, ws, s);
     case 4: return launch_scan<ScanCfg<1024, 4, true>>(in, out, n, ws, s);
     case 5: return launch_scan<ScanCfg<512, 4, true>>(in, out, n, ws, s);
+    case 6: return launch_scan<ScanCfg<256, 32, true>>(in, out, n, ws, s);
+    case 7: return launch_scan<ScanCfg<512, 16, true>>(in, out, n, ws, s);
+    case 8: return launch_scan<ScanCfg<1024, 8, true>>(in, out, n, ws, s);
+    case 9: return launch_scan<ScanCfg<512, 32, true>>(in, out, n, ws, s);
     default: return launch_scan<ScanCfg<256, 8, true>>(in, out, n, ws, s);
   }
 }

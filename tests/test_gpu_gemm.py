@@ -231,3 +231,25 @@ def test_fp8_against_its_own_codes(M, N, K):
     R, D = oracle.gemm_ref_sampled(A, B, ii, jj)
     e = np.abs(C[ii, jj] - R) / D
     print(f"[result] fp8 {M}x{N}x{K} vs exact product: max {e.max():.3e} mean {e.mean():.3e}")
+
+
+@pytest.mark.parametrize("op,mode", [("gemm_bf16x3", "bf16x3"), ("gemm_fp8", "fp8")])
+def test_lowp_every_config(op, mode):
+    M, N, K = 300, 520, 384
+    if mode == "bf16x3":
+        A = _int_matrix(M, K, 13); B = _int_matrix(K, N, 14)
+    else:
+        g = workloads.rng(15)
+        A = g.integers(-8, 9, (M, K)).astype(np.float32)
+        B = g.integers(-8, 9, (K, N)).astype(np.float32)
+        A[:, 0] = 448.0; B[0, :] = 0.0
+        A[:, 1] = 0.0; B[1, :] = 448.0
+    exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+    cls = desc.desc_size_class(op, M * N * K)
+    try:
+        for cfg in range(desc.desc_config_count(op)):
+            case(f"{op} config {desc.desc_config_name(op, cfg)}")
+            desc.desc_config_set(op, cls, cfg)
+            assert np.array_equal(_run(A, B, mode), exact), desc.desc_config_name(op, cfg)
+    finally:
+        desc.desc_config_set(op, cls, -1)
