@@ -157,16 +157,27 @@ __device__ __forceinline__ void tile(const GemmProblemF32& p, idx_t tm, idx_t tn
   }
 
   auto c_g = matrix(p.C, p.M, p.ldc);
+  if (m0 + BM <= p.M && n0 + BN <= p.N) {       // whole tile inside C: no guards
 #pragma unroll
-  for (int i = 0; i < C::fm; ++i)
+    for (int i = 0; i < C::fm; ++i)
 #pragma unroll
-    for (int j = 0; j < C::fn; ++j)
+      for (int j = 0; j < C::fn; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
-        const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
-        if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
-      }
+        for (int r = 0; r < 16; ++r)
+          c_g.at(m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane),
+                 n0 + wn * C::wtn + j * 32 + col32) = acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+          const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+          if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
+        }
+  }
 }
 
 }  // namespace gemm_f32

@@ -3,9 +3,11 @@
 // Both operands arrive K-contiguous ("NT"): A as [Mp][Kp] and B transposed as
 // [Np][Kp], padded with zeros to whole tiles by the operand pre-pass, so the
 // main loop needs no guards.  Rows are byte strings here: a stage copies BKB
-// bytes of K per row of each operand plane into LDS (row pitch BKB + 16
-// bytes, which spreads the 16-byte fragment reads of 16 consecutive rows
-// over all banks), double buffered, one barrier per stage.
+// bytes of K per row of each operand plane into LDS as 16-byte chunks,
+// double buffered, one barrier per stage.  The LDS rows are unpadded and the
+// chunk index is XOR-swizzled with the row (xor_swizzle), so both the
+// coalesced staging writes (consecutive lanes along a row) and the fragment
+// reads (one chunk of 16 consecutive rows) hit distinct banks.
 //
 // Modes:
 //   Bf16x3 -- planes {hi, lo}; per 16-wide K step three 32x32x16 bf16
@@ -51,7 +53,9 @@ struct NtCfg {
   static constexpr int bm = kBM, bn = kBN, bkb = kBKB;
   static constexpr int wtm = kBM / 2, wtn = kBN / 2;
   static constexpr int fm = wtm / 32, fn = wtn / 32;
-  static constexpr int pitch = kBKB + 16;
+  static constexpr int chunks = kBKB / 16;                 // 16-byte chunks per row
+  static constexpr int rows_per_256 = 256 / kBKB;          // rows sharing one bank period
+  static constexpr int pitch = kBKB;
   static constexpr int steps = kBKB / Mode::step_bytes;
   static constexpr int a_chunks = kBM * kBKB / 16 / 256;   // 16-byte chunks per thread per plane
   static constexpr int b_chunks = kBN * kBKB / 16 / 256;
@@ -95,10 +99,16 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
   const int wm = (int)wv.index() / 2, wn = (int)wv.index() % 2;
   const idx_t m0 = tm * C::bm, n0 = tn * C::bn;
 
-  // LDS: [stage][plane][A rows then B rows][pitch] bytes
-  auto sm = matrices(lds, 2 * P, C::bm + C::bn, C::pitch);
+  // LDS: [stage][plane][A rows then B rows][chunks] of 16 bytes, swizzled
+  auto sm = matrices((u32x4*)lds, 2 * P, C::bm + C::bn, C::chunks);
+  auto plane = [&](int stage, int pl) {
+    return sm.idx(stage * P + pl).template xor_swizzle<C::rows_per_256, C::chunks>();
+  };
 
   u32x4 ra[P][C::a_chunks], rb[P][C::b_chunks];
+  // 16-byte chunk q of a stage (q = thread + 256 i) is chunk q % CPR of row
+  // q / CPR: consecutive lanes read consecutive bytes of a row.
+  constexpr int CPR = C::chunks;
   auto load = [&](idx_t k0b) {
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
@@ -107,28 +117,28 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        ra[pl][i] = *(const u32x4*)&ag.at(m0 + q / (BKB / 16), k0b + 16 * (q % (BKB / 16)));
+        ra[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        rb[pl][i] = *(const u32x4*)&bg.at(n0 + q / (BKB / 16), k0b + 16 * (q % (BKB / 16)));
+        rb[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
       }
     }
   };
   auto store = [&](int stage) {
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
-      auto s = sm.idx(stage * P + pl);
+      auto s = plane(stage, pl);
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        *(u32x4*)&s.at(q / (BKB / 16), 16 * (q % (BKB / 16))) = ra[pl][i];
+        s.at(q / CPR, q % CPR) = ra[pl][i];
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        *(u32x4*)&s.at(C::bm + q / (BKB / 16), 16 * (q % (BKB / 16))) = rb[pl][i];
+        s.at(C::bm + q / CPR, q % CPR) = rb[pl][i];
       }
     }
   };
@@ -141,31 +151,27 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const idx_t nk = p.row_bytes / BKB;
-  load(0);
-  store(0);
-  sync(thread);
-  for (idx_t kt = 0; kt < nk; ++kt) {
-    const int stage = (int)(kt & 1);
-    if (kt + 1 < nk) load((kt + 1) * BKB);
+  // Matrix ops of one stage from LDS buffer `stage`.
+  auto compute = [&](int stage) {
 #pragma unroll
     for (int st = 0; st < C::steps; ++st) {
-      const int off = st * Mode::step_bytes + half * LB;
+      // this lane's chunk(s) of the step: LB bytes from byte st*step + half*LB
+      const int ch = (st * Mode::step_bytes + half * LB) / 16;
       gemm_nt::Frag<LB> fa[P][C::fm], fb[P][C::fn];
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) {
-        auto s = sm.idx(stage * P + pl);
+        auto s = plane(stage, pl);
 #pragma unroll
         for (int i = 0; i < C::fm; ++i) {
-          const u32x4* src = (const u32x4*)&s.at(wm * C::wtm + i * 32 + col32, off);
-          if constexpr (LB == 16) fa[pl][i].v = src[0];
-          else { fa[pl][i].v0 = src[0]; fa[pl][i].v1 = src[1]; }
+          const idx_t row = wm * C::wtm + i * 32 + col32;
+          if constexpr (LB == 16) fa[pl][i].v = s.at(row, ch);
+          else { fa[pl][i].v0 = s.at(row, ch); fa[pl][i].v1 = s.at(row, ch + 1); }
         }
 #pragma unroll
         for (int j = 0; j < C::fn; ++j) {
-          const u32x4* src = (const u32x4*)&s.at(C::bm + wn * C::wtn + j * 32 + col32, off);
-          if constexpr (LB == 16) fb[pl][j].v = src[0];
-          else { fb[pl][j].v0 = src[0]; fb[pl][j].v1 = src[1]; }
+          const idx_t row = C::bm + wn * C::wtn + j * 32 + col32;
+          if constexpr (LB == 16) fb[pl][j].v = s.at(row, ch);
+          else { fb[pl][j].v0 = s.at(row, ch); fb[pl][j].v1 = s.at(row, ch + 1); }
         }
       }
 #pragma unroll
@@ -181,26 +187,68 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
           }
         }
     }
-    if (kt + 1 < nk) store(stage ^ 1);
+  };
+
+  // Steady state: every iteration loads stage kt+1 into registers, computes
+  // stage kt from LDS and writes stage kt+1 to the other buffer, with no
+  // branch inside, so the scheduler can interleave the global loads and LDS
+  // writes with the matrix ops.  The last stage is peeled off.
+  const idx_t nk = p.row_bytes / BKB;
+  load(0);
+  store(0);
+  sync(thread);
+  for (idx_t kt = 0; kt + 1 < nk; ++kt) {
+    const int stage = (int)(kt & 1);
+    load((kt + 1) * BKB);
+    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the matrix ops
+    compute(stage);
+    __builtin_amdgcn_sched_barrier(0);
+    store(stage ^ 1);
     sync(thread);
   }
+  compute((int)((nk - 1) & 1));
 
+  // Epilogue.  The scales are padded to whole tiles, so all of this lane's
+  // scale loads are issued together, before any store; a tile wholly inside
+  // C stores without guards.
   auto c_g = matrix(p.C, p.M, p.ldc);
+  float sav[C::fm][16], sbv[C::fn];
+  if constexpr (Mode::scaled) {
+    auto sa = array(p.sa, 0);
+    auto sb = array(p.sb, 0);
 #pragma unroll
-  for (int i = 0; i < C::fm; ++i)
+    for (int i = 0; i < C::fm; ++i)
 #pragma unroll
-    for (int j = 0; j < C::fn; ++j) {
-      const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
-      float sbj = 1.f;
-      if constexpr (Mode::scaled) sbj = array(p.sb, 0)[col];
+      for (int r = 0; r < 16; ++r) sav[i][r] = sa[m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane)];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
-        float v = acc[i][j][r];
-        if constexpr (Mode::scaled) v = (v * array(p.sa, 0)[row]) * sbj;
-        if (row < p.M && col < p.N) c_g.at(row, col) = v;
-      }
-    }
+    for (int j = 0; j < C::fn; ++j) sbv[j] = sb[n0 + wn * C::wtn + j * 32 + col32];
+  }
+  auto value = [&](int i, int j, int r) {
+    float v = acc[i][j][r];
+    if constexpr (Mode::scaled) v = (v * sav[i][r]) * sbv[j];
+    return v;
+  };
+  if (m0 + C::bm <= p.M && n0 + C::bn <= p.N) {
+#pragma unroll
+    for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          c_g.at(m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane),
+                 n0 + wn * C::wtn + j * 32 + col32) = value(i, j, r);
+  } else {
+#pragma unroll
+    for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+          const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+          if (row < p.M && col < p.N) c_g.at(row, col) = value(i, j, r);
+        }
+  }
 }
 
 }  // namespace gemm_nt

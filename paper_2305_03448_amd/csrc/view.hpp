@@ -131,6 +131,23 @@ struct SplitMap {
   }
 };
 
+// xor_swizzle at depth D: in a [rows][chunks] pair of dimensions, chunk c of
+// row r is stored at chunk c ^ ((r / kDiv) % kMod) of that row -- a
+// permutation within every row, so the view is a bijection onto the same
+// storage.  Used to spread the LDS accesses of consecutive rows over banks.
+template <class P, int D, idx_t kDiv, idx_t kMod>
+struct XorMap {
+  static constexpr int rank = P::rank;
+  static_assert(D + 1 < P::rank, "xor_swizzle needs two dimensions");
+  P p;
+  DESC_HD idx_t ext(int d) const { return p.ext(d); }
+  DESC_HD Idx<rank> to_parent(const Idx<rank>& i) const {
+    Idx<rank> j = i;
+    j[D + 1] = i[D + 1] ^ ((i[D] / kDiv) % kMod);
+    return j;
+  }
+};
+
 // select: dimension 0 is fixed to one index (the selecting resource's).
 template <class P>
 struct SelectMap {
@@ -275,6 +292,8 @@ struct View {
   DESC_HD View<T, TransposeMap<M, D>> transpose() const { return {base, {m}}; }
   template <int D = 0>
   DESC_HD View<T, ReverseMap<M, D>> reverse() const { return {base, {m}}; }
+  template <idx_t kDiv, idx_t kMod, int D = 0>
+  DESC_HD View<T, XorMap<M, D, kDiv, kMod>> xor_swizzle() const { return {base, {m}}; }
   template <int D = 0>
   DESC_HD View<T, SplitMap<M, D>> fst(idx_t pos) const { return {base, {m, pos, false}}; }
   template <int D = 0>

@@ -241,6 +241,36 @@ int main(int argc, char** argv) {
     check(rb.bijection(), "reduce_block_striped_bijection");
   }
 
+  // low-precision GEMM LDS stage: [rows][chunks] of 16 bytes, XOR-swizzled;
+  // a bijection per row, and both access patterns of 16 lanes (the staging
+  // writes along a row, the fragment reads down 16 rows) hit 16 distinct
+  // 16-byte bank groups of a 256-byte bank period.
+  auto swizzle_case = [&](auto Bc) {
+    constexpr int BKB = decltype(Bc)::value, CPR = BKB / 16, RPB = 256 / BKB;
+    const int rows = 64;
+    std::vector<u32x4> lds(rows * CPR);
+    auto v = matrix(lds.data(), rows, CPR).xor_swizzle<RPB, CPR>();
+    Access all(rows * CPR);
+    for (int r = 0; r < rows; ++r)
+      for (int c = 0; c < CPR; ++c) all.add(&v.at(r, c) - lds.data(), r * CPR + c);
+    bool reads_ok = true, writes_ok = true;
+    for (int r0 = 0; r0 < rows; r0 += 16)
+      for (int c = 0; c < CPR; ++c) {
+        std::set<long> g;
+        for (int r = r0; r < r0 + 16; ++r) g.insert((&v.at(r, c) - lds.data()) % 16);
+        reads_ok &= g.size() == 16;
+      }
+    for (int q0 = 0; q0 < rows * CPR; q0 += 16) {
+      std::set<long> g;
+      for (int q = q0; q < q0 + 16; ++q) g.insert((&v.at(q / CPR, q % CPR) - lds.data()) % 16);
+      writes_ok &= g.size() == 16;
+    }
+    const std::string name = "gemm_lds_xor_swizzle_bkb" + std::to_string(BKB);
+    check(all.bijection() && reads_ok && writes_ok, name.c_str());
+  };
+  swizzle_case(std::integral_constant<int, 64>{});
+  swizzle_case(std::integral_constant<int, 128>{});
+
   // transposition kernel: tiles T = 32, 64, 128 on a 2T x 3T matrix
   auto transpose_case = [&](auto Tc) {
     constexpr int T = decltype(Tc)::value;
