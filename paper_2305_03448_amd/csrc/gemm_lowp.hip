@@ -262,7 +262,7 @@ unsigned grid_for(int64_t items) {
 }
 
 constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32",
-                                      "m256n256k32"};
+                                      "m256n256k32_d1"};
 constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
                                      "m128n256k128", "m256n128k64"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
@@ -332,7 +332,7 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
   switch (tune::get(tune::kGemmBf16x3, tune::size_class(tune::kGemmBf16x3, M * N * K))) {
     case 1: return launch_nt<NtCfg<256, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
     case 2: return launch_nt<NtCfg<128, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
-    case 3: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
+    case 3: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
   }
 }

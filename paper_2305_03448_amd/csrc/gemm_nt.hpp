@@ -47,10 +47,13 @@ struct Fp8Mode {
   static constexpr bool scaled = true;
 };
 
-template <int kBM, int kBN, int kBKB, class Mode>
+// kDepth: stages in flight in registers (1: the next stage's loads are
+// issued before the current stage's matrix ops; 2: two stages ahead, which
+// needs a second register staging set).
+template <int kBM, int kBN, int kBKB, class Mode, int kDepth = 2>
 struct NtCfg {
   using mode = Mode;
-  static constexpr int bm = kBM, bn = kBN, bkb = kBKB;
+  static constexpr int bm = kBM, bn = kBN, bkb = kBKB, depth = kDepth;
   static constexpr int wtm = kBM / 2, wtn = kBN / 2;
   static constexpr int fm = wtm / 32, fn = wtn / 32;
   static constexpr int chunks = kBKB / 16;                 // 16-byte chunks per row
@@ -105,11 +108,15 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     return sm.idx(stage * P + pl).template xor_swizzle<C::rows_per_256, C::chunks>();
   };
 
-  u32x4 ra[P][C::a_chunks], rb[P][C::b_chunks];
+  // Two register staging sets: stage j travels through set j % 2.
+  struct Stage {
+    u32x4 a[P][C::a_chunks], b[P][C::b_chunks];
+  };
+  Stage R0, R1;
   // 16-byte chunk q of a stage (q = thread + 256 i) is chunk q % CPR of row
   // q / CPR: consecutive lanes read consecutive bytes of a row.
   constexpr int CPR = C::chunks;
-  auto load = [&](idx_t k0b) {
+  auto load = [&](idx_t k0b, Stage& R) {
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
       auto ag = matrix(p.a[pl], 0, p.row_bytes);
@@ -117,28 +124,28 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        ra[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
+        R.a[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        rb[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
+        R.b[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
       }
     }
   };
-  auto store = [&](int stage) {
+  auto store = [&](const Stage& R, int stage) {
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
       auto s = plane(stage, pl);
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        s.at(q / CPR, q % CPR) = ra[pl][i];
+        s.at(q / CPR, q % CPR) = R.a[pl][i];
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
         const int q = (int)thread.index() + 256 * i;
-        s.at(C::bm + q / CPR, q % CPR) = rb[pl][i];
+        s.at(C::bm + q / CPR, q % CPR) = R.b[pl][i];
       }
     }
   };
@@ -189,24 +196,59 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     }
   };
 
-  // Steady state: every iteration loads stage kt+1 into registers, computes
-  // stage kt from LDS and writes stage kt+1 to the other buffer, with no
-  // branch inside, so the scheduler can interleave the global loads and LDS
-  // writes with the matrix ops.  The last stage is peeled off.
   const idx_t nk = p.row_bytes / BKB;
-  load(0);
-  store(0);
-  sync(thread);
-  for (idx_t kt = 0; kt + 1 < nk; ++kt) {
-    const int stage = (int)(kt & 1);
-    load((kt + 1) * BKB);
-    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the matrix ops
-    compute(stage);
-    __builtin_amdgcn_sched_barrier(0);
-    store(stage ^ 1);
+  if constexpr (C::depth == 1) {
+    // One stage ahead: iteration kt loads stage kt+1 into registers, computes
+    // stage kt from LDS and writes stage kt+1 to the other buffer; the last
+    // stage is peeled so the loop body has no branch.
+    load(0, R0);
+    store(R0, 0);
     sync(thread);
+    for (idx_t kt = 0; kt + 1 < nk; ++kt) {
+      const int stage = (int)(kt & 1);
+      load((kt + 1) * BKB, R0);
+      __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the matrix ops
+      compute(stage);
+      __builtin_amdgcn_sched_barrier(0);
+      store(R0, stage ^ 1);
+      sync(thread);
+    }
+    compute((int)((nk - 1) & 1));
+  } else {
+    // Two stages deep: at the start of iteration kt, LDS buffer kt % 2 holds
+    // stage kt and register set (kt+1) % 2 holds stage kt+1 (its loads issued
+    // one iteration earlier).  Iteration kt issues the loads of stage kt+2,
+    // computes stage kt, writes stage kt+1 to the other LDS buffer and
+    // synchronises, so a global load has two stages of matrix ops to arrive.
+    // The steady state runs in pairs of iterations (register sets named
+    // statically) without branches; the last iterations are peeled.
+    load(0, R0);
+    store(R0, 0);
+    if (nk > 1) load(BKB, R1);
+    sync(thread);
+    idx_t kt = 0;
+    for (; kt + 3 < nk; kt += 2) {
+      load((kt + 2) * BKB, R0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      store(R1, 1);
+      sync(thread);
+      load((kt + 3) * BKB, R1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      store(R0, 0);
+      sync(thread);
+    }
+    for (; kt < nk; ++kt) {            // at most three iterations left
+      const bool even = (kt & 1) == 0;
+      if (kt + 2 < nk) load((kt + 2) * BKB, even ? R0 : R1);
+      compute((int)(kt & 1));
+      if (kt + 1 < nk) store(even ? R1 : R0, (int)((kt + 1) & 1));
+      sync(thread);
+    }
   }
-  compute((int)((nk - 1) & 1));
 
   // Epilogue.  The scales are padded to whole tiles, so all of this lane's
   // scale loads are issued together, before any store; a tile wholly inside

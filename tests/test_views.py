@@ -22,7 +22,7 @@ EXPECTED = [
     "reverse_per_block_read_write_conflict", "split_Y_at_1_gives_two_single_block_groups",
     "scan_wave_striped_groups_bijection_and_coalesced", "scan_wave_striped_elements_bijection",
     "reduce_block_striped_bijection", "transpose_kernel_maps_T32", "transpose_kernel_maps_T64",
-    "transpose_kernel_maps_T128", "gemm_lds_xor_swizzle_bkb64", "gemm_lds_xor_swizzle_bkb128",
+    "transpose_kernel_maps_T128", "gemm_lds_xor_swizzle_bkb32", "gemm_lds_xor_swizzle_bkb64", "gemm_lds_xor_swizzle_bkb128",
 ]
 
 

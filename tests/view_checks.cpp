@@ -268,6 +268,7 @@ int main(int argc, char** argv) {
     const std::string name = "gemm_lds_xor_swizzle_bkb" + std::to_string(BKB);
     check(all.bijection() && reads_ok && writes_ok, name.c_str());
   };
+  swizzle_case(std::integral_constant<int, 32>{});
   swizzle_case(std::integral_constant<int, 64>{});
   swizzle_case(std::integral_constant<int, 128>{});
 
