@@ -37,14 +37,21 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ split
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef uint8_t u8x4 __attribute__((ext_vector_type(4)));
+
 // Rows of A (M x K, stride lda) -> hi, lo (rows_out x k_out, stride ldh);
-// positions beyond M or K are written as zero.  Thread = 4 consecutive k.
+// positions beyond M or K are written as zero.  Thread = 4 consecutive k:
+// one 16-byte load and two 8-byte stores when the group is whole and
+// aligned (vec_in: A and lda allow float4; vec_out: hi, lo and ldh allow
+// 8-byte stores), element by element otherwise.
 __global__ __launch_bounds__(kBlock) void split_rows_kernel(const float* __restrict__ A,
                                                             int64_t M, int64_t K, int64_t lda,
                                                             uint16_t* __restrict__ hi,
                                                             uint16_t* __restrict__ lo,
                                                             int64_t rows_out, int64_t k_out,
-                                                            int64_t ldh) {
+                                                            int64_t ldh, bool vec_in,
+                                                            bool vec_out) {
   auto block = block_x();
   auto thread = thread_x<kBlock>();
   auto a = matrix(A, M, lda);
@@ -55,25 +62,45 @@ __global__ __launch_bounds__(kBlock) void split_rows_kernel(const float* __restr
   for (idx_t g = block.index() * kBlock + thread.index(); g < total;
        g += block.count() * kBlock) {
     const idx_t r = g / groups, c = 4 * (g % groups);
+    f32x4 v;
+    if (vec_in && r < M && c + 4 <= K) {
+      v = *(const f32x4*)&a.at(r, c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (r < M && c + j < K) ? a.at(r, c + j) : 0.f;
+    }
+    u16x4 vh, vl;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      if (c + j >= k_out) break;
-      const float v = (r < M && c + j < K) ? a.at(r, c + j) : 0.f;
-      const lowp::Split s = lowp::split_bf16(v);
-      h.at(r, c + j) = s.hi;
-      l.at(r, c + j) = s.lo;
+      const lowp::Split sp = lowp::split_bf16(v[j]);
+      vh[j] = sp.hi;
+      vl[j] = sp.lo;
+    }
+    if (vec_out && c + 4 <= k_out) {
+      *(u16x4*)&h.at(r, c) = vh;
+      *(u16x4*)&l.at(r, c) = vl;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c + j < k_out) {
+          h.at(r, c + j) = vh[j];
+          l.at(r, c + j) = vl[j];
+        }
     }
   }
 }
 
 // Columns of B (K x N, stride ldb) -> hi^T, lo^T (n_out x k_out, stride ldh).
-// 64 x 64 tiles of B through LDS; grid (k tiles, n tiles).
+// 64 x 64 tiles of B through LDS; grid (k tiles, n tiles).  Reads run along
+// n (thread = 4 columns of one row), writes along k (thread = 4 consecutive
+// k of one output row, two 8-byte stores).
 __global__ __launch_bounds__(kBlock) void split_cols_t_kernel(const float* __restrict__ B,
                                                               int64_t K, int64_t N, int64_t ldb,
                                                               uint16_t* __restrict__ hi,
                                                               uint16_t* __restrict__ lo,
                                                               int64_t n_out, int64_t k_out,
-                                                              int64_t ldh) {
+                                                              int64_t ldh, bool vec_in,
+                                                              bool vec_out) {
   __shared__ float lds[64 * 65];
   auto kt = block_x();
   auto nt = block_y();
@@ -83,17 +110,43 @@ __global__ __launch_bounds__(kBlock) void split_cols_t_kernel(const float* __res
   auto h = matrix(hi, n_out, ldh);
   auto l = matrix(lo, n_out, ldh);
   const idx_t k0 = kt.index() * 64, n0 = nt.index() * 64;
-  for (idx_t e = thread.index(); e < 64 * 64; e += kBlock) {   // read along n
-    const idx_t r = e / 64, c = e % 64;
-    tile.at(r, c) = (k0 + r < K && n0 + c < N) ? b.at(k0 + r, n0 + c) : 0.f;
+  const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
+    const idx_t r = ty + 16 * i, c = 4 * tx;
+    f32x4 v;
+    if (vec_in && k0 + r < K && n0 + c + 4 <= N) {
+      v = *(const f32x4*)&b.at(k0 + r, n0 + c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[j] = (k0 + r < K && n0 + c + j < N) ? b.at(k0 + r, n0 + c + j) : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) tile.at(r, c + j) = v[j];
   }
   sync(thread);
-  for (idx_t e = thread.index(); e < 64 * 64; e += kBlock) {   // write along k
-    const idx_t c = e / 64, r = e % 64;
-    if (n0 + c < n_out && k0 + r < k_out) {
-      const lowp::Split s = lowp::split_bf16(tile.at(r, c));
-      h.at(n0 + c, k0 + r) = s.hi;
-      l.at(n0 + c, k0 + r) = s.lo;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {                 // output rows (columns of B) ty + 16 i
+    const idx_t c = ty + 16 * i, r = 4 * tx;
+    if (n0 + c >= n_out) continue;
+    u16x4 vh, vl;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const lowp::Split sp = lowp::split_bf16(tile.at(r + j, c));
+      vh[j] = sp.hi;
+      vl[j] = sp.lo;
+    }
+    if (vec_out && k0 + r + 4 <= k_out) {
+      *(u16x4*)&h.at(n0 + c, k0 + r) = vh;
+      *(u16x4*)&l.at(n0 + c, k0 + r) = vl;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + r + j < k_out) {
+          h.at(n0 + c, k0 + r + j) = vh[j];
+          l.at(n0 + c, k0 + r + j) = vl[j];
+        }
     }
   }
 }
@@ -112,26 +165,52 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   return m;
 }
 
-// One block per output row: absmax over the row, then encode.
+// One block per output row: absmax over the row, then encode, 4 consecutive
+// k per thread (16-byte loads and 4-byte stores when whole and aligned).
 // q is rows_out x k_out (stride ldq); rows >= M and columns >= K get zero.
 __global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restrict__ A,
                                                             int64_t M, int64_t K, int64_t lda,
                                                             uint8_t* __restrict__ q,
                                                             int64_t k_out, int64_t ldq,
-                                                            float* __restrict__ scale) {
+                                                            float* __restrict__ scale,
+                                                            bool vec_in, bool vec_out) {
   __shared__ float red[kBlock / kWave];
   auto row = block_x();
   auto thread = thread_x<kBlock>();
   const idx_t r = row.index();
   auto a = matrix(A, M, lda);
   auto qr = matrix(q, row.count(), ldq).idx(r);
+  auto load4 = [&](idx_t c) {
+    f32x4 v;
+    if (vec_in && r < M && c + 4 <= K) {
+      v = *(const f32x4*)&a.at(r, c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (r < M && c + j < K) ? a.at(r, c + j) : 0.f;
+    }
+    return v;
+  };
   float amax = 0.f;
-  if (r < M)
-    for (idx_t k = thread.index(); k < K; k += kBlock) amax = fmaxf(amax, fabsf(a.at(r, k)));
+  for (idx_t c = 4 * thread.index(); c < K; c += 4 * kBlock) {
+    const f32x4 v = load4(c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fabsf(v[j]));
+  }
   amax = block_max(amax, red);
   const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
-  for (idx_t k = thread.index(); k < k_out; k += kBlock)
-    qr[k] = (r < M && k < K) ? lowp::e4m3_rne_sat(a.at(r, k) * inv) : (uint8_t)0;
+  for (idx_t c = 4 * thread.index(); c < k_out; c += 4 * kBlock) {
+    const f32x4 v = load4(c);
+    u8x4 e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] = (r < M && c + j < K) ? lowp::e4m3_rne_sat(v[j] * inv) : 0;
+    if (vec_out && c + 4 <= k_out) {
+      *(u8x4*)&qr[c] = e;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c + j < k_out) qr[c + j] = e[j];
+    }
+  }
   if (thread.index() == 0) array(scale, row.count())[r] = amax / 448.0f;
 }
 
@@ -157,7 +236,9 @@ __global__ __launch_bounds__(kBlock) void colmax_partial_kernel(const float* __r
 
 // Encode 64 x 64 tiles of B with their column scales and write them
 // transposed: qt is n_out x k_out (stride ldq).  The first k tile of each
-// column block also writes the column scales.
+// column block also writes the column scales.  Reads run along n (thread =
+// 4 columns of one row), writes along k (thread = 4 consecutive k, one
+// 4-byte store).
 __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __restrict__ B,
                                                               int64_t K, int64_t N, int64_t ldb,
                                                               const float* __restrict__ part,
@@ -165,9 +246,11 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
                                                               uint8_t* __restrict__ qt,
                                                               int64_t n_out, int64_t k_out,
                                                               int64_t ldq,
-                                                              float* __restrict__ scale) {
+                                                              float* __restrict__ scale,
+                                                              bool vec_in, bool vec_out) {
   __shared__ uint8_t codes[64 * 68];
   __shared__ float inv_s[64];
+  __shared__ float pmax[4][64];
   auto kt = block_x();
   auto nt = block_y();
   auto thread = thread_x<kBlock>();
@@ -176,25 +259,60 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
   auto pm = matrix(part, nslices, ldp);
   auto out = matrix(qt, n_out, ldq);
   const idx_t k0 = kt.index() * 64, n0 = nt.index() * 64;
-  if (thread.index() < 64) {
-    const idx_t n = n0 + thread.index();
+  {
+    // column maxima of the 64 columns from the slice partials: thread
+    // (g, c) takes slices g, g + 4, ... of column c (loads coalesced along
+    // the columns, independent, so they are in flight together)
+    const int c = (int)thread.index() % 64, g = (int)thread.index() / 64;
+    const idx_t n = n0 + c;
     float m = 0.f;
     if (n < N)
-      for (idx_t s = 0; s < nslices; ++s) m = fmaxf(m, pm.at(s, n));
-    inv_s[thread.index()] = m > 0.f ? 448.0f / m : 1.0f;
+#pragma unroll 8
+      for (idx_t sl = g; sl < nslices; sl += 4) m = fmaxf(m, pm.at(sl, n));
+    pmax[g][c] = m;
+  }
+  sync(thread);
+  if (thread.index() < 64) {
+    const int c = (int)thread.index();
+    const idx_t n = n0 + c;
+    const float m = fmaxf(fmaxf(pmax[0][c], pmax[1][c]), fmaxf(pmax[2][c], pmax[3][c]));
+    inv_s[c] = m > 0.f ? 448.0f / m : 1.0f;
     if (kt.index() == 0 && n < n_out) array(scale, n_out)[n] = m / 448.0f;
   }
   sync(thread);
-  for (idx_t e = thread.index(); e < 64 * 64; e += kBlock) {   // read along n
-    const idx_t r = e / 64, c = e % 64;
-    tile.at(r, c) = (k0 + r < K && n0 + c < N)
-                        ? lowp::e4m3_rne_sat(b.at(k0 + r, n0 + c) * inv_s[c])
-                        : (uint8_t)0;
+  const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
+    const idx_t r = ty + 16 * i, c = 4 * tx;
+    f32x4 v;
+    if (vec_in && k0 + r < K && n0 + c + 4 <= N) {
+      v = *(const f32x4*)&b.at(k0 + r, n0 + c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[j] = (k0 + r < K && n0 + c + j < N) ? b.at(k0 + r, n0 + c + j) : 0.f;
+    }
+    u8x4 e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      e[j] = (k0 + r < K && n0 + c + j < N) ? lowp::e4m3_rne_sat(v[j] * inv_s[c + j]) : 0;
+    *(u8x4*)&tile.at(r, c) = e;
   }
   sync(thread);
-  for (idx_t e = thread.index(); e < 64 * 64; e += kBlock) {   // write along k
-    const idx_t c = e / 64, r = e % 64;
-    if (n0 + c < n_out && k0 + r < k_out) out.at(n0 + c, k0 + r) = tile.at(r, c);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {                 // output rows ty + 16 i, k = 4 tx ..
+    const idx_t c = ty + 16 * i, r = 4 * tx;
+    if (n0 + c >= n_out) continue;
+    u8x4 e;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) e[j] = tile.at(r + j, c);
+    if (vec_out && k0 + r + 4 <= k_out) {
+      *(u8x4*)&out.at(n0 + c, k0 + r) = e;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + r + j < k_out) out.at(n0 + c, k0 + r + j) = e[j];
+    }
   }
 }
 
@@ -278,10 +396,16 @@ size_t gemm_lowp_workspace(int mode, int64_t M, int64_t N, int64_t K) {
   return layout(mode, M, N, K).total;
 }
 
+bool f4_ok(const void* p, int64_t ld) { return ((uintptr_t)p % 16) == 0 && ld % 4 == 0; }
+bool w_ok(const void* p, int64_t ld, int64_t es) {   // 4 elements of es bytes per store
+  return ((uintptr_t)p % (4 * es)) == 0 && ld % 4 == 0;
+}
+
 hipError_t split_bf16_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint16_t* hi,
                            uint16_t* lo, int64_t ldh, hipStream_t s) {
   hipLaunchKernelGGL(split_rows_kernel, dim3(grid_for(M * ((K + 3) / 4))), dim3(kBlock), 0, s, A,
-                     M, K, lda, hi, lo, M, K, ldh);
+                     M, K, lda, hi, lo, M, K, ldh, f4_ok(A, lda),
+                     w_ok(hi, ldh, 2) && w_ok(lo, ldh, 2));
   return hipGetLastError();
 }
 
@@ -289,14 +413,14 @@ hipError_t split_bf16_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
                            uint16_t* lo_t, int64_t ldh, hipStream_t s) {
   const dim3 grid((unsigned)((K + 63) / 64), (unsigned)((N + 63) / 64));
   hipLaunchKernelGGL(split_cols_t_kernel, grid, dim3(kBlock), 0, s, B, K, N, ldb, hi_t, lo_t, N,
-                     K, ldh);
+                     K, ldh, f4_ok(B, ldb), w_ok(hi_t, ldh, 2) && w_ok(lo_t, ldh, 2));
   return hipGetLastError();
 }
 
 hipError_t quant_e4m3_rows(const float* A, int64_t M, int64_t K, int64_t lda, uint8_t* q,
                            int64_t ldq, float* scale, hipStream_t s) {
   hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)M), dim3(kBlock), 0, s, A, M, K, lda, q, K,
-                     ldq, scale);
+                     ldq, scale, f4_ok(A, lda), w_ok(q, ldq, 1));
   return hipGetLastError();
 }
 
@@ -311,7 +435,8 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
   hipLaunchKernelGGL(colmax_partial_kernel, dim3((unsigned)((N + kBlock - 1) / kBlock), (unsigned)S),
                      dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N);
   hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)((N + 63) / 64)),
-                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale);
+                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale,
+                     f4_ok(B, ldb), w_ok(qt, ldq, 1));
   return hipGetLastError();
 }
 
@@ -323,9 +448,9 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
   uint16_t *ah = (uint16_t*)(w + L.off[0]), *al = (uint16_t*)(w + L.off[1]);
   uint16_t *bh = (uint16_t*)(w + L.off[2]), *bl = (uint16_t*)(w + L.off[3]);
   hipLaunchKernelGGL(split_rows_kernel, dim3(grid_for(L.Mp * (L.Kp / 4))), dim3(kBlock), 0, s, A,
-                     M, K, lda, ah, al, L.Mp, L.Kp, L.Kp);
+                     M, K, lda, ah, al, L.Mp, L.Kp, L.Kp, f4_ok(A, lda), true);
   hipLaunchKernelGGL(split_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)(L.Np / 64)),
-                     dim3(kBlock), 0, s, B, K, N, ldb, bh, bl, L.Np, L.Kp, L.Kp);
+                     dim3(kBlock), 0, s, B, K, N, ldb, bh, bl, L.Np, L.Kp, L.Kp, f4_ok(B, ldb), true);
   NtOperands p{{(const uint8_t*)ah, (const uint8_t*)al},
                {(const uint8_t*)bh, (const uint8_t*)bl},
                L.Kp * 2, Cm, ldc, M, N, nullptr, nullptr};
@@ -345,13 +470,14 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
   uint8_t *qa = w + L.off[0], *qb = w + L.off[2];
   float *sa = (float*)(w + L.off[4]), *sb = (float*)(w + L.off[5]), *part = (float*)(w + L.off[6]);
   hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)L.Mp), dim3(kBlock), 0, s, A, M, K, lda, qa,
-                     L.Kp, L.Kp, sa);
+                     L.Kp, L.Kp, sa, f4_ok(A, lda), true);
   const int64_t S = colmax_slices(K, N), rows_per = (K + S - 1) / S;
   hipLaunchKernelGGL(colmax_partial_kernel, dim3((unsigned)(L.Np / kBlock + (L.Np % kBlock != 0)),
                                                  (unsigned)S),
                      dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, L.Np);
   hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)(L.Np / 64)),
-                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb);
+                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb,
+                     f4_ok(B, ldb), true);
   NtOperands p{{qa, nullptr}, {qb, nullptr}, L.Kp, Cm, ldc, M, N, sa, sb};
   switch (tune::get(tune::kGemmFp8, tune::size_class(tune::kGemmFp8, M * N * K))) {
     case 1: return launch_nt<NtCfg<128, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
