@@ -46,9 +46,10 @@ STEP_BYTES = SCAN_BYTES + TRANSPOSE_BYTES
 
 # HBM traffic of one scan launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by what the counter reads for the copy kernel of known size
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), for the scan kernel as it stands;
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), taken for ScanCfg<512, 32, true>;
 # None when the kernel has changed since the counters were taken.
-SCAN_TRAFFIC_BYTES = None
+SCAN_TRAFFIC_BYTES = 2152071171
+SCAN_TRAFFIC_CONFIG = "b512_r32_nt"
 
 
 def log(msg: str) -> None:
@@ -325,6 +326,9 @@ def main(argv=None):
     ok_tr = bool(torch.equal(mt[:64, :64].cpu(), m[:64, :64].t().cpu()))
 
     value = STEP_BYTES / (ms_per_step * 1e-3) / 1e9
+    scan_cfg = desc.desc_config_name(
+        "scan_i32", desc.desc_config_get("scan_i32", desc.desc_size_class("scan_i32", SCAN_N)))
+    traffic = SCAN_TRAFFIC_BYTES if scan_cfg == SCAN_TRAFFIC_CONFIG else None
     scan_gbs = SCAN_BYTES / (scan_ms * 1e-3) / 1e9
     tr_gbs = TRANSPOSE_BYTES / (tr_ms * 1e-3) / 1e9
     result = {
@@ -346,11 +350,11 @@ def main(argv=None):
                    "bytes_per_step": STEP_BYTES},
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 3),
-        "roofline": {"bound": "hbm", "kernel": "scan_i32_kernel",
+        "roofline": {"bound": "hbm", "kernel": f"scan_i32_kernel {scan_cfg}",
                      "achieved": round(scan_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(scan_gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": SCAN_BYTES, "launch_us": round(scan_ms * 1e3, 2),
-                     "traffic": SCAN_TRAFFIC_BYTES},
+                     "traffic": traffic},
         "ops": {"scan_2^28": {"us": round(scan_ms * 1e3, 2), "GBs": round(scan_gbs, 1),
                               "frac": round(scan_gbs / HBM_PEAK_GBS, 4), "check": ok_scan},
                 "transpose_8192": {"us": round(tr_ms * 1e3, 2), "GBs": round(tr_gbs, 1),
