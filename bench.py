@@ -21,7 +21,7 @@ Small kernels are timed as HIP-graph replays of many back-to-back launches,
 so that host launch overhead does not enter their time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--ops LIST]
-  --ops: comma list of copy,reduce,gemm,gemm8192,segmented,grouped ('' for none)
+  --ops: comma list of copy,reduce,gemm,gemm8192,segmented,grouped,views ('' for none)
 """
 from __future__ import annotations
 
@@ -115,6 +115,64 @@ def events_time_ms(torch, fn, reps: int = 10, warm: int = 2) -> float:
     for _ in range(reps):
         s = t.start(); fn(); t.stop(s)
     return t.mean_ms()
+
+
+def op_views(desc, torch, workloads, reps: int = 100):
+    """The evaluation of Sec. 5 on this GPU: the library's view kernels against
+    their hand-indexed twins (same algorithm and configuration, indices
+    written by hand), for 256 MB, 512 MB and 1 GB of memory per operation,
+    100 runs each, alternating the two; reported as median kernel times and
+    the relative runtime hand / view (above 1: the view kernel is faster)."""
+    import statistics
+    sys.path.insert(0, os.path.join(ROOT, "tests", "handwritten"))
+    import handlib
+    cfgs = {op: desc.desc_config_name(op, desc.desc_config_get(op, desc.desc_size_class(op, 1 << 25)))
+            for op in handlib.VIEW_CONFIGS}
+    if cfgs != handlib.VIEW_CONFIGS:
+        raise RuntimeError(f"view kernel configs {cfgs} differ from the twins' {handlib.VIEW_CONFIGS}")
+
+    def median_ms(timer):
+        return statistics.median(a.elapsed_time(b) for a, b in timer.pairs)
+
+    results = []
+    for mb in (256, 512, 1024):
+        words = mb << 18                      # 32-bit words in `mb` MiB
+        half = words // 2                     # scan and transpose: input + output
+        x = torch.from_numpy(workloads.int_uniform(words, seed=2)).cuda()
+        xs = x[:half]
+        rows = 8192 if mb == 1024 else 4096 * mb // 256
+        m = xs.view(torch.float32).view(rows, half // rows)
+        r1, r2 = torch.empty(1, dtype=torch.int64, device="cuda"), torch.empty(1, dtype=torch.int64,
+                                                                                device="cuda")
+        y1, y2 = torch.empty_like(xs), torch.empty_like(xs)
+        t1 = torch.empty((m.shape[1], m.shape[0]), dtype=torch.float32, device="cuda")
+        t2 = torch.empty_like(t1)
+        cases = [
+            ("reduce", lambda: desc.desc_reduce_i32(x, r1), lambda: handlib.reduce_i32(x, r2),
+             lambda: torch.equal(r1, r2)),
+            ("scan", lambda: desc.desc_scan_i32(xs, y1), lambda: handlib.scan_i32(xs, y2),
+             lambda: torch.equal(y1, y2)),
+            ("transpose", lambda: desc.desc_transpose_f32(m, t1),
+             lambda: handlib.transpose_f32(m, t2),
+             lambda: torch.equal(t1.view(torch.int32), t2.view(torch.int32))),
+        ]
+        for name, fv, fh, check in cases:
+            for _ in range(3):
+                fv(); fh()
+            tv, th = Timer(torch), Timer(torch)
+            for _ in range(reps):
+                e = tv.start(); fv(); tv.stop(e)
+                e = th.start(); fh(); th.stop(e)
+            torch.cuda.synchronize()
+            mv, mh = median_ms(tv), median_ms(th)
+            r = {"op": name, "memory_MB": mb, "view_us": round(mv * 1e3, 2),
+                 "hand_us": round(mh * 1e3, 2), "hand_over_view": round(mh / mv, 4),
+                 "equal": bool(check())}
+            log(f"views {r}")
+            results.append(r)
+        del x, xs, m, y1, y2, t1, t2
+        torch.cuda.empty_cache()
+    return results
 
 
 def cpu_baseline(x_np, m_np, budget_s: float = 20.0):
@@ -267,7 +325,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped",
+    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views",
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -365,6 +423,9 @@ def main(argv=None):
         import oracle
         del x, y, m, mt, ws
         torch.cuda.empty_cache()
+    if "views" in extra:
+        log("view kernels against hand-indexed twins")
+        result["ops"]["views_vs_hand"] = op_views(desc, torch, workloads)
     if "copy" in extra:
         log("copy ceiling")
         result["ops"]["copy_2^28"] = op_copy(desc, torch)

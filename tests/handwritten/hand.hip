@@ -1,0 +1,372 @@
+// hand.hip -- hand-indexed twins of the view-based reduce, scan and
+// transpose kernels: the baseline of the evaluation of Sec. 5, which compares
+// the kernels written against views with the same algorithms written directly
+// in the kernel programming model, with raw index arithmetic.
+//
+// Each twin has the algorithm, tile shape, memory-access order, index types
+// (int64) and synchronisation of the view kernel it mirrors, for the one
+// configuration that kernel uses at 2^24 elements and above:
+//   reduce     256 threads, 4 int32x4 per lane per tile, non-temporal loads;
+//   scan       512 threads x 32 rounds x 4 int32 per tile (64K elements),
+//              non-temporal loads and stores, 256-word look-back window;
+//   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32].
+// Only the index expressions differ: here they are written out by hand
+// instead of being derived from a composition of views.  The helpers shared
+// with the library (relaxed status-word atomics, DPP wave sums) hold no index
+// arithmetic.
+//
+// The twins are measurement infrastructure, not part of the library; they
+// are exported with a minimal C interface that does no argument checking.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "wave.hpp"
+
+namespace hand {
+using desc::i32x4;
+using desc::u32x4;
+using desc::kWave;
+using desc::WsHeader;
+using desc::kSpinLimit;
+
+// ---------------------------------------------------------------- reduce
+constexpr int kRBlock = 256, kRUnroll = 4;
+constexpr int kRTileVec = kRBlock * kRUnroll, kRTile = kRTileVec * 4;
+constexpr int kValueBits = 51;
+constexpr uint64_t kValueMask = (1ull << kValueBits) - 1;
+constexpr uint32_t kTagPeriod = 8191;
+
+__device__ __forceinline__ uint64_t tag_of(uint32_t gen) { return 1u + gen % kTagPeriod; }
+
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
+  v = desc::wave::sum_i64(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x / 64] = v;
+  __syncthreads();
+  int64_t s = 0;
+#pragma unroll
+  for (int w = 0; w < kRBlock / kWave; ++w) s += lds[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kRBlock) void reduce_i32_hand(
+    const i32x4* __restrict__ body, int64_t ntiles, const int32_t* __restrict__ head,
+    int64_t nhead, const int32_t* __restrict__ tail, int64_t ntail, int64_t* __restrict__ out,
+    WsHeader* __restrict__ hdr, uint64_t* __restrict__ partials) {
+  __shared__ int64_t lds[kRBlock / kWave];
+  __shared__ uint32_t s_gen;
+  const int64_t b = blockIdx.x, nb = gridDim.x, tid = threadIdx.x;
+  if (tid == 0) s_gen = desc::load_u32(&hdr->gen);
+  int64_t acc = 0;
+  for (int64_t t = b; t < ntiles; t += nb) {
+    const i32x4* p = body + t * kRTileVec + tid;
+    i32x4 q[kRUnroll];
+#pragma unroll
+    for (int u = 0; u < kRUnroll; ++u) q[u] = __builtin_nontemporal_load(p + u * kRBlock);
+#pragma unroll
+    for (int u = 0; u < kRUnroll; ++u)
+      acc += (int64_t)q[u].x + (int64_t)q[u].y + (int64_t)q[u].z + (int64_t)q[u].w;
+  }
+  const bool last = b == nb - 1;
+  if (last) {
+    for (int64_t i = tid; i < nhead; i += kRBlock) acc += head[i];
+    for (int64_t i = tid; i < ntail; i += kRBlock) acc += tail[i];
+  }
+  const int64_t s = block_sum(acc, lds);
+  const uint32_t gen = s_gen;
+  if (!last) {
+    if (tid == 0)
+      desc::store_status(&partials[b], (tag_of(gen) << kValueBits) | ((uint64_t)s & kValueMask));
+    return;
+  }
+  const uint64_t want = tag_of(gen);
+  int64_t acc2 = tid == 0 ? s : 0;
+  for (int64_t i = tid; i < nb - 1; i += kRBlock) {
+    uint64_t w = desc::load_status(&partials[i]);
+    for (uint32_t polls = 0; (w >> kValueBits) != want; ++polls) {
+      if (polls == kSpinLimit) {
+        desc::store_u32(&hdr->error, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      w = desc::load_status(&partials[i]);
+    }
+    acc2 += (int64_t)(w << (64 - kValueBits)) >> (64 - kValueBits);
+  }
+  __syncthreads();
+  const int64_t total = block_sum(acc2, lds);
+  if (tid == 0) {
+    out[0] = total;
+    desc::store_u32(&hdr->gen, gen + 1u);
+  }
+}
+
+// ---------------------------------------------------------------- scan
+constexpr uint64_t kFlagAggregate = 1, kFlagPrefix = 2;
+constexpr uint32_t kTagMask = 0x3fffffffu;
+constexpr int kLookWords = 4, kWindow = kWave * kLookWords;
+constexpr int kSBlock = 512, kSRounds = 32, kSWaves = kSBlock / kWave;
+constexpr int kSTile = kSBlock * kSRounds * 4;
+
+__device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t gen, uint32_t v) {
+  return (flag << 62) | ((uint64_t)(gen & kTagMask) << 32) | (uint64_t)v;
+}
+
+__device__ __forceinline__ uint32_t look_back(const uint64_t* __restrict__ status, int64_t tile,
+                                              uint32_t gen, WsHeader* __restrict__ hdr) {
+  const int lane = (int)(threadIdx.x & 63);
+  const uint32_t tag = gen & kTagMask;
+  uint32_t excl = 0;
+  int64_t pos = tile - 1;
+  for (uint32_t polls = 0;; ++polls) {
+    if (polls == kSpinLimit) {
+      if (lane == 0) desc::store_u32(&hdr->error, 1u);
+      break;
+    }
+    uint64_t w[kLookWords];
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) {
+      const int64_t j = pos - (q * kWave + lane);
+      w[q] = j >= 0 ? desc::load_status(&status[j]) : pack(kFlagPrefix, gen, 0u);
+    }
+    int first_p = kWindow;
+    bool missing = false;
+#pragma unroll
+    for (int q = kLookWords - 1; q >= 0; --q) {
+      const uint32_t flag = (uint32_t)(w[q] >> 62);
+      const bool valid = flag != 0 && (uint32_t)((w[q] >> 32) & kTagMask) == tag;
+      const uint64_t pm = __ballot(valid && flag == kFlagPrefix);
+      if (pm) first_p = q * kWave + __builtin_ctzll(pm);
+    }
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) {
+      const uint32_t flag = (uint32_t)(w[q] >> 62);
+      const bool valid = flag != 0 && (uint32_t)((w[q] >> 32) & kTagMask) == tag;
+      missing |= __ballot(!valid && q * kWave + lane <= first_p) != 0;
+    }
+    if (missing) {
+      __builtin_amdgcn_s_sleep(2);
+      continue;
+    }
+    uint32_t part = 0;
+#pragma unroll
+    for (int q = 0; q < kLookWords; ++q) part += (q * kWave + lane <= first_p) ? (uint32_t)w[q] : 0u;
+    excl += desc::wave::sum_u32(part);
+    if (first_p < kWindow) break;
+    pos -= kWindow;
+  }
+  return excl;
+}
+
+template <bool kVec>
+__global__ __launch_bounds__(kSBlock) void scan_i32_hand(const int32_t* __restrict__ in,
+                                                         int32_t* __restrict__ out, int64_t n,
+                                                         WsHeader* __restrict__ hdr,
+                                                         uint64_t* __restrict__ status) {
+  constexpr int R = kSRounds, NW = kSWaves;
+  __shared__ uint32_t s_gen, s_prefix;
+  __shared__ uint32_t s_wtot[NW];
+  const int64_t ntiles = gridDim.x, tile = blockIdx.x, tid = threadIdx.x;
+  const int64_t wv = tid / kWave, lane = tid % kWave;
+  if (tid == 0) s_gen = desc::load_u32(&hdr->gen);
+  __syncthreads();
+  const uint32_t gen = s_gen;
+
+  // group g = ((tile * NW + wave) * R + r) * 64 + lane holds elements 4g..4g+3
+  const int64_t g0 = ((tile * NW + wv) * R) * kWave + lane;
+  const bool full = kVec && (tile + 1) * kSTile <= n;
+  uint32_t x[R][4];
+  if (full) {
+    const i32x4* p = (const i32x4*)in + g0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const i32x4 q = __builtin_nontemporal_load(p + r * kWave);
+      x[r][0] = (uint32_t)q.x; x[r][1] = (uint32_t)q.y;
+      x[r][2] = (uint32_t)q.z; x[r][3] = (uint32_t)q.w;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t e = 4 * (g0 + r * kWave);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[r][k] = e + k < n ? (uint32_t)in[e + k] : 0u;
+    }
+  }
+
+  uint32_t lsum = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) lsum += x[r][0] + x[r][1] + x[r][2] + x[r][3];
+  const uint32_t wsum = desc::wave::sum_u32(lsum);
+  if (lane == 0) s_wtot[wv] = wsum;
+  __syncthreads();
+  uint32_t wex = 0, agg = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t v = s_wtot[w];
+    wex += (w < wv) ? v : 0u;
+    agg += v;
+  }
+
+  if (wv == 0) {
+    uint32_t excl = 0;
+    if (tile == 0) {
+      if (lane == 0) desc::store_status(&status[0], pack(kFlagPrefix, gen, agg));
+    } else {
+      if (lane == 0) desc::store_status(&status[tile], pack(kFlagAggregate, gen, agg));
+      excl = look_back(status, tile, gen, hdr);
+      if (lane == 0) desc::store_status(&status[tile], pack(kFlagPrefix, gen, excl + agg));
+    }
+    if (lane == 0) {
+      s_prefix = excl;
+      if (tile == ntiles - 1) desc::store_u32(&hdr->gen, gen + 1u);
+    }
+  }
+
+  uint32_t carry = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    x[r][1] += x[r][0];
+    x[r][2] += x[r][1];
+    x[r][3] += x[r][2];
+    const uint32_t t = x[r][3];
+    const uint32_t incl = desc::wave::inclusive_add_u32(t);
+    const uint32_t ex = carry + incl - t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[r][k] += ex;
+    carry += desc::wave::lane_read_u32(incl, kWave - 1);
+  }
+  __syncthreads();
+  const uint32_t add = s_prefix + wex;
+
+  if (full) {
+    i32x4* p = (i32x4*)out + g0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      i32x4 q;
+      q.x = (int32_t)(x[r][0] + add); q.y = (int32_t)(x[r][1] + add);
+      q.z = (int32_t)(x[r][2] + add); q.w = (int32_t)(x[r][3] + add);
+      __builtin_nontemporal_store(q, p + r * kWave);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t e = 4 * (g0 + r * kWave);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (e + k < n) out[e + k] = (int32_t)(x[r][k] + add);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- transpose
+constexpr int kT = 128, kPitch = kT + 1, kTX = kT / 4, kTY = 256 / kTX, kIT = kT / kTY;
+
+template <bool kVec>
+__global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out, int64_t rows,
+                                                        int64_t cols) {
+  __shared__ uint32_t lds[kT * kPitch];
+  const int64_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z, tid = threadIdx.x;
+  const bool full = kVec && (by + 1) * kT <= rows && (bx + 1) * kT <= cols;
+  if (full) {
+    const int64_t y = tid / kTX, x = tid % kTX, c4 = cols / 4, r4 = rows / 4;
+    // row y of input tile (by, bx) and row y of output tile (bx, by)
+    const u32x4* a = (const u32x4*)in + (bz * rows + by * kT + y) * c4 + bx * kTX + x;
+    u32x4* b = (u32x4*)out + (bz * cols + bx * kT + y) * r4 + by * kTX + x;
+    u32x4 v[kIT];
+#pragma unroll
+    for (int i = 0; i < kIT; ++i) v[i] = a[kTY * i * c4];
+#pragma unroll
+    for (int i = 0; i < kIT; ++i) {
+      uint32_t* l = &lds[(y + kTY * i) * kPitch + 4 * x];
+      l[0] = v[i].x; l[1] = v[i].y; l[2] = v[i].z; l[3] = v[i].w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kIT; ++i) {
+      const uint32_t* l = &lds[4 * x * kPitch + y + kTY * i];
+      u32x4 w;
+      w.x = l[0]; w.y = l[kPitch]; w.z = l[2 * kPitch]; w.w = l[3 * kPitch];
+      b[kTY * i * r4] = w;
+    }
+  } else {
+    const int64_t r0 = by * kT, c0 = bx * kT;
+    const uint32_t* a = in + (bz * rows + r0) * cols + c0;
+    uint32_t* b = out + (bz * cols + c0) * rows + r0;
+    for (int64_t e = tid; e < kT * kT; e += 256) {
+      const int64_t r = e / kT, c = e % kT;
+      if (r0 + r < rows && c0 + c < cols) lds[r * kPitch + c] = a[r * cols + c];
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < kT * kT; e += 256) {
+      const int64_t c = e / kT, r = e % kT;
+      if (r0 + r < rows && c0 + c < cols) b[c * rows + r] = lds[r * kPitch + c];
+    }
+  }
+}
+
+}  // namespace hand
+
+// ---------------------------------------------------------------- C interface
+// All return a hipError_t value.  Workspaces follow the library's contract:
+// zero-filled before the first call, then reused.
+
+extern "C" {
+
+size_t hand_reduce_i32_workspace(int64_t n) {
+  const int64_t ntiles = n / hand::kRTile;
+  int64_t grid = ntiles < 2048 ? ntiles : 2048;
+  const int64_t need = (n + (1 << 19) - 1) >> 19;
+  if (grid < need) grid = need;
+  if (grid < 1) grid = 1;
+  return sizeof(hand::WsHeader) + 8 * (size_t)grid;
+}
+
+int hand_reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipStream_t s) {
+  const uintptr_t addr = (uintptr_t)in;
+  int64_t nhead = (int64_t)(((16 - (addr & 15)) & 15) / 4);
+  if (nhead > n) nhead = n;
+  const int64_t rest = n - nhead, ntiles = rest / hand::kRTile;
+  const int64_t ntail = rest - ntiles * hand::kRTile;
+  const int64_t grid = (int64_t)(hand_reduce_i32_workspace(n) - sizeof(hand::WsHeader)) / 8;
+  hipLaunchKernelGGL(hand::reduce_i32_hand, dim3((unsigned)grid), dim3(hand::kRBlock), 0, s,
+                     (const hand::i32x4*)(in + nhead), ntiles, in, nhead,
+                     in + nhead + ntiles * hand::kRTile, ntail, out, (hand::WsHeader*)ws,
+                     (uint64_t*)((char*)ws + sizeof(hand::WsHeader)));
+  return (int)hipGetLastError();
+}
+
+size_t hand_scan_i32_workspace(int64_t n) {
+  const int64_t ntiles = (n + hand::kSTile - 1) / hand::kSTile;
+  return sizeof(hand::WsHeader) + 8 * (size_t)(ntiles > 0 ? ntiles : 1);
+}
+
+int hand_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+  if (n == 0) return 0;
+  const int64_t ntiles = (n + hand::kSTile - 1) / hand::kSTile;
+  hand::WsHeader* hdr = (hand::WsHeader*)ws;
+  uint64_t* status = (uint64_t*)((char*)ws + sizeof(hand::WsHeader));
+  if ((((uintptr_t)in | (uintptr_t)out) & 15) == 0)
+    hipLaunchKernelGGL(hand::scan_i32_hand<true>, dim3((unsigned)ntiles), dim3(hand::kSBlock), 0,
+                       s, in, out, n, hdr, status);
+  else
+    hipLaunchKernelGGL(hand::scan_i32_hand<false>, dim3((unsigned)ntiles), dim3(hand::kSBlock),
+                       0, s, in, out, n, hdr, status);
+  return (int)hipGetLastError();
+}
+
+int hand_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows == 0 || cols == 0) return 0;
+  const dim3 grid((unsigned)((cols + hand::kT - 1) / hand::kT),
+                  (unsigned)((rows + hand::kT - 1) / hand::kT), 1);
+  const bool vec = rows % 4 == 0 && cols % 4 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(hand::transpose32_hand<true>, grid, dim3(256), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, rows, cols);
+  else
+    hipLaunchKernelGGL(hand::transpose32_hand<false>, grid, dim3(256), 0, s,
+                       (const uint32_t*)in, (uint32_t*)out, rows, cols);
+  return (int)hipGetLastError();
+}
+
+}  // extern "C"
