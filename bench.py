@@ -277,7 +277,7 @@ def op_segmented(desc, torch, workloads):
     y = torch.empty_like(x)
     wr = torch.empty(desc.desc_reduce_segmented_i32_workspace(T, S), dtype=torch.uint8,
                      device="cuda")
-    wy = torch.empty(desc.desc_scan_segmented_i32_workspace(T, S), dtype=torch.uint8,
+    wy = torch.zeros(desc.desc_scan_segmented_i32_workspace(T, S), dtype=torch.uint8,
                      device="cuda")
     red = graph_time_ms(torch, lambda: desc.desc_reduce_segmented_i32(x, off, r, ws=wr), reps=10)
     scn = graph_time_ms(torch, lambda: desc.desc_scan_segmented_i32(x, off, y, ws=wy), reps=10)
@@ -286,6 +286,11 @@ def op_segmented(desc, torch, workloads):
     r_h = r.cpu().numpy()
     ok = all(int(r_h[s]) == int(x_np[off_np[s]:off_np[s + 1]].sum(dtype=np.int64))
              for s in (0, 1, S // 2, S - 1))
+    ends = [int(off_np[s + 1]) - 1 for s in (0, 1, S // 2, S - 1) if off_np[s + 1] > off_np[s]]
+    y_h = y[torch.tensor(ends, device="cuda")].cpu().numpy()
+    ok = ok and all(int(v) == int(np.int64(r_h[s]).astype(np.int32))
+                    for v, s in zip(y_h, [s for s in (0, 1, S // 2, S - 1)
+                                          if off_np[s + 1] > off_np[s]]))
     rb = 4 * T + 8 * (S + 1) + 8 * S
     sb = 8 * T + 8 * (S + 1)
     del x, y

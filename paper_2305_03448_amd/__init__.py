@@ -398,8 +398,7 @@ def desc_reduce_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch
     if S < 0 or out.numel() != S:
         raise ValueError("offsets must hold S + 1 entries and out S")
     n = x.numel()
-    need = desc_reduce_segmented_i32_workspace(n, S)
-    w = ws if ws is not None else torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
+    w = _ws("reduce_segmented_i32", desc_reduce_segmented_i32_workspace(n, S), x, ws)
     _check(lib().desc_reduce_segmented_i32(_ptr(x), n, _ptr(offsets), S, _ptr(out), _ptr(w),
                                            w.numel(), _stream(x, stream)),
            "desc_reduce_segmented_i32")
@@ -414,8 +413,7 @@ def desc_scan_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch.T
     if S < 0 or out.numel() != x.numel():
         raise ValueError("offsets must hold S + 1 entries and out as many elements as x")
     n = x.numel()
-    need = desc_scan_segmented_i32_workspace(n, S)
-    w = ws if ws is not None else torch.empty(max(need, 8), dtype=torch.uint8, device=x.device)
+    w = _ws("scan_segmented_i32", desc_scan_segmented_i32_workspace(n, S), x, ws)
     _check(lib().desc_scan_segmented_i32(_ptr(x), _ptr(out), n, _ptr(offsets), S, _ptr(w),
                                          w.numel(), _stream(x, stream)),
            "desc_scan_segmented_i32")

@@ -3,10 +3,12 @@
 // positions [offsets[s], offsets[s+1]) of one int32 array.
 //
 // Work is cut into units: segment s of length L_s gives ceil(L_s / UNIT)
-// units of at most UNIT consecutive elements (an empty segment gives none).
+// units of at most UNIT consecutive elements (an empty segment gives none);
+// UNIT is 8K, 16K or 32K elements, picked per size class by the tuning table.
 //
-//   plan kernel (one block): unit counts and their exclusive prefix over the
-//     segments, written to the workspace with the total; for the reduction,
+//   plan kernel (one block of 1024 threads, 4096 segments per pass): unit
+//     counts and their exclusive prefix over the segments, written to the
+//     workspace with the total; for the reduction,
 //     the outputs of segments spanning several units are zeroed (and empty
 //     segments get 0); for the scan, the look-back status words are cleared.
 //   main kernel: block b handles unit b (the grid is launched for the upper
@@ -34,10 +36,15 @@
 namespace desc {
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / kWave;
-constexpr int kRounds = 8;
-constexpr int kUnit = kWaves * kWave * 4 * kRounds;   // 8192 elements
+// A unit is kBlock threads x kRounds rounds x 4 int32.
+template <int kBlock_, int kRounds_>
+struct UnitCfg {
+  static constexpr int block = kBlock_;
+  static constexpr int rounds = kRounds_;
+  static constexpr int waves = kBlock_ / kWave;
+  static constexpr int unit = waves * kWave * 4 * kRounds_;   // int32 per unit
+};
+constexpr int kMinUnit = 8192;   // smallest unit of the configurations below
 constexpr uint64_t kFlagAggregate = 1, kFlagPrefix = 2;
 
 // Workspace: header (total units), unit prefix [S + 1] int64, status [units].
@@ -47,52 +54,72 @@ struct SegWs {
   uint64_t* status;      // one word per unit (scan)
 };
 
-__device__ __forceinline__ int64_t units_of(int64_t len) { return (len + kUnit - 1) / kUnit; }
+template <class C>
+__device__ __forceinline__ int64_t units_of(int64_t len) { return (len + C::unit - 1) / C::unit; }
 
 // Offsets are read clamped to [0, n]: offsets that break the documented
 // precondition (non-decreasing, within the array) give unspecified results
 // but never an access outside the array.
 __device__ __forceinline__ int64_t clampn(int64_t v, int64_t n) { return v < 0 ? 0 : (v > n ? n : v); }
 
-// One block: unit counts and their exclusive prefix, in chunks of kBlock
-// segments with a running carry; then per-op initialisation.
-template <bool kScan>
-__global__ __launch_bounds__(kBlock) void plan_kernel(const int64_t* __restrict__ offsets,
-                                                      int64_t n, int64_t S,
-                                                      int64_t* __restrict__ total,
-                                                      int64_t* __restrict__ unit_start,
-                                                      int64_t* __restrict__ red_out,
-                                                      uint64_t* __restrict__ status,
-                                                      int64_t max_units) {
-  __shared__ int64_t s_wsum[kWaves];
+// One block of kPlanBlock threads, kPlanPer consecutive segments per thread:
+// unit counts and their exclusive prefix over the segments, a chunk of
+// kPlanBlock * kPlanPer segments per pass with a running carry; then per-op
+// initialisation.  Reduce: the outputs of segments that do not have exactly
+// one unit are zeroed (atomics add into them; an empty segment sums to 0).
+// Scan: the look-back status words are cleared.
+constexpr int kPlanBlock = 1024, kPlanPer = 4, kPlanWaves = kPlanBlock / kWave;
+
+template <class C, bool kScan>
+__global__ __launch_bounds__(kPlanBlock) void plan_kernel(const int64_t* __restrict__ offsets,
+                                                          int64_t n, int64_t S,
+                                                          int64_t* __restrict__ total,
+                                                          int64_t* __restrict__ unit_start,
+                                                          int64_t* __restrict__ red_out,
+                                                          uint64_t* __restrict__ status,
+                                                          int64_t max_units) {
+  __shared__ int64_t s_wsum[kPlanWaves];
   __shared__ int64_t s_carry;
-  auto thread = thread_x<kBlock>();
-  auto wv = wave_of_block<kBlock>();
+  auto thread = thread_x<kPlanBlock>();
+  auto wv = wave_of_block<kPlanBlock>();
+  auto lane = lane_of_wave();
   auto off = array(offsets, S + 1);
   auto us = array(unit_start, S + 1);
   if (thread.index() == 0) s_carry = 0;
   sync(thread);
-  for (idx_t base = 0; base < S; base += kBlock) {
-    const idx_t s = base + thread.index();
-    const int64_t len = s < S ? clampn(off[s + 1], n) - clampn(off[s], n) : 0;
-    const int64_t u = s < S ? units_of(len > 0 ? len : 0) : 0;
-    if constexpr (!kScan) {
-      if (s < S && u != 1) array(red_out, S)[s] = 0;   // zero for atomics / empty segments
+  for (idx_t base = 0; base < S; base += kPlanBlock * kPlanPer) {
+    const idx_t s0 = base + thread.index() * kPlanPer;
+    int64_t u[kPlanPer];
+    int64_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kPlanPer; ++j) {
+      const idx_t s = s0 + j;
+      const int64_t len = s < S ? clampn(off[s + 1], n) - clampn(off[s], n) : 0;
+      u[j] = s < S ? units_of<C>(len > 0 ? len : 0) : 0;
+      if constexpr (!kScan) {
+        if (s < S && u[j] != 1) array(red_out, S)[s] = 0;
+      }
+      mine += u[j];
     }
-    // block-wide exclusive prefix of u (int64; lanes via shuffles)
-    int64_t incl = u;
+    // block-wide exclusive prefix of the per-thread unit counts (int64)
+    int64_t incl = mine;
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
       const int64_t t = __shfl_up(incl, d, kWave);
-      if ((int)lane_of_wave().index() >= d) incl += t;
+      if ((int)lane.index() >= d) incl += t;
     }
-    if (lane_of_wave().index() == kWave - 1) s_wsum[wv.index()] = incl;
+    if (lane.index() == kWave - 1) s_wsum[wv.index()] = incl;
     sync(thread);
     int64_t before = s_carry;
-    for (int w = 0; w < kWaves; ++w) before += (w < wv.index()) ? s_wsum[w] : 0;
-    if (s < S) us[s] = before + incl - u;
+    for (int w = 0; w < kPlanWaves; ++w) before += (w < wv.index()) ? s_wsum[w] : 0;
+    int64_t at = before + incl - mine;
+#pragma unroll
+    for (int j = 0; j < kPlanPer; ++j) {
+      if (s0 + j < S) us[s0 + j] = at;
+      at += u[j];
+    }
     sync(thread);
-    if (thread.index() == kBlock - 1) s_carry = before + incl;
+    if (thread.index() == kPlanBlock - 1) s_carry = before + incl;
     sync(thread);
   }
   if (thread.index() == 0) {
@@ -101,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void plan_kernel(const int64_t* __restrict_
   }
   if constexpr (kScan) {
     auto st = array(status, max_units);
-    for (idx_t i = thread.index(); i < max_units; i += kBlock) st[i] = 0;
+    for (idx_t i = thread.index(); i < max_units; i += kPlanBlock) st[i] = 0;
   }
 }
 
@@ -122,10 +149,11 @@ struct UnitInfo {
   bool single;                // the segment has one unit only
 };
 
+template <class C>
 __device__ __forceinline__ bool unit_info(const int64_t* offsets, const int64_t* unit_start,
                                           int64_t n, int64_t S, int64_t total, UnitInfo* out) {
   __shared__ int64_t s_info[5];
-  auto thread = thread_x<kBlock>();
+  auto thread = thread_x<C::block>();
   const idx_t u = block_x().index();
   if (u >= total) return false;
   if (thread.index() == 0) {
@@ -133,10 +161,10 @@ __device__ __forceinline__ bool unit_info(const int64_t* offsets, const int64_t*
     auto off = array(offsets, S + 1);
     auto us = array(unit_start, S + 1);
     const idx_t j = u - us[s];
-    const idx_t b = clampn(off[s], n) + j * kUnit;
+    const idx_t b = clampn(off[s], n) + j * C::unit;
     const idx_t e = clampn(off[s + 1], n);
     s_info[0] = s; s_info[1] = j; s_info[2] = b;
-    s_info[3] = (e - b) < kUnit ? (e - b) : kUnit;
+    s_info[3] = (e - b) < C::unit ? (e - b) : C::unit;
     s_info[4] = (us[s + 1] - us[s]) == 1;
   }
   sync(thread);
@@ -145,10 +173,12 @@ __device__ __forceinline__ bool unit_info(const int64_t* offsets, const int64_t*
 }
 
 // The unit's elements as [waves][rounds][lanes][4]; x[r][k] gets element
-// w*2048 + r*256 + lane*4 + k (0 beyond the unit's length).
+// (w * rounds + r) * 256 + lane * 4 + k (0 beyond the unit's length).
+template <class C>
 __device__ __forceinline__ void load_unit(const int32_t* in, const UnitInfo& ui,
-                                          uint32_t (&x)[kRounds][4]) {
-  auto wv = wave_of_block<kBlock>();
+                                          uint32_t (&x)[C::rounds][4]) {
+  constexpr int kWaves = C::waves, kRounds = C::rounds, kUnit = C::unit;
+  auto wv = wave_of_block<C::block>();
   auto lane = lane_of_wave();
   auto unit = array(in, 0).snd(ui.begin);
   if (ui.len == kUnit) {
@@ -172,20 +202,22 @@ __device__ __forceinline__ void load_unit(const int32_t* in, const UnitInfo& ui,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void seg_reduce_kernel(const int32_t* __restrict__ in,
+template <class C>
+__global__ __launch_bounds__(C::block) void seg_reduce_kernel(const int32_t* __restrict__ in,
                                                             int64_t n,
                                                             const int64_t* __restrict__ offsets,
                                                             int64_t S,
                                                             const int64_t* __restrict__ total,
                                                             const int64_t* __restrict__ unit_start,
                                                             int64_t* __restrict__ out) {
+  constexpr int kBlock = C::block, kWaves = C::waves, kRounds = C::rounds;
   __shared__ int64_t s_w[kWaves];
   UnitInfo ui;
-  if (!unit_info(offsets, unit_start, n, S, total[0], &ui)) return;
+  if (!unit_info<C>(offsets, unit_start, n, S, total[0], &ui)) return;
   auto thread = thread_x<kBlock>();
   auto wv = wave_of_block<kBlock>();
   uint32_t x[kRounds][4];
-  load_unit(in, ui, x);
+  load_unit<C>(in, ui, x);
   int64_t acc = 0;
 #pragma unroll
   for (int r = 0; r < kRounds; ++r)
@@ -238,7 +270,8 @@ __device__ __forceinline__ uint32_t seg_look_back(const uint64_t* status, idx_t 
   return excl;
 }
 
-__global__ __launch_bounds__(kBlock) void seg_scan_kernel(const int32_t* __restrict__ in,
+template <class C>
+__global__ __launch_bounds__(C::block) void seg_scan_kernel(const int32_t* __restrict__ in,
                                                           int32_t* __restrict__ out, int64_t n,
                                                           const int64_t* __restrict__ offsets,
                                                           int64_t S,
@@ -246,16 +279,17 @@ __global__ __launch_bounds__(kBlock) void seg_scan_kernel(const int32_t* __restr
                                                           const int64_t* __restrict__ unit_start,
                                                           uint64_t* __restrict__ status,
                                                           uint32_t* __restrict__ error) {
+  constexpr int kBlock = C::block, kWaves = C::waves, kRounds = C::rounds, kUnit = C::unit;
   __shared__ uint32_t s_wtot[kWaves];
   __shared__ uint32_t s_prefix;
   UnitInfo ui;
-  if (!unit_info(offsets, unit_start, n, S, total[0], &ui)) return;
+  if (!unit_info<C>(offsets, unit_start, n, S, total[0], &ui)) return;
   auto thread = thread_x<kBlock>();
   auto wv = wave_of_block<kBlock>();
   auto lane = lane_of_wave();
   const idx_t u = block_x().index();
   uint32_t x[kRounds][4];
-  load_unit(in, ui, x);
+  load_unit<C>(in, ui, x);
 
   uint32_t lsum = 0;
 #pragma unroll
@@ -321,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void seg_scan_kernel(const int32_t* __restr
   }
 }
 
-int64_t max_units(int64_t n, int64_t S) { return S + (n + kUnit - 1) / kUnit; }
+// Upper bound on the units of any configuration (the smallest unit).
+int64_t max_units(int64_t n, int64_t S) { return S + (n + kMinUnit - 1) / kMinUnit; }
 
 SegWs carve(void* ws, int64_t S) {
   uint8_t* w = (uint8_t*)ws;
@@ -332,11 +367,38 @@ SegWs carve(void* ws, int64_t S) {
   return r;
 }
 
-constexpr const char* kNames[] = {"unit8192"};
-constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
+template <class C>
+hipError_t launch_reduce(const int32_t* in, int64_t n, const int64_t* offsets, int64_t S,
+                         int64_t* out, void* ws, hipStream_t s) {
+  const SegWs w = carve(ws, S);
+  hipLaunchKernelGGL((plan_kernel<C, false>), dim3(1), dim3(kPlanBlock), 0, s, offsets, n, S,
+                     w.total, w.unit_start, out, (uint64_t*)nullptr, (int64_t)0);
+  const int64_t grid = S + (n + C::unit - 1) / C::unit;
+  if (grid > 0)
+    hipLaunchKernelGGL(seg_reduce_kernel<C>, dim3((unsigned)grid), dim3(C::block), 0, s, in, n,
+                       offsets, S, w.total, w.unit_start, out);
+  return hipGetLastError();
+}
+
+template <class C>
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, const int64_t* offsets,
+                       int64_t S, void* ws, hipStream_t s) {
+  const SegWs w = carve(ws, S);
+  const int64_t mu = S + (n + C::unit - 1) / C::unit;
+  hipLaunchKernelGGL((plan_kernel<C, true>), dim3(1), dim3(kPlanBlock), 0, s, offsets, n, S,
+                     w.total, w.unit_start, (int64_t*)nullptr, w.status, mu);
+  if (mu > 0)
+    hipLaunchKernelGGL(seg_scan_kernel<C>, dim3((unsigned)mu), dim3(C::block), 0, s, in, out, n,
+                       offsets, S, w.total, w.unit_start, w.status, &((WsHeader*)ws)->error);
+  return hipGetLastError();
+}
+
+constexpr const char* kNames[] = {"unit8k", "unit16k", "unit32k"};
+constexpr int kReduceDefaults[tune::kClasses] = {0, 0, 0, 0};
+constexpr int kScanDefaults[tune::kClasses] = {0, 0, 0, 2};
 const bool kRegistered =
-    (tune::register_op(tune::kSegReduceI32, "seg_reduce_i32", 1, kNames, kDefaults),
-     tune::register_op(tune::kSegScanI32, "seg_scan_i32", 1, kNames, kDefaults), true);
+    (tune::register_op(tune::kSegReduceI32, "seg_reduce_i32", 3, kNames, kReduceDefaults),
+     tune::register_op(tune::kSegScanI32, "seg_scan_i32", 3, kNames, kScanDefaults), true);
 
 }  // namespace
 
@@ -352,27 +414,21 @@ int64_t segmented_max_grid(int64_t n, int64_t S) { return max_units(n, S); }
 hipError_t reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets, int64_t S,
                                 int64_t* out, void* ws, hipStream_t s) {
   (void)kRegistered;
-  const SegWs w = carve(ws, S);
-  hipLaunchKernelGGL((plan_kernel<false>), dim3(1), dim3(kBlock), 0, s, offsets, n, S, w.total,
-                     w.unit_start, out, (uint64_t*)nullptr, (int64_t)0);
-  const int64_t grid = max_units(n, S);
-  if (grid > 0)
-    hipLaunchKernelGGL(seg_reduce_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s, in, n,
-                       offsets, S, w.total, w.unit_start, out);
-  return hipGetLastError();
+  switch (tune::get(tune::kSegReduceI32, tune::size_class(tune::kSegReduceI32, n))) {
+    case 1: return launch_reduce<UnitCfg<256, 16>>(in, n, offsets, S, out, ws, s);
+    case 2: return launch_reduce<UnitCfg<512, 16>>(in, n, offsets, S, out, ws, s);
+    default: return launch_reduce<UnitCfg<256, 8>>(in, n, offsets, S, out, ws, s);
+  }
 }
 
 hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const int64_t* offsets,
                               int64_t S, void* ws, hipStream_t s) {
   (void)kRegistered;
-  const SegWs w = carve(ws, S);
-  const int64_t mu = max_units(n, S);
-  hipLaunchKernelGGL((plan_kernel<true>), dim3(1), dim3(kBlock), 0, s, offsets, n, S, w.total,
-                     w.unit_start, (int64_t*)nullptr, w.status, mu);
-  if (mu > 0)
-    hipLaunchKernelGGL(seg_scan_kernel, dim3((unsigned)mu), dim3(kBlock), 0, s, in, out, n,
-                       offsets, S, w.total, w.unit_start, w.status, &((WsHeader*)ws)->error);
-  return hipGetLastError();
+  switch (tune::get(tune::kSegScanI32, tune::size_class(tune::kSegScanI32, n))) {
+    case 1: return launch_scan<UnitCfg<256, 16>>(in, out, n, offsets, S, ws, s);
+    case 2: return launch_scan<UnitCfg<512, 16>>(in, out, n, offsets, S, ws, s);
+    default: return launch_scan<UnitCfg<256, 8>>(in, out, n, offsets, S, ws, s);
+  }
 }
 
 }  // namespace launch

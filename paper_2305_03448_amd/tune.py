@@ -75,6 +75,31 @@ def _problems(op: str, dev):
             fn = (lambda A=A, B=B, C=C, ws=ws, mode=mode: desc.desc_gemm(A, B, C, mode=mode, ws=ws))
             # "bytes" here is the flop count (2 n^3); the GBs column then reads GFLOP/s
             out.append((desc.desc_size_class(op, n ** 3), f"{n}^3", 2 * n ** 3, fn))
+    elif op in ("seg_scan_i32", "seg_reduce_i32"):
+        # log-uniform segment lengths in [1, max_len]; the last problem is the
+        # size of the 4096-segment workload (about 3.2e8 elements)
+        for S, max_len in ((8, 1 << 12), (64, 1 << 14), (256, 1 << 16), (4096, 1 << 20)):
+            u = torch.rand(S, device=dev, generator=g, dtype=torch.float64)
+            lengths = torch.floor(2.0 ** (u * torch.log2(torch.tensor(max_len + 1.0)))).long()
+            off = torch.zeros(S + 1, dtype=torch.int64, device=dev)
+            off[1:] = torch.cumsum(lengths, 0)
+            n = int(off[-1].item())
+            x = torch.randint(-1024, 1025, (n,), dtype=torch.int32, device=dev, generator=g)
+            if op == "seg_scan_i32":
+                y = torch.empty_like(x)
+                ws = torch.zeros(desc.desc_scan_segmented_i32_workspace(n, S), dtype=torch.uint8,
+                                 device=dev)
+                fn = (lambda x=x, off=off, y=y, ws=ws:
+                      desc.desc_scan_segmented_i32(x, off, y, ws=ws))
+                nbytes = 8 * n
+            else:
+                r = torch.empty(S, dtype=torch.int64, device=dev)
+                ws = torch.zeros(desc.desc_reduce_segmented_i32_workspace(n, S),
+                                 dtype=torch.uint8, device=dev)
+                fn = (lambda x=x, off=off, r=r, ws=ws:
+                      desc.desc_reduce_segmented_i32(x, off, r, ws=ws))
+                nbytes = 4 * n
+            out.append((desc.desc_size_class(op, n), f"n={n} S={S}", nbytes, fn))
     else:
         raise ValueError(f"no tuning problems for {op}")
     return out
@@ -109,7 +134,7 @@ def write_table(table, path: str) -> None:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--ops", default="copy_32,scan_i32,transpose_32,reduce_i32")
+    ap.add_argument("--ops", default="copy_32,scan_i32,transpose_32,reduce_i32,seg_scan_i32,seg_reduce_i32")
     ap.add_argument("--out", default=None, help="table file to write")
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args(argv)

@@ -15,7 +15,8 @@ from gpu_util import case, dev, needs_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
-UNIT = 8192
+UNIT = 8192                    # units of work
+TILES = (8192, 16384, 32768)   # power-of-two block sizes that edge cases straddle
 
 
 def _both(x, off, fill=-7):
@@ -81,8 +82,8 @@ def test_repeated_calls_and_graph_replay():
     y = torch.empty(x.size, dtype=torch.int32, device=dev())
     wr = torch.empty(desc.desc_reduce_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
                      device=dev())
-    wy = torch.empty(desc.desc_scan_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
-                     device=dev())
+    wy = torch.zeros(desc.desc_scan_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
+                     device=dev())   # zero-filled once, as the workspace contract asks
     for rep in range(3):
         case(f"segmented eager rep {rep}")
         desc.desc_reduce_segmented_i32(xt, ot, r, ws=wr)
@@ -113,3 +114,71 @@ def test_workload_4096_segments():
     r, y = _both(x, off)
     assert np.array_equal(r, oracle.reduce_segmented_i32(x, off))
     assert np.array_equal(y, oracle.scan_segmented_i32(x, off))
+
+
+def _tile_edge_lengths():
+    # boundaries on, just before and just after every tile edge of every
+    # configuration, a segment spanning many tiles, and dense short segments
+    lengths = []
+    for t in TILES:
+        lengths += [t, t - 1, 1, t + 1, 0, 2 * t, 3]
+    lengths += [5 * 32768 + 11]
+    lengths += list(workloads.rng(5).integers(0, 9, 2000))
+    lengths += [1] * 300 + [0] * 5 + [70_000]
+    return np.array(lengths, np.int64)
+
+
+@pytest.fixture
+def restore_seg_configs():
+    yield
+    for op in ("seg_scan_i32", "seg_reduce_i32"):
+        for cls in range(4):
+            desc.desc_config_set(op, cls, -1)
+
+
+@pytest.mark.parametrize("offset", [0, 1])
+def test_every_config_tile_edges(offset, restore_seg_configs):
+    lengths = _tile_edge_lengths()
+    off = workloads.offsets_from_lengths(lengths)
+    n = int(off[-1])
+    x = workloads.int_uniform(n, seed=23)
+    want = oracle.scan_segmented_i32(x, off)
+    xt, ot = to_dev(x, offset), to_dev(off)   # offset 1: unaligned input, scalar path
+    cls = desc.desc_size_class("seg_scan_i32", n)
+    want_r = oracle.reduce_segmented_i32(x, off)
+    for cfg in range(desc.desc_config_count("seg_scan_i32")):
+        name = desc.desc_config_name("seg_scan_i32", cfg)
+        case(f"segmented scan/reduce config {name} n={n} offset={offset}")
+        desc.desc_config_set("seg_scan_i32", cls, cfg)
+        desc.desc_config_set("seg_reduce_i32", cls, cfg)
+        y = torch.full((n,), -5, dtype=torch.int32, device=dev())
+        desc.desc_scan_segmented_i32(xt, ot, y)
+        r = torch.full((off.size - 1,), 9, dtype=torch.int64, device=dev())
+        desc.desc_reduce_segmented_i32(xt, ot, r)
+        assert np.array_equal(y.cpu().numpy(), want), name
+        assert np.array_equal(r.cpu().numpy(), want_r), name
+
+
+def test_every_config_gaps_and_workload_slice(restore_seg_configs):
+    # starts late and ends early (positions outside every segment untouched),
+    # and a 2^22-element slice of the 4096-segment workload's lengths
+    x = workloads.int_uniform(200_000, seed=29)
+    off_gap = np.array([9000, 9000, 40_000, 40_001, 150_000, 150_000], np.int64)
+    lengths = workloads.segment_lengths(400, seed=10, max_len=1 << 14)
+    off_w = workloads.offsets_from_lengths(lengths)
+    xw = workloads.int_uniform(int(off_w[-1]), seed=11)
+    for cfg in range(desc.desc_config_count("seg_scan_i32")):
+        name = desc.desc_config_name("seg_scan_i32", cfg)
+        for xx, off, fill in ((x, off_gap, -77), (xw, off_w, 0)):
+            n = xx.size
+            case(f"segmented scan config {name} n={n} S={off.size - 1}")
+            for cls in range(4):
+                desc.desc_config_set("seg_scan_i32", cls, cfg)
+            for cls in range(4):
+                desc.desc_config_set("seg_reduce_i32", cls, cfg)
+            y = torch.full((n,), fill, dtype=torch.int32, device=dev())
+            r = torch.full((off.size - 1,), 9, dtype=torch.int64, device=dev())
+            desc.desc_scan_segmented_i32(to_dev(xx), to_dev(off), y)
+            desc.desc_reduce_segmented_i32(to_dev(xx), to_dev(off), r)
+            assert np.array_equal(y.cpu().numpy(), oracle.scan_segmented_i32(xx, off, fill=fill)), name
+            assert np.array_equal(r.cpu().numpy(), oracle.reduce_segmented_i32(xx, off)), name
