@@ -189,10 +189,10 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hip
 
 constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
                                    "b1024_r4_nt", "b512_r4_nt", "b256_r32_nt", "b512_r16_nt",
-                                   "b1024_r8_nt", "b512_r32_nt"};
+                                   "b1024_r8_nt", "b512_r32_nt", "b1024_r16_nt"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kScanI32, "scan_i32", 10, kNames, kDefaults), true);
+    (tune::register_op(tune::kScanI32, "scan_i32", 11, kNames, kDefaults), true);
 
 }  // namespace
 
@@ -216,6 +216,7 @@ hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStr
     case 7: return launch_scan<ScanCfg<512, 16, true>>(in, out, n, ws, s);
     case 8: return launch_scan<ScanCfg<1024, 8, true>>(in, out, n, ws, s);
     case 9: return launch_scan<ScanCfg<512, 32, true>>(in, out, n, ws, s);
+    case 10: return launch_scan<ScanCfg<1024, 16, true>>(in, out, n, ws, s);
     default: return launch_scan<ScanCfg<256, 8, true>>(in, out, n, ws, s);
   }
 }
