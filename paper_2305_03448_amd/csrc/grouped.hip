@@ -5,7 +5,8 @@
 // pointers, described in a device array.
 //
 //   plan kernel (one block): gives each problem a tile shape (128 x 128 when
-//     both M and N are at least 256, else 64 x 64), orders the problems with
+//     both M and N are at least 256, else 64 x 64; or 64 x 64 throughout, by
+//     the tuning table), orders the problems with
 //     the large tiles first (so the long tiles start early and the short ones
 //     fill in at the end), and writes the exclusive prefix of tile counts in
 //     that order with the total to the workspace.
@@ -36,7 +37,10 @@ struct GroupedWs {
   int32_t* big;          // [G] 1 if the problem uses the large tile (indexed by problem)
 };
 
-__device__ __forceinline__ bool is_big(const desc_gemm_problem& p) { return p.M >= 256 && p.N >= 256; }
+// A problem takes the large tile when both M and N are at least big_min.
+__device__ __forceinline__ bool is_big(const desc_gemm_problem& p, int64_t big_min) {
+  return p.M >= big_min && p.N >= big_min;
+}
 
 __device__ __forceinline__ int64_t tiles_of(const desc_gemm_problem& p, bool big) {
   if (p.M <= 0 || p.N <= 0 || p.K < 0) return 0;
@@ -68,7 +72,8 @@ __device__ __forceinline__ int64_t block_excl(int64_t v, int64_t* excl, int64_t*
 }
 
 __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_problem* probs,
-                                                              int64_t G, int64_t* total,
+                                                              int64_t G, int64_t big_min,
+                                                              int64_t* total,
                                                               int64_t* tile_start,
                                                               int32_t* order, int32_t* big) {
   __shared__ int64_t lds[kBlock / kWave];
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_pr
   int64_t nbig = 0;
   for (idx_t base = 0; base < G; base += kBlock) {
     const idx_t g = base + thread.index();
-    const bool b = g < G && is_big(pr[g]);
+    const bool b = g < G && is_big(pr[g], big_min);
     if (g < G) bg[g] = b;
     int64_t ex;
     const int64_t tot = block_excl(b ? 1 : 0, &ex, lds);
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_pr
   int64_t nsmall = 0;
   for (idx_t base = 0; base < G; base += kBlock) {
     const idx_t g = base + thread.index();
-    const bool s = g < G && !is_big(pr[g]);
+    const bool s = g < G && !is_big(pr[g], big_min);
     int64_t ex;
     const int64_t tot = block_excl(s ? 1 : 0, &ex, lds);
     if (s) ord[nbig + nsmall + ex] = (int32_t)g;
@@ -118,12 +123,15 @@ __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_pr
   }
 }
 
+// kBig: whether any problem may use the large tile (the LDS is sized for the
+// largest tile the launch can meet, which bounds how many blocks fit a CU).
+template <bool kBig>
 __global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_problem* probs,
                                                               int64_t G, const int64_t* total,
                                                               const int64_t* tile_start,
                                                               const int32_t* order,
                                                               const int32_t* big) {
-  __shared__ float lds[gemm_f32::lds_floats<BigTile>()];
+  __shared__ float lds[kBig ? gemm_f32::lds_floats<BigTile>() : gemm_f32::lds_floats<SmallTile>()];
   __shared__ int64_t s_slot;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_pr
     const GemmProblemF32 q{p.A, p.lda, p.B, p.ldb, p.C, p.ldc, p.M, p.N, p.K};
     const idx_t local = t - ts[slot];
     const bool vec = gemm_f32::vec_ok(p.A, p.lda, p.B, p.ldb);
-    if (b) {
+    if (kBig && b) {
       const idx_t tn = (p.N + 127) / 128;
       if (vec) gemm_f32::tile<BigTile, true>(q, local / tn, local % tn, lds);
       else gemm_f32::tile<BigTile, false>(q, local / tn, local % tn, lds);
@@ -172,6 +180,7 @@ GroupedWs carve(void* ws, int64_t G) {
   return r;
 }
 
+template <bool kBig>
 int persistent_grid() {
   static int cached[64] = {0};
   int dev = 0;
@@ -180,18 +189,22 @@ int persistent_grid() {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, grouped_gemm_kernel, kBlock, 0) !=
-            hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, grouped_gemm_kernel<kBig>, kBlock,
+                                                     0) != hipSuccess || per < 1)
       per = 1;
     cached[dev] = cus * per;
   }
   return cached[dev];
 }
 
-constexpr const char* kNames[] = {"tile128_or_64"};
-constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
+// Tile choice: 128 x 128 tiles for problems with M, N >= 256 and 64 x 64
+// otherwise, or 64 x 64 tiles throughout (more, smaller tiles balance better
+// over the CUs when the problems are small).
+constexpr const char* kNames[] = {"tile128_or_64", "tile64"};
+constexpr int kDefaults[tune::kClasses] = {1, 1, 1, 1};
+constexpr int64_t kBigMin[] = {256, INT64_MAX};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 1, kNames, kDefaults), true);
+    (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 2, kNames, kDefaults), true);
 
 }  // namespace
 
@@ -205,10 +218,16 @@ hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* 
                             hipStream_t s) {
   (void)kRegistered;
   const GroupedWs w = carve(ws, G);
-  hipLaunchKernelGGL(grouped_plan_kernel, dim3(1), dim3(kBlock), 0, s, problems, G, w.total,
-                     w.tile_start, w.order, w.big);
-  hipLaunchKernelGGL(grouped_gemm_kernel, dim3((unsigned)persistent_grid()), dim3(kBlock), 0, s,
-                     problems, G, w.total, w.tile_start, w.order, w.big);
+  // the size class is taken from the problem count
+  const int cfg = tune::get(tune::kGemmGrouped, tune::size_class(tune::kGemmGrouped, G));
+  hipLaunchKernelGGL(grouped_plan_kernel, dim3(1), dim3(kBlock), 0, s, problems, G,
+                     kBigMin[cfg == 1 ? 1 : 0], w.total, w.tile_start, w.order, w.big);
+  if (cfg == 1)
+    hipLaunchKernelGGL(grouped_gemm_kernel<false>, dim3((unsigned)persistent_grid<false>()),
+                       dim3(kBlock), 0, s, problems, G, w.total, w.tile_start, w.order, w.big);
+  else
+    hipLaunchKernelGGL(grouped_gemm_kernel<true>, dim3((unsigned)persistent_grid<true>()),
+                       dim3(kBlock), 0, s, problems, G, w.total, w.tile_start, w.order, w.big);
   return hipGetLastError();
 }
 

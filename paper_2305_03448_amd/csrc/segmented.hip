@@ -4,7 +4,7 @@
 //
 // Work is cut into units: segment s of length L_s gives ceil(L_s / UNIT)
 // units of at most UNIT consecutive elements (an empty segment gives none);
-// UNIT is 8K, 16K or 32K elements, picked per size class by the tuning table.
+// UNIT is 8K to 64K elements, picked per size class by the tuning table.
 //
 //   plan kernel (one block of 1024 threads, 4096 segments per pass): unit
 //     counts and their exclusive prefix over the segments, written to the
@@ -393,12 +393,13 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, const int64_t
   return hipGetLastError();
 }
 
-constexpr const char* kNames[] = {"unit8k", "unit16k", "unit32k"};
-constexpr int kReduceDefaults[tune::kClasses] = {0, 0, 0, 0};
+// The reduce has no 64K unit: holding 16 rounds in 1024 threads spills.
+constexpr const char* kNames[] = {"unit8k", "unit16k", "unit32k", "unit32k_w16", "unit64k_w16"};
+constexpr int kReduceDefaults[tune::kClasses] = {0, 0, 0, 1};
 constexpr int kScanDefaults[tune::kClasses] = {0, 0, 0, 2};
 const bool kRegistered =
-    (tune::register_op(tune::kSegReduceI32, "seg_reduce_i32", 3, kNames, kReduceDefaults),
-     tune::register_op(tune::kSegScanI32, "seg_scan_i32", 3, kNames, kScanDefaults), true);
+    (tune::register_op(tune::kSegReduceI32, "seg_reduce_i32", 4, kNames, kReduceDefaults),
+     tune::register_op(tune::kSegScanI32, "seg_scan_i32", 5, kNames, kScanDefaults), true);
 
 }  // namespace
 
@@ -417,6 +418,7 @@ hipError_t reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* off
   switch (tune::get(tune::kSegReduceI32, tune::size_class(tune::kSegReduceI32, n))) {
     case 1: return launch_reduce<UnitCfg<256, 16>>(in, n, offsets, S, out, ws, s);
     case 2: return launch_reduce<UnitCfg<512, 16>>(in, n, offsets, S, out, ws, s);
+    case 3: return launch_reduce<UnitCfg<1024, 8>>(in, n, offsets, S, out, ws, s);
     default: return launch_reduce<UnitCfg<256, 8>>(in, n, offsets, S, out, ws, s);
   }
 }
@@ -427,6 +429,8 @@ hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const 
   switch (tune::get(tune::kSegScanI32, tune::size_class(tune::kSegScanI32, n))) {
     case 1: return launch_scan<UnitCfg<256, 16>>(in, out, n, offsets, S, ws, s);
     case 2: return launch_scan<UnitCfg<512, 16>>(in, out, n, offsets, S, ws, s);
+    case 3: return launch_scan<UnitCfg<1024, 8>>(in, out, n, offsets, S, ws, s);
+    case 4: return launch_scan<UnitCfg<1024, 16>>(in, out, n, offsets, S, ws, s);
     default: return launch_scan<UnitCfg<256, 8>>(in, out, n, offsets, S, ws, s);
   }
 }

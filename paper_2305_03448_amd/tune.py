@@ -100,6 +100,21 @@ def _problems(op: str, dev):
                       desc.desc_reduce_segmented_i32(x, off, r, ws=ws))
                 nbytes = 4 * n
             out.append((desc.desc_size_class(op, n), f"n={n} S={S}", nbytes, fn))
+    elif op == "gemm_grouped":
+        # G problems with M, N, K uniform over {64, 128, ..., 1024}
+        for G in (64, 512):
+            dims = torch.randint(1, 17, (G, 3), device=dev, generator=g) * 64
+            probs = []
+            flops = 0
+            for M, N, K in dims.tolist():
+                probs.append((torch.randn(M, K, device=dev, generator=g),
+                              torch.randn(K, N, device=dev, generator=g),
+                              torch.empty(M, N, device=dev)))
+                flops += 2 * M * N * K
+            d = desc.grouped_descriptors(probs, dev)
+            ws = torch.empty(desc.desc_gemm_grouped_workspace(G), dtype=torch.uint8, device=dev)
+            fn = (lambda d=d, ws=ws, probs=probs: desc.desc_gemm_grouped(d, ws=ws))
+            out.append((desc.desc_size_class(op, G), f"G={G}", flops, fn))
     else:
         raise ValueError(f"no tuning problems for {op}")
     return out

@@ -49,10 +49,25 @@ def _run(pairs, pad=0):
     return [c.cpu().numpy() for _, _, c in dev_pairs], dev_pairs, d
 
 
-def test_grouped_integer_exact_mixed_shapes():
+@pytest.fixture
+def grouped_config(request):
+    """Force one tile configuration of the grouped GEMM for the test."""
+    cfg = request.param
+    for cls in range(4):
+        desc.desc_config_set("gemm_grouped", cls, cfg)
+    yield cfg
+    for cls in range(4):
+        desc.desc_config_set("gemm_grouped", cls, -1)
+
+
+CONFIGS = [0, 1]   # tile128_or_64, tile64
+
+
+@pytest.mark.parametrize("grouped_config", CONFIGS, indirect=True)
+def test_grouped_integer_exact_mixed_shapes(grouped_config):
     shapes = [(64, 64, 64), (1, 1, 1), (300, 257, 65), (256, 256, 16), (1024, 64, 128),
               (70, 513, 3), (257, 300, 129), (5, 7, 0)]
-    case(f"grouped integer {len(shapes)} problems")
+    case(f"grouped integer {len(shapes)} problems config {grouped_config}")
     pairs = _problems(shapes, 3, integer=True)
     outs, _, _ = _run(pairs)
     for (A, B), C in zip(pairs, outs):
@@ -102,8 +117,10 @@ def test_grouped_graph_replay():
             assert np.array_equal(C.cpu().numpy(), want)
 
 
-def test_grouped_workload_512():
-    case("grouped 512 problems (seeds 12/13/14)")
+@pytest.mark.parametrize("grouped_config", CONFIGS, indirect=True)
+def test_grouped_workload_512(grouped_config):
+    assert desc.desc_config_count("gemm_grouped") == len(CONFIGS)
+    case(f"grouped 512 problems (seeds 12/13/14) config {grouped_config}")
     shapes = workloads.grouped_shapes()
     pairs = workloads.grouped_operands(shapes)
     outs, _, _ = _run(pairs)

@@ -150,7 +150,9 @@ def test_every_config_tile_edges(offset, restore_seg_configs):
         name = desc.desc_config_name("seg_scan_i32", cfg)
         case(f"segmented scan/reduce config {name} n={n} offset={offset}")
         desc.desc_config_set("seg_scan_i32", cls, cfg)
-        desc.desc_config_set("seg_reduce_i32", cls, cfg)
+        # the reduce has fewer configurations; past its last, keep its last
+        rcfg = min(cfg, desc.desc_config_count("seg_reduce_i32") - 1)
+        desc.desc_config_set("seg_reduce_i32", cls, rcfg)
         y = torch.full((n,), -5, dtype=torch.int32, device=dev())
         desc.desc_scan_segmented_i32(xt, ot, y)
         r = torch.full((off.size - 1,), 9, dtype=torch.int64, device=dev())
@@ -175,7 +177,8 @@ def test_every_config_gaps_and_workload_slice(restore_seg_configs):
             for cls in range(4):
                 desc.desc_config_set("seg_scan_i32", cls, cfg)
             for cls in range(4):
-                desc.desc_config_set("seg_reduce_i32", cls, cfg)
+                desc.desc_config_set("seg_reduce_i32", cls,
+                                     min(cfg, desc.desc_config_count("seg_reduce_i32") - 1))
             y = torch.full((n,), fill, dtype=torch.int32, device=dev())
             r = torch.full((off.size - 1,), 9, dtype=torch.int64, device=dev())
             desc.desc_scan_segmented_i32(to_dev(xx), to_dev(off), y)
