@@ -4,8 +4,8 @@
 // in the kernel programming model, with raw index arithmetic.
 //
 // Each twin has the algorithm, tile shape, memory-access order, index types
-// (int64) and synchronisation of the view kernel it mirrors, for the one
-// configuration that kernel uses at 2^24 elements and above:
+// (int64) and synchronisation of the view kernel it mirrors, in one of that
+// kernel's configurations:
 //   reduce     256 threads, 4 int32x4 per lane per tile, non-temporal loads;
 //   scan       512 threads x 32 rounds x 4 int32 per tile (64K elements),
 //              non-temporal loads and stores, 256-word look-back window;

@@ -22,8 +22,8 @@ from paper_2305_03448_amd import build as _pkg_build  # noqa: E402
 SRC = os.path.join(HERE, "hand.hip")
 LIB_PATH = os.path.join(HERE, "libdesc_hand.so")
 
-# The one configuration of each library kernel that the twins mirror (the
-# library's choice at 2^24 elements and above).
+# The one configuration of each library kernel that the twins mirror; the
+# comparison sets the library to these.
 VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b512_r32_nt", "transpose_32": "t128"}
 
 
