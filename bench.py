@@ -21,7 +21,8 @@ Small kernels are timed as HIP-graph replays of many back-to-back launches,
 so that host launch overhead does not enter their time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--ops LIST]
-  --ops: comma list of copy,reduce,gemm,gemm8192,segmented,grouped,views ('' for none)
+  --ops: comma list of copy,reduce,gemm,gemm8192,segmented,grouped,views,variants
+         ('' for none)
 """
 from __future__ import annotations
 
@@ -180,6 +181,46 @@ def op_views(desc, torch, workloads, reps: int = 100):
     return results
 
 
+def op_variants(desc, torch, workloads, reps: int = 20):
+    """The paper's forms against the single-pass ones at 2^28 int32: the scan
+    as two kernels (tile sums, then carry and scan: 12 B per element) against
+    the single pass (8 B), and the block-wide reduction (one int64 per chunk of
+    E elements) against the full reduction.  Median times of `reps` runs."""
+    import statistics
+    n = 1 << 28
+    x = torch.from_numpy(workloads.int_uniform(n, seed=2)).cuda()
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    r = torch.empty(1, dtype=torch.int64, device="cuda")
+    blocks = {E: torch.empty((n + E - 1) // E, dtype=torch.int64, device="cuda")
+              for E in (4096, 65536)}
+
+    def median_us(fn):
+        for _ in range(3):
+            fn()
+        t = Timer(torch)
+        for _ in range(reps):
+            e = t.start(); fn(); t.stop(e)
+        torch.cuda.synchronize()
+        return statistics.median(a.elapsed_time(b) for a, b in t.pairs) * 1e3
+
+    out = {}
+    single = median_us(lambda: desc.desc_scan_i32(x, y1))
+    two = median_us(lambda: desc.desc_scan_two_pass_i32(x, y2))
+    out["scan_single_pass"] = {"us": round(single, 2), "GBs": round(8 * n / single / 1e3, 1)}
+    out["scan_two_kernels"] = {"us": round(two, 2), "GBs_algorithmic": round(8 * n / two / 1e3, 1),
+                               "GBs_moved": round(12 * n / two / 1e3, 1),
+                               "equal": bool(torch.equal(y1, y2))}
+    full = median_us(lambda: desc.desc_reduce_i32(x, r))
+    out["reduce_full"] = {"us": round(full, 2), "GBs": round(4 * n / full / 1e3, 1)}
+    for E, o in blocks.items():
+        t = median_us(lambda o=o, E=E: desc.desc_reduce_blocks_i32(x, E, o))
+        out[f"reduce_blocks_E{E}"] = {"us": round(t, 2), "GBs": round(4 * n / t / 1e3, 1),
+                                      "sum_equal": bool(int(o.sum().item()) == int(r.item()))}
+    del x, y1, y2
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(x_np, m_np, budget_s: float = 20.0):
     """Time the oracle's scan and transpose on the same workload (1 thread)."""
     import oracle
@@ -335,7 +376,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views",
+    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views,variants",
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -433,6 +474,9 @@ def main(argv=None):
         import oracle
         del x, y, m, mt, ws
         torch.cuda.empty_cache()
+    if "variants" in extra:
+        log("paper's forms: two-kernel scan, block-wide reduction")
+        result["ops"]["paper_forms_2^28"] = op_variants(desc, torch, workloads)
     if "views" in extra:
         log("view kernels against hand-indexed twins")
         result["ops"]["views_vs_hand"] = op_views(desc, torch, workloads)

@@ -91,6 +91,28 @@ desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
                           size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's own forms of the two operations above (Sec. 5), for
+ * comparison with the single-pass forms.
+ *
+ * Block-wide reduction: out[b] = exact int64 sum of in[b*E .. min(n,(b+1)*E))
+ * for b < ceil(n / E), one GPU block per chunk, each block combining its
+ * threads' sums in a split/synchronise tree (Sec. 2-3).  E (elements per
+ * block) must be a multiple of 1024 (DESC_ERR_SIZE otherwise); `out` holds
+ * ceil(n / E) int64.  n = 0 launches nothing.  No workspace.
+ *
+ * Two-kernel scan: the inclusive scan of desc_scan_i32 computed as kernel 1,
+ * the sum of every 65536-element tile into the workspace, then kernel 2, each
+ * tile's carry (the sum of the tile sums before it) and its scan.  It reads
+ * the input twice (3n words of traffic against 2n).  The workspace holds one
+ * word per tile, scratch between the two kernels (no initialisation).
+ * ---------------------------------------------------------------------- */
+desc_status desc_reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,
+                                   void* stream);
+size_t desc_scan_two_pass_i32_workspace(int64_t n);
+desc_status desc_scan_two_pass_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Transposition (Sec. 1, Listings 1-2; Sec. 5, "matrix transposition"):
  * `in` is a row-major rows x cols matrix of 32-bit words, `out` receives
  * the row-major cols x rows matrix with out[c][r] = in[r][c].  The words are

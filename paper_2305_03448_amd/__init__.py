@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(HERE, "libdesc.so")
 __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
-    "desc_scan_i32_workspace", "desc_scan_i32",
+    "desc_scan_i32_workspace", "desc_scan_i32", "desc_reduce_blocks_i32",
+    "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_copy_32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
     "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
@@ -52,6 +53,9 @@ SIGNATURES = {
     "desc_reduce_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
     "desc_scan_i32_workspace": (_SZ, [_I64]),
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
+    "desc_reduce_blocks_i32": (_ST, [_P, _I64, _I64, _P, _P]),
+    "desc_scan_two_pass_i32_workspace": (_SZ, [_I64]),
+    "desc_scan_two_pass_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_transpose_f32": (_ST, [_P, _P, _I64, _I64, _P]),
     "desc_transpose_batched_f32": (_ST, [_P, _P, _I64, _I64, _I64, _P]),
     "desc_copy_32": (_ST, [_P, _P, _I64, _P]),
@@ -207,6 +211,35 @@ def desc_scan_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = 
     w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
     _check(lib().desc_scan_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
            "desc_scan_i32")
+    return out
+
+
+# ------------------------------------------------------------------ the paper's forms
+def desc_reduce_blocks_i32(x: torch.Tensor, E: int, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[b] = exact int64 sum of x[b*E : (b+1)*E] (E a multiple of 1024)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int64, "out")
+    n = x.numel()
+    if E > 0 and out.numel() != (n + E - 1) // E:
+        raise ValueError("out must hold ceil(n / E) int64")
+    _check(lib().desc_reduce_blocks_i32(_ptr(x), n, E, _ptr(out), _stream(x, stream)),
+           "desc_reduce_blocks_i32")
+    return out
+
+
+def desc_scan_two_pass_i32_workspace(n: int) -> int:
+    return lib().desc_scan_two_pass_i32_workspace(n)
+
+
+def desc_scan_two_pass_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    """Inclusive scan of int32 ``x`` into ``out`` by the two-kernel method."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many elements as x")
+    n = x.numel()
+    w = _ws("scan_two_pass_i32", desc_scan_two_pass_i32_workspace(n), x, ws)
+    _check(lib().desc_scan_two_pass_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(),
+                                        _stream(x, stream)), "desc_scan_two_pass_i32")
     return out
 
 

@@ -147,6 +147,41 @@ desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
   return hip_status(desc::launch::scan_i32(in, out, n, ws, (hipStream_t)stream));
 }
 
+// ----------------------------------------------------------------- the paper's forms
+desc_status desc_reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,
+                                   void* stream) {
+  if ((in == nullptr || out == nullptr) && n > 0) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0 || E <= 0 || E % 1024 != 0) return DESC_ERR_SIZE;
+  if (n == 0) return DESC_OK;
+  const int64_t blocks = (n + E - 1) / E;
+  if (blocks > INT32_MAX) return DESC_ERR_SIZE;
+  const int64_t ob = blocks * 8;
+  DESC_TRY(check_device({in, out}));
+  if (misaligned(in, 4) || misaligned(out, 8)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, ob}, {in, nb})) return DESC_ERR_ALIAS;
+  return hip_status(desc::launch::reduce_blocks_i32(in, n, E, out, (hipStream_t)stream));
+}
+
+size_t desc_scan_two_pass_i32_workspace(int64_t n) {
+  return desc::launch::scan_two_pass_workspace(n < 0 ? 0 : n);
+}
+
+desc_status desc_scan_two_pass_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (ws == nullptr || ((in == nullptr || out == nullptr) && n > 0)) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (n == 0) return DESC_OK;
+  DESC_TRY(check_device({in, out, ws}));
+  if (misaligned(in, 4) || misaligned(out, 4) || misaligned(ws, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb}) || overlap({ws, (int64_t)ws_bytes}, {in, nb}) ||
+      overlap({ws, (int64_t)ws_bytes}, {out, nb}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < desc_scan_two_pass_i32_workspace(n)) return DESC_ERR_WORKSPACE;
+  return hip_status(desc::launch::scan_two_pass_i32(in, out, n, ws, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- transpose
 desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batch,
                                        int64_t rows, int64_t cols, void* stream) {

@@ -61,5 +61,12 @@ hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* 
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 
+// variants.hip
+hipError_t reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,
+                             hipStream_t s);
+size_t scan_two_pass_workspace(int64_t n);
+hipError_t scan_two_pass_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                             hipStream_t s);
+
 }  // namespace launch
 }  // namespace desc

@@ -104,6 +104,39 @@ def test_scan_checks(fake_pointers):
     assert L.desc_scan_i32_workspace(1 << 28) > L.desc_scan_i32_workspace(1 << 20)
 
 
+def test_reduce_blocks_checks(fake_pointers):
+    L = fake_pointers
+    st = lambda *a: L.desc_reduce_blocks_i32(*a, None)
+    n = 10_000                                                       # 3 chunks of 4096
+    assert st(D(0), 0, 4096, D(1 << 20)) == OK                       # empty: nothing to do
+    assert st(None, n, 4096, D(1 << 20)) == NULL
+    assert st(D(0), n, 4096, None) == NULL
+    assert st(D(0), -1, 4096, D(1 << 20)) == SIZE
+    assert st(D(0), n, 1000, D(1 << 20)) == SIZE                     # not a multiple of 1024
+    assert st(D(0), n, 0, D(1 << 20)) == SIZE
+    assert st(HOSTP, n, 4096, D(1 << 20)) == HOST
+    assert st(D(0), n, 4096, HOSTP) == HOST
+    assert st(D(2), n, 4096, D(1 << 20)) == ALIGN
+    assert st(D(0), n, 4096, D((1 << 20) + 4)) == ALIGN
+    assert st(D(0), n, 4096, D(4 * n - 16)) == ALIAS                 # 3 outputs reach into in
+
+
+def test_scan_two_pass_checks(fake_pointers):
+    L = fake_pointers
+    n = 100_000                                                      # 2 tiles of 65536
+    wsb = L.desc_scan_two_pass_i32_workspace(n)
+    assert wsb == 8
+    st = lambda *a: L.desc_scan_two_pass_i32(*a, None)
+    assert st(D(0), D(1 << 20), 0, D(1 << 24), wsb) == OK
+    assert st(D(0), D(1 << 20), n, None, wsb) == NULL
+    assert st(D(0), D(1 << 20), -1, D(1 << 24), wsb) == SIZE
+    assert st(D(0), D(1 << 20), n, HOSTP, wsb) == HOST
+    assert st(D(0), D(1 << 20), n, D((1 << 24) + 2), wsb) == ALIGN
+    assert st(D(0), D(4 * n - 4), n, D(1 << 24), wsb) == ALIAS
+    assert st(D(0), D(1 << 20), n, D(4 * n - 4), wsb) == ALIAS       # ws overlaps in
+    assert st(D(0), D(1 << 20), n, D(1 << 24), wsb - 1) == WS
+
+
 def test_transpose_checks(fake_pointers):
     L = fake_pointers
     st = L.desc_transpose_batched_f32
