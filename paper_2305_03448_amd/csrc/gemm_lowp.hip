@@ -167,7 +167,11 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 
 // One block per output row: absmax over the row, then encode, 4 consecutive
 // k per thread (16-byte loads and 4-byte stores when whole and aligned).
+// Rows of up to kRowCache * 1024 elements stay in registers between the two
+// phases, so the row is read once; longer rows are read again to encode.
 // q is rows_out x k_out (stride ldq); rows >= M and columns >= K get zero.
+constexpr int kRowCache = 8;   // float4 per thread
+
 __global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restrict__ A,
                                                             int64_t M, int64_t K, int64_t lda,
                                                             uint8_t* __restrict__ q,
@@ -190,19 +194,13 @@ __global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restr
     }
     return v;
   };
-  float amax = 0.f;
-  for (idx_t c = 4 * thread.index(); c < K; c += 4 * kBlock) {
-    const f32x4 v = load4(c);
+  auto encode = [&](idx_t c, const f32x4& v, float inv) {
+    // positions past the row (padding) get code 0
+    uint32_t keep = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fabsf(v[j]));
-  }
-  amax = block_max(amax, red);
-  const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
-  for (idx_t c = 4 * thread.index(); c < k_out; c += 4 * kBlock) {
-    const f32x4 v = load4(c);
-    u8x4 e;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) e[j] = (r < M && c + j < K) ? lowp::e4m3_rne_sat(v[j] * inv) : 0;
+    for (int j = 0; j < 4; ++j) keep |= (r < M && c + j < K) ? (0xffu << (8 * j)) : 0u;
+    const uint32_t w = lowp::e4m3x4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv) & keep;
+    const u8x4 e = __builtin_bit_cast(u8x4, w);
     if (vec_out && c + 4 <= k_out) {
       *(u8x4*)&qr[c] = e;
     } else {
@@ -210,28 +208,88 @@ __global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restr
       for (int j = 0; j < 4; ++j)
         if (c + j < k_out) qr[c + j] = e[j];
     }
+  };
+  const bool cached = k_out <= 4 * kBlock * kRowCache && K <= k_out;
+  float amax = 0.f;
+  f32x4 cache[kRowCache];
+  if (cached && vec_in && r < M && K % 4 == 0) {
+    // Branch-free: every load reads a valid address (column 0 past the end
+    // of the row) and the value is dropped by a select, so the loads are all
+    // in flight together instead of one conditional load after another.
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < kRowCache; ++i) {
+      const idx_t c = 4 * (thread.index() + kBlock * i);
+      const f32x4 v = *(const f32x4*)&a.at(r, c < K ? c : 0);
+      cache[i] = c < K ? v : zero;
+    }
+#pragma unroll
+    for (int i = 0; i < kRowCache; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fabsf(cache[i][j]));
+  } else if (cached) {
+#pragma unroll
+    for (int i = 0; i < kRowCache; ++i) {
+      const idx_t c = 4 * (thread.index() + kBlock * i);
+      cache[i] = c < K ? load4(c) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fabsf(cache[i][j]));
+    }
+  } else {
+    for (idx_t c = 4 * thread.index(); c < K; c += 4 * kBlock) {
+      const f32x4 v = load4(c);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) amax = fmaxf(amax, fabsf(v[j]));
+    }
+  }
+  amax = block_max(amax, red);
+  const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
+  if (cached) {
+#pragma unroll
+    for (int i = 0; i < kRowCache; ++i) {
+      const idx_t c = 4 * (thread.index() + kBlock * i);
+      if (c < k_out) encode(c, cache[i], inv);
+    }
+  } else {
+    for (idx_t c = 4 * thread.index(); c < k_out; c += 4 * kBlock) encode(c, load4(c), inv);
   }
   if (thread.index() == 0) array(scale, row.count())[r] = amax / 448.0f;
 }
 
 // Partial column maxima of |B| over K slices: part[s][n] for slice s of
-// `rows_per` rows; grid (column blocks of 256, slices).
+// `rows_per` rows; grid (column blocks of 1024, slices).  Thread = 4
+// consecutive columns, read as one 16-byte vector per row when aligned;
+// eight rows are loaded before they are combined.
 __global__ __launch_bounds__(kBlock) void colmax_partial_kernel(const float* __restrict__ B,
                                                                 int64_t K, int64_t N,
                                                                 int64_t ldb, int64_t rows_per,
                                                                 float* __restrict__ part,
-                                                                int64_t ldp) {
+                                                                int64_t ldp, bool vec_in) {
   auto cb = block_x();
   auto sl = block_y();
   auto thread = thread_x<kBlock>();
   auto b = matrix(B, K, ldb);
-  const idx_t n = cb.index() * kBlock + thread.index();
+  const idx_t n = (cb.index() * kBlock + thread.index()) * 4;
   const idx_t k0 = sl.index() * rows_per;
   const idx_t k1 = k0 + rows_per < K ? k0 + rows_per : K;
-  float m = 0.f;
-  if (n < N)
-    for (idx_t k = k0; k < k1; ++k) m = fmaxf(m, fabsf(b.at(k, n)));
-  if (n < ldp) matrix(part, sl.count(), ldp).at(sl.index(), n) = m;
+  f32x4 m = {0.f, 0.f, 0.f, 0.f};
+  if (vec_in && n + 4 <= N) {
+#pragma unroll 8
+    for (idx_t k = k0; k < k1; ++k) {
+      const f32x4 v = *(const f32x4*)&b.at(k, n);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[j] = fmaxf(m[j], fabsf(v[j]));
+    }
+  } else {
+    for (idx_t k = k0; k < k1; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (n + j < N) m[j] = fmaxf(m[j], fabsf(b.at(k, n + j)));
+  }
+  auto pr = matrix(part, sl.count(), ldp).idx(sl.index());
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (n + j < ldp) pr[n + j] = m[j];
 }
 
 // Encode 64 x 64 tiles of B with their column scales and write them
@@ -292,11 +350,12 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
       for (int j = 0; j < 4; ++j)
         v[j] = (k0 + r < K && n0 + c + j < N) ? b.at(k0 + r, n0 + c + j) : 0.f;
     }
-    u8x4 e;
+    uint32_t keep = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      e[j] = (k0 + r < K && n0 + c + j < N) ? lowp::e4m3_rne_sat(v[j] * inv_s[c + j]) : 0;
-    *(u8x4*)&tile.at(r, c) = e;
+    for (int j = 0; j < 4; ++j) keep |= (k0 + r < K && n0 + c + j < N) ? (0xffu << (8 * j)) : 0u;
+    const uint32_t w = lowp::e4m3x4(v[0] * inv_s[c], v[1] * inv_s[c + 1], v[2] * inv_s[c + 2],
+                                    v[3] * inv_s[c + 3]) & keep;
+    *(u8x4*)&tile.at(r, c) = __builtin_bit_cast(u8x4, w);
   }
   sync(thread);
 #pragma unroll
@@ -317,8 +376,8 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
 }
 
 int64_t colmax_slices(int64_t K, int64_t N) {
-  const int64_t cblocks = (N + kBlock - 1) / kBlock;
-  int64_t s = 1024 / (cblocks > 0 ? cblocks : 1);
+  const int64_t cblocks = (N + 4 * kBlock - 1) / (4 * kBlock);
+  int64_t s = 256 / (cblocks > 0 ? cblocks : 1);
   const int64_t kmax = (K + 63) / 64;
   if (s > kmax) s = kmax;
   return s < 1 ? 1 : s;
@@ -432,8 +491,9 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
                            int64_t ldq, float* scale, void* ws, hipStream_t s) {
   const int64_t S = colmax_slices(K, N), rows_per = (K + S - 1) / S;
   float* part = (float*)ws;
-  hipLaunchKernelGGL(colmax_partial_kernel, dim3((unsigned)((N + kBlock - 1) / kBlock), (unsigned)S),
-                     dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N);
+  hipLaunchKernelGGL(colmax_partial_kernel,
+                     dim3((unsigned)((N + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
+                     dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N, f4_ok(B, ldb));
   hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)((N + 63) / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale,
                      f4_ok(B, ldb), w_ok(qt, ldq, 1));
@@ -472,9 +532,9 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
   hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)L.Mp), dim3(kBlock), 0, s, A, M, K, lda, qa,
                      L.Kp, L.Kp, sa, f4_ok(A, lda), true);
   const int64_t S = colmax_slices(K, N), rows_per = (K + S - 1) / S;
-  hipLaunchKernelGGL(colmax_partial_kernel, dim3((unsigned)(L.Np / kBlock + (L.Np % kBlock != 0)),
-                                                 (unsigned)S),
-                     dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, L.Np);
+  hipLaunchKernelGGL(colmax_partial_kernel,
+                     dim3((unsigned)((L.Np + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
+                     dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, L.Np, f4_ok(B, ldb));
   hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)(L.Np / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb,
                      f4_ok(B, ldb), true);

@@ -10,6 +10,8 @@
 // mantissa bits, no infinities, S.1111.111 is NaN, so the largest finite
 // magnitude is 448; subnormals are m * 2^-9.  Encoding rounds to nearest
 // even and saturates magnitudes above 448 (infinities included) to 448.
+// e4m3_rne_sat is the encoding written out; e4m3x4 reaches the same codes
+// four at a time with the hardware conversion.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -53,6 +55,22 @@ __device__ __forceinline__ uint8_t e4m3_rne_sat(float x) {
   uint32_t E = (uint32_t)(e + 7);
   if (q == 8u) { q = 0u; ++E; }
   return (uint8_t)(sign | (E << 3) | q);                    // |x| < 448 keeps E.q <= 15.6
+}
+
+// Four values at once with the format conversion instruction of gfx950
+// (v_cvt_pk_fp8_f32: OCP E4M3, round to nearest even; a, b, c, d land in
+// bytes 0..3).  Compared with e4m3_rne_sat over every binary32 input it
+// gives the same code for every finite |x| <= 448, and the NaN code instead
+// of the saturated one from 464 up, so a group holding a NaN or a magnitude
+// above 448 is encoded by e4m3_rne_sat instead.
+__device__ __forceinline__ uint32_t e4m3x4(float a, float b, float c, float d) {
+  if (fabsf(a) <= 448.0f && fabsf(b) <= 448.0f && fabsf(c) <= 448.0f && fabsf(d) <= 448.0f) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (uint32_t)w;
+  }
+  return (uint32_t)e4m3_rne_sat(a) | ((uint32_t)e4m3_rne_sat(b) << 8) |
+         ((uint32_t)e4m3_rne_sat(c) << 16) | ((uint32_t)e4m3_rne_sat(d) << 24);
 }
 
 }  // namespace lowp

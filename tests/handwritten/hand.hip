@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "common.hpp"
+#include "lowp.hpp"
 #include "wave.hpp"
 
 namespace hand {
@@ -305,6 +306,39 @@ __global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restri
   }
 }
 
+// ---------------------------------------------------------------- e4m3 check
+// The library's e4m3 quantisers use the hardware conversion for groups whose
+// magnitudes are all finite and <= 448 and the software encoder otherwise.
+// This kernel compares the two over all 2^32 binary32 inputs: counts[0]
+// gets the disagreements at finite |x| <= 448, counts[1] the others.  One
+// atomic per block and counter.
+constexpr int kCvtThreads = 256, kCvtPer = 64;
+constexpr uint64_t kCvtBlocks = (1ull << 32) / (kCvtThreads * kCvtPer);
+
+__global__ __launch_bounds__(kCvtThreads) void e4m3_all_inputs(unsigned long long* counts) {
+  __shared__ unsigned long long s_in, s_out;
+  if (threadIdx.x == 0) { s_in = 0; s_out = 0; }
+  __syncthreads();
+  unsigned long long n_in = 0, n_out = 0;
+  const uint64_t base = (uint64_t)blockIdx.x * kCvtThreads * kCvtPer;
+  for (int j = 0; j < kCvtPer; ++j) {
+    const uint32_t i = (uint32_t)(base + (uint64_t)j * kCvtThreads + threadIdx.x);
+    const float x = __uint_as_float(i);
+    const uint32_t sw = desc::lowp::e4m3_rne_sat(x);
+    const uint32_t hw = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, x, 0, false) & 0xffu;
+    if (sw != hw) {
+      if (fabsf(x) <= 448.0f) ++n_in; else ++n_out;
+    }
+  }
+  atomicAdd(&s_in, n_in);
+  atomicAdd(&s_out, n_out);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&counts[0], s_in);
+    atomicAdd(&counts[1], s_out);
+  }
+}
+
 }  // namespace hand
 
 // ---------------------------------------------------------------- C interface
@@ -366,6 +400,13 @@ int hand_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols, 
   else
     hipLaunchKernelGGL(hand::transpose32_hand<false>, grid, dim3(256), 0, s,
                        (const uint32_t*)in, (uint32_t*)out, rows, cols);
+  return (int)hipGetLastError();
+}
+
+// counts: two zeroed unsigned 64-bit counters in GPU memory.
+int hand_e4m3_all_inputs(unsigned long long* counts, hipStream_t s) {
+  hipLaunchKernelGGL(hand::e4m3_all_inputs, dim3((unsigned)hand::kCvtBlocks),
+                     dim3(hand::kCvtThreads), 0, s, counts);
   return (int)hipGetLastError();
 }
 

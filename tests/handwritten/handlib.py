@@ -1,4 +1,5 @@
-"""Build and ctypes binding of the hand-indexed twin kernels (hand.hip).
+"""Build and ctypes binding of the hand-indexed twin kernels (hand.hip) and
+of the exhaustive check of the e4m3 conversion the quantisers rely on.
 
 The twins are the baseline of the view-layer comparison: the same reduce,
 scan and transpose algorithms as the library's view kernels, with the index
@@ -57,6 +58,7 @@ def lib() -> ctypes.CDLL:
                                         c.c_void_p]),
             ("hand_transpose_f32", c.c_int, [c.c_void_p, c.c_void_p, c.c_int64, c.c_int64,
                                              c.c_void_p]),
+            ("hand_e4m3_all_inputs", c.c_int, [c.c_void_p, c.c_void_p]),
         ):
             f = getattr(L, name)
             f.restype, f.argtypes = res, args
@@ -117,3 +119,14 @@ def transpose_f32(x, out):
     _check(lib().hand_transpose_f32(x.data_ptr(), out.data_ptr(), x.shape[0], x.shape[1],
                                     _stream(x)), "hand_transpose_f32")
     return out
+
+
+def e4m3_all_inputs():
+    """(disagreements at finite |x| <= 448, other disagreements) between the
+    hardware e4m3 conversion and the library's software encoder over all
+    2^32 binary32 inputs."""
+    import torch
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    _check(lib().hand_e4m3_all_inputs(counts.data_ptr(), _stream(counts)), "hand_e4m3_all_inputs")
+    torch.cuda.synchronize()
+    return int(counts[0].item()), int(counts[1].item())

@@ -179,6 +179,57 @@ def test_quant_e4m3_rows_cols_bit_exact(M, K):
     assert np.array_equal(st.cpu().numpy(), sb)
 
 
+def _e4m3_rounding_points():
+    """Every e4m3 code value, every midpoint between neighbouring codes (the
+    ties) and the floats one ulp either side of each, over the whole range
+    including subnormals, with both signs; then random bit patterns of
+    magnitude <= 448.  Each row also holds 448, so its scale is 1 and the
+    encoder sees these values unscaled."""
+    pts = []
+    for e in range(-9, 9):                     # code spacing 2^(e-3) in [2^e, 2^(e+1))
+        step = 2.0 ** (max(e, -6) - 3)
+        lo = 0.0 if e == -9 else 2.0 ** e
+        v = np.arange(lo, min(2.0 ** (e + 1), 448.0) + step, step / 2)
+        pts.append(v)
+    p = np.unique(np.concatenate(pts)).astype(np.float32)
+    p = p[p <= 448.0]
+    up = np.nextafter(p, np.float32(np.inf))
+    dn = np.nextafter(p, np.float32(0))
+    p = np.unique(np.concatenate([p, up[up <= 448.0], dn]))
+    p = np.concatenate([p, -p])
+    g = workloads.rng(77)
+    bits = g.integers(0, 0x43e00001, 1 << 20, dtype=np.uint32) | \
+        (g.integers(0, 2, 1 << 20, dtype=np.uint32) << 31)
+    return np.concatenate([p, bits.view(np.float32)])
+
+
+def test_quant_e4m3_every_rounding_point():
+    # the quantisers encode with the hardware conversion where it agrees with
+    # the format definition (finite magnitudes up to 448): checked here on
+    # all ties and code boundaries against the oracle's encoder
+    vals = _e4m3_rounding_points()
+    K = 4096
+    rows = (vals.size + K - 2) // (K - 1)
+    A = np.zeros((rows, K), np.float32)
+    A[:, 0] = 448.0
+    flat = np.zeros(rows * (K - 1), np.float32)
+    flat[:vals.size] = vals
+    A[:, 1:] = flat.reshape(rows, K - 1)
+    case(f"quant e4m3 rounding points {vals.size} values")
+    q, _, sa = oracle.quant_rows_e4m3(A)
+    assert np.all(sa == 1.0)
+    qd = torch.empty((rows, K), dtype=torch.uint8, device=dev())
+    sd = torch.empty(rows, dtype=torch.float32, device=dev())
+    desc.desc_quant_e4m3_rows(to_dev(A), qd, sd)
+    assert np.array_equal(qd.cpu().numpy(), q)
+    B = np.ascontiguousarray(A.T)
+    qc, _, _ = oracle.quant_cols_e4m3(B)
+    qt = torch.empty((rows, K), dtype=torch.uint8, device=dev())
+    st = torch.empty(rows, dtype=torch.float32, device=dev())
+    desc.desc_quant_e4m3_cols(to_dev(B), qt, st)
+    assert np.array_equal(qt.cpu().numpy(), qc.T)
+
+
 # ------------------------------------------------------------------ precision modes
 def _check_against(C, R, D, tol, what):
     err = np.abs(C.astype(np.float64) - R) / np.maximum(D, 1e-300)
