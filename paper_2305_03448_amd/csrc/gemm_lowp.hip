@@ -385,8 +385,8 @@ int64_t colmax_slices(int64_t K, int64_t N) {
 
 // ------------------------------------------------------------------ GEMM launch
 template <class C>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(NtOperands p, int64_t tiles_m,
-                                                      int64_t tiles_n) {
+__global__ __launch_bounds__(C::threads) void gemm_nt_kernel(NtOperands p, int64_t tiles_m,
+                                                             int64_t tiles_n) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[C::lds_bytes];
   const idx_t t = gemm_f32::xcd_tile(block_x(), tiles_m, tiles_n);
   gemm_nt::tile<C>(p, t / tiles_n, t % tiles_n, lds);
@@ -395,7 +395,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(NtOperands p, int64_t tile
 template <class C>
 hipError_t launch_nt(const NtOperands& p, int64_t Mp, int64_t Np, hipStream_t s) {
   const int64_t tm = Mp / C::bm, tn = Np / C::bn;
-  hipLaunchKernelGGL((gemm_nt_kernel<C>), dim3((unsigned)(tm * tn)), dim3(256), 0, s, p, tm, tn);
+  hipLaunchKernelGGL((gemm_nt_kernel<C>), dim3((unsigned)(tm * tn)), dim3(C::threads), 0, s, p, tm,
+                     tn);
   return hipGetLastError();
 }
 
@@ -438,14 +439,15 @@ unsigned grid_for(int64_t items) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
+// "_w8": eight waves (2 x 4) share the tile instead of four (2 x 2).
 constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32",
-                                      "m256n256k32_d1"};
+                                      "m256n256k32_d1", "m256n256k32_w8d1"};
 constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
-                                     "m128n256k128", "m256n128k64"};
+                                     "m128n256k128", "m256n128k64", "m256n256k64_w8d1"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 4, kNamesBf16, kDefaults),
-     tune::register_op(tune::kGemmFp8, "gemm_fp8", 5, kNamesFp8, kDefaults), true);
+    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 5, kNamesBf16, kDefaults),
+     tune::register_op(tune::kGemmFp8, "gemm_fp8", 6, kNamesFp8, kDefaults), true);
 
 }  // namespace
 
@@ -518,6 +520,7 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
     case 1: return launch_nt<NtCfg<256, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
     case 2: return launch_nt<NtCfg<128, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
     case 3: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1>>(p, L.Mp, L.Np, s);
+    case 4: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
   }
 }
@@ -544,6 +547,7 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
     case 2: return launch_nt<NtCfg<256, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
     case 3: return launch_nt<NtCfg<128, 256, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
     case 4: return launch_nt<NtCfg<256, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
+    case 5: return launch_nt<NtCfg<256, 256, 64, Fp8Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
   }
 }

@@ -49,24 +49,29 @@ struct Fp8Mode {
 
 // kDepth: stages in flight in registers (1: the next stage's loads are
 // issued before the current stage's matrix ops; 2: two stages ahead, which
-// needs a second register staging set).
-template <int kBM, int kBN, int kBKB, class Mode, int kDepth = 2>
+// needs a second register staging set).  kWM x kWN waves share the tile,
+// each computing a (kBM / kWM) x (kBN / kWN) part of it.
+template <int kBM, int kBN, int kBKB, class Mode, int kDepth = 2, int kWM = 2, int kWN = 2>
 struct NtCfg {
   using mode = Mode;
   static constexpr int bm = kBM, bn = kBN, bkb = kBKB, depth = kDepth;
-  static constexpr int wtm = kBM / 2, wtn = kBN / 2;
+  static constexpr int wm = kWM, wn = kWN, threads = 64 * kWM * kWN;
+  static constexpr int wtm = kBM / kWM, wtn = kBN / kWN;
   static constexpr int fm = wtm / 32, fn = wtn / 32;
   static constexpr int chunks = kBKB / 16;                 // 16-byte chunks per row
   static constexpr int rows_per_256 = 256 / kBKB;          // rows sharing one bank period
   static constexpr int pitch = kBKB;
   static constexpr int steps = kBKB / Mode::step_bytes;
-  static constexpr int a_chunks = kBM * kBKB / 16 / 256;   // 16-byte chunks per thread per plane
-  static constexpr int b_chunks = kBN * kBKB / 16 / 256;
+  static constexpr int a_chunks = kBM * kBKB / 16 / threads;   // 16-byte chunks per thread per plane
+  static constexpr int b_chunks = kBN * kBKB / 16 / threads;
   static constexpr int plane_bytes = (kBM + kBN) * pitch;
   static constexpr int stage_bytes = Mode::planes * plane_bytes;
   static constexpr int lds_bytes = 2 * stage_bytes;
   static_assert(steps >= 1 && kBKB % Mode::step_bytes == 0, "stage holds whole steps");
-  static_assert(a_chunks >= 1 && b_chunks >= 1, "tile too small for 256 threads");
+  static_assert(a_chunks >= 1 && b_chunks >= 1, "tile too small for the threads");
+  static_assert(a_chunks * threads * 16 == kBM * kBKB && b_chunks * threads * 16 == kBN * kBKB,
+                "stage divides evenly among the threads");
+  static_assert(fm >= 1 && fn >= 1, "wave tile holds whole 32 x 32 fragments");
 };
 
 namespace gemm_nt {
@@ -95,11 +100,12 @@ template <class C>
 __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, uint8_t* lds) {
   using Mode = typename C::mode;
   constexpr int P = Mode::planes, LB = Mode::lane_bytes, BKB = C::bkb;
-  auto thread = thread_x<256>();
-  auto wv = wave_of_block<256>();
+  constexpr int T = C::threads;
+  auto thread = thread_x<T>();
+  auto wv = wave_of_block<T>();
   const int lane = (int)lane_of_wave().index();
   const int half = lane / 32, col32 = lane % 32;
-  const int wm = (int)wv.index() / 2, wn = (int)wv.index() % 2;
+  const int wm = (int)wv.index() / C::wn, wn = (int)wv.index() % C::wn;
   const idx_t m0 = tm * C::bm, n0 = tn * C::bn;
 
   // LDS: [stage][plane][A rows then B rows][chunks] of 16 bytes, swizzled
@@ -113,7 +119,7 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     u32x4 a[P][C::a_chunks], b[P][C::b_chunks];
   };
   Stage R0, R1;
-  // 16-byte chunk q of a stage (q = thread + 256 i) is chunk q % CPR of row
+  // 16-byte chunk q of a stage (q = thread + T i) is chunk q % CPR of row
   // q / CPR: consecutive lanes read consecutive bytes of a row.
   constexpr int CPR = C::chunks;
   auto load = [&](idx_t k0b, Stage& R) {
@@ -123,12 +129,12 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
       auto bg = matrix(p.b[pl], 0, p.row_bytes);
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
-        const int q = (int)thread.index() + 256 * i;
+        const int q = (int)thread.index() + T * i;
         R.a[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
-        const int q = (int)thread.index() + 256 * i;
+        const int q = (int)thread.index() + T * i;
         R.b[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
       }
     }
@@ -139,12 +145,12 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
       auto s = plane(stage, pl);
 #pragma unroll
       for (int i = 0; i < C::a_chunks; ++i) {
-        const int q = (int)thread.index() + 256 * i;
+        const int q = (int)thread.index() + T * i;
         s.at(q / CPR, q % CPR) = R.a[pl][i];
       }
 #pragma unroll
       for (int i = 0; i < C::b_chunks; ++i) {
-        const int q = (int)thread.index() + 256 * i;
+        const int q = (int)thread.index() + T * i;
         s.at(C::bm + q / CPR, q % CPR) = R.b[pl][i];
       }
     }
@@ -250,46 +256,57 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     }
   }
 
-  // Epilogue.  The scales are padded to whole tiles, so all of this lane's
-  // scale loads are issued together, before any store; a tile wholly inside
-  // C stores without guards.
+  // Epilogue.  The scales are padded to whole tiles, so a lane's scale loads
+  // are issued together, before its stores: all of them when the wave tile
+  // has at most two fragment rows, one fragment row at a time otherwise (the
+  // row scales of four fragment rows would take 64 registers).  A tile wholly
+  // inside C stores without guards.
   auto c_g = matrix(p.C, p.M, p.ldc);
-  float sav[C::fm][16], sbv[C::fn];
+  constexpr int EB = C::fm > 2 ? 1 : C::fm;   // fragment rows per batch
+  const bool full = m0 + C::bm <= p.M && n0 + C::bn <= p.N;
+  float sbv[C::fn];
   if constexpr (Mode::scaled) {
-    auto sa = array(p.sa, 0);
     auto sb = array(p.sb, 0);
-#pragma unroll
-    for (int i = 0; i < C::fm; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) sav[i][r] = sa[m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane)];
 #pragma unroll
     for (int j = 0; j < C::fn; ++j) sbv[j] = sb[n0 + wn * C::wtn + j * 32 + col32];
   }
-  auto value = [&](int i, int j, int r) {
-    float v = acc[i][j][r];
-    if constexpr (Mode::scaled) v = (v * sav[i][r]) * sbv[j];
-    return v;
-  };
-  if (m0 + C::bm <= p.M && n0 + C::bn <= p.N) {
 #pragma unroll
-    for (int i = 0; i < C::fm; ++i)
+  for (int i0 = 0; i0 < C::fm; i0 += EB) {
+    float sav[EB][16];
+    if constexpr (Mode::scaled) {
+      auto sa = array(p.sa, 0);
 #pragma unroll
-      for (int j = 0; j < C::fn; ++j)
+      for (int i = 0; i < EB; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          c_g.at(m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane),
-                 n0 + wn * C::wtn + j * 32 + col32) = value(i, j, r);
-  } else {
+          sav[i][r] = sa[m0 + wm * C::wtm + (i0 + i) * 32 + mfma::acc_row(r, lane)];
+    }
+    auto value = [&](int i, int j, int r) {
+      float v = acc[i0 + i][j][r];
+      if constexpr (Mode::scaled) v = (v * sav[i][r]) * sbv[j];
+      return v;
+    };
+    if (full) {
 #pragma unroll
-    for (int i = 0; i < C::fm; ++i)
+      for (int i = 0; i < EB; ++i)
 #pragma unroll
-      for (int j = 0; j < C::fn; ++j)
+        for (int j = 0; j < C::fn; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
-          const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
-          if (row < p.M && col < p.N) c_g.at(row, col) = value(i, j, r);
-        }
+          for (int r = 0; r < 16; ++r)
+            c_g.at(m0 + wm * C::wtm + (i0 + i) * 32 + mfma::acc_row(r, lane),
+                   n0 + wn * C::wtn + j * 32 + col32) = value(i, j, r);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EB; ++i)
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const idx_t row = m0 + wm * C::wtm + (i0 + i) * 32 + mfma::acc_row(r, lane);
+            const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+            if (row < p.M && col < p.N) c_g.at(row, col) = value(i, j, r);
+          }
+    }
   }
 }
 
