@@ -14,6 +14,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "access_check.hpp"
 #include "layouts.hpp"
 
 using namespace desc;
@@ -323,6 +324,133 @@ int main(int argc, char** argv) {
   transpose_case(std::integral_constant<int, 32>{});
   transpose_case(std::integral_constant<int, 64>{});
   transpose_case(std::integral_constant<int, 128>{});
+
+  // --- access checking over the kernels' own maps (access_check.hpp) ----------
+  // Listing 1 as printed: the 256 threads of a 32 x 8 block write tmp through
+  // the racy index in one interval; the corrected index writes disjointly.
+  {
+    std::vector<float> tmp(1024);
+    access_check::Checker racy, fixed;
+    for (int j = 0; j < 32; j += 8)
+      for (int y = 0; y < 8; ++y)
+        for (int x = 0; x < 32; ++x) {
+          racy.write(0, y * 32 + x, &tmp[y + j * 32 + x]);
+          fixed.write(0, y * 32 + x, &tmp[(y + j) * 32 + x]);
+        }
+    check(!racy.conflicts().empty() && fixed.conflicts().empty(),
+          "access_check_listing1_racy_conflicts_corrected_clean",
+          std::to_string(racy.conflicts().size()) + " conflicts");
+  }
+  // rev_per_block (Sec. 2): each thread writes arr[[thread]] and reads
+  // arr.rev[[thread]], which another thread writes: a conflict unless a
+  // barrier separates the write from the read.
+  {
+    const int n = 64;
+    std::vector<int> arr(n);
+    access_check::Checker no_sync, with_sync;
+    for (int t = 0; t < n; ++t)
+      for (auto* c : {&no_sync, &with_sync})
+        c->write(0, t, &array(arr.data(), n).select(R<Level::Thread>(t, n)).get());
+    with_sync.sync(0);
+    for (int t = 0; t < n; ++t)
+      for (auto* c : {&no_sync, &with_sync})
+        c->read(0, t, &array(arr.data(), n).reverse().select(R<Level::Thread>(t, n)).get());
+    check(no_sync.conflicts().size() == (size_t)n && with_sync.conflicts().empty(),
+          "access_check_rev_per_block_needs_barrier");
+  }
+  // The transposition kernel: global reads and LDS writes, a barrier, LDS
+  // reads and global writes; each block has its own LDS tile.  Clean as
+  // written; without the barrier the LDS reads race the writes of other
+  // threads of the block.
+  auto transpose_access = [&](auto Tc, bool barrier) {
+    constexpr int T = decltype(Tc)::value;
+    constexpr int TX = T / 4, TY = 256 / TX, IT = T / TY;
+    const int rows = 2 * T, cols = 2 * T, nb = 4;
+    std::vector<unsigned> in(rows * cols), out(rows * cols);
+    std::vector<std::vector<unsigned>> lds(nb, std::vector<unsigned>(T * (T + 1)));
+    access_check::Checker c;
+    for (int by = 0; by < 2; ++by)
+      for (int bx = 0; bx < 2; ++bx) {
+        const long blk = by * 2 + bx;
+        auto bY = R<Level::Block>(by, 2), bX = R<Level::Block>(bx, 2);
+        auto tile = matrix(lds[blk].data(), T, T + 1).template fst<1>(T);
+        auto inm = matrix((u32x4*)in.data(), rows, cols / 4);
+        auto outm = matrix((u32x4*)out.data(), cols, rows / 4);
+        for (int y = 0; y < TY; ++y)
+          for (int x = 0; x < TX; ++x) {
+            auto tY = R<Level::Thread>(y, TY), tX = R<Level::Thread>(x, TX);
+            auto a = layout::tile_rows<T, IT>(inm, bY, bX, tY, tX);
+            auto l = layout::lds_rows<T, IT>(tile, tY, tX);
+            const long who = blk * 256 + y * TX + x;
+            for (int i = 0; i < IT; ++i) {
+              c.read(blk, who, &a[i]);
+              for (int k = 0; k < 4; ++k) c.write(blk, who, &l.idx(i)[k]);
+            }
+          }
+        if (barrier) c.sync(blk);
+        for (int y = 0; y < TY; ++y)
+          for (int x = 0; x < TX; ++x) {
+            auto tY = R<Level::Thread>(y, TY), tX = R<Level::Thread>(x, TX);
+            auto b = layout::tile_rows<T, IT>(outm, bX, bY, tY, tX);
+            auto l = layout::lds_cols<T, IT>(tile, tY, tX);
+            const long who = blk * 256 + y * TX + x;
+            for (int i = 0; i < IT; ++i) {
+              for (int k = 0; k < 4; ++k) c.read(blk, who, &l.idx(i)[k]);
+              c.write(blk, who, &b[i]);
+            }
+          }
+      }
+    return c.conflicts().size();
+  };
+  {
+    const size_t c32 = transpose_access(std::integral_constant<int, 32>{}, true);
+    const size_t c64 = transpose_access(std::integral_constant<int, 64>{}, true);
+    const size_t c128 = transpose_access(std::integral_constant<int, 128>{}, true);
+    const size_t r64 = transpose_access(std::integral_constant<int, 64>{}, false);
+    check(c32 == 0 && c64 == 0 && c128 == 0, "access_check_transpose_kernel_clean");
+    check(r64 > 0, "access_check_transpose_without_barrier_races",
+          std::to_string(r64) + " conflicts");
+  }
+  // The block-wide reduction's tree (variants.hip): at each step the block is
+  // split at k, the first k threads read p[i] and p[i + k] and write p[i], and
+  // the whole block synchronises.  Clean with the barriers, racy without.
+  auto tree_access = [&](bool barriers) {
+    std::vector<long> part(256);
+    access_check::Checker c;
+    auto p = array(part.data(), 256);
+    for (int t = 0; t < 256; ++t) c.write(0, t, &p[t]);
+    c.sync(0);
+    for (int k = 128; k >= 1; k /= 2) {
+      for (int t = 0; t < 256; ++t)
+        split(R<Level::Thread>(t, 256), k,
+              [&](auto first) {
+                c.read(0, t, &p.fst(k).select(first).get());
+                c.read(0, t, &p.snd(k).fst(k).select(first).get());
+                c.write(0, t, &p.fst(k).select(first).get());
+              },
+              [](auto) {});
+      if (barriers) c.sync(0);
+    }
+    return c.conflicts().size();
+  };
+  check(tree_access(true) == 0, "access_check_reduce_tree_clean");
+  check(tree_access(false) > 0, "access_check_reduce_tree_without_barriers_races");
+  // The scan's tile stores: every (tile, wave, lane) writes its own 4-element
+  // groups, across all blocks, with no barrier needed.
+  {
+    const int W = 4, Rr = 4, tiles = 3, per = W * Rr * 64;
+    std::vector<int> out(tiles * per * 4);
+    access_check::Checker c;
+    for (int t = 0; t < tiles; ++t)
+      for (int w = 0; w < W; ++w)
+        for (int l = 0; l < 64; ++l) {
+          auto s = layout::wave_striped<W, Rr>(array(out.data(), tiles * per * 4).group<4>(), t,
+                                               R<Level::Wave>(w, W), R<Level::Thread>(l, 64));
+          for (int r = 0; r < Rr; ++r)
+            for (int k = 0; k < 4; ++k) c.write(t, (t * W + w) * 64 + l, &s.idx(r)[k]);
+        }
+    check(c.conflicts().empty() && c.accesses() == out.size(), "access_check_scan_stores_clean");
+  }
 
   return g_fail;
 }
