@@ -11,10 +11,11 @@
 //     fill in at the end), and writes the exclusive prefix of tile counts in
 //     that order with the total to the workspace.
 //   main kernel: a grid of as many blocks as fit on the device at once walks
-//     the global tile index t = block, block + grid, ...; a binary search over
-//     the prefix finds the problem, and the FP32 matrix-core tile routine of
-//     the plain GEMM computes the tile.  Tiles are independent, so the loop
-//     needs no inter-block communication.
+//     the global tile sequence, runs of 64 consecutive tiles per XCD so that
+//     a problem's tiles share one L2; a binary search over the prefix finds
+//     the problem, and the FP32 matrix-core tile routine of the plain GEMM
+//     computes the tile.  Tiles are independent, so the loop needs no
+//     inter-block communication.
 #include "common.hpp"
 #include "gemm_f32.hpp"
 #include "launch.hpp"
@@ -137,7 +138,18 @@ __global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_pr
   auto thread = thread_x<kBlock>();
   auto ts = array(tile_start, G + 1);
   const int64_t T = total[0];
-  for (idx_t t = block.index(); t < T; t += block.count()) {
+  // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+  // The planned tile sequence is cut into runs of kRun consecutive tiles
+  // (about one problem), run u going to XCD u % 8, so the tiles that share a
+  // problem's operands run on one XCD; the XCD's blocks walk its runs in
+  // order.  t(l) grows with l, so the walk ends at the first t >= T.
+  constexpr idx_t kRun = 64, kXcd = 8;
+  const bool by_xcd = block.count() % kXcd == 0;
+  const idx_t x = by_xcd ? block.index() % kXcd : 0;
+  const idx_t per = by_xcd ? block.count() / kXcd : block.count();
+  for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
+    const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
+    if (t >= T) break;
     if (thread.index() == 0) {       // planned slot of tile t: last i with ts[i] <= t
       idx_t lo = 0, hi = G;
       while (hi - lo > 1) {
