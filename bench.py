@@ -365,9 +365,24 @@ def op_grouped(desc, torch, workloads):
     ws = torch.empty(desc.desc_gemm_grouped_workspace(len(pairs)), dtype=torch.uint8,
                      device="cuda")
     ms = graph_time_ms(torch, lambda: desc.desc_gemm_grouped(d, ws=ws), reps=5)
+    # split-BF16 mode: three bf16 products on the matrix cores; its floor is
+    # the larger of 3 x 2MNK at the bf16 peak and the bytes of reading A, B,
+    # writing and re-reading their bf16 planes (4 bytes per element each
+    # way) and writing C
+    ws3 = torch.empty(desc.desc_gemm_grouped_workspace_for("bf16x3", d.cpu()),
+                      dtype=torch.uint8, device="cuda")
+    ms3 = graph_time_ms(torch, lambda: desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws3), reps=5)
+    roof3_s = 0.0
+    for M, N, K in shapes:
+        M, N, K = int(M), int(N), int(K)
+        roof3_s += max(6 * M * N * K / (PEAK_TFLOPS["bf16"] * 1e12),
+                       (12 * (M * K + K * N) + 4 * M * N) / (HBM_PEAK_GBS * 1e9))
     return {"problems": len(pairs), "flop": flops, "us": round(ms * 1e3, 1),
             "TFLOPs": round(flops / ms / 1e9, 2), "roofline_us": round(roof_s * 1e6, 1),
-            "roofline_frac": round(roof_s * 1e3 / ms, 4)}
+            "roofline_frac": round(roof_s * 1e3 / ms, 4),
+            "bf16x3_us": round(ms3 * 1e3, 1), "bf16x3_TFLOPs": round(flops / ms3 / 1e9, 2),
+            "bf16x3_roofline_us": round(roof3_s * 1e6, 1),
+            "bf16x3_roofline_frac": round(roof3_s * 1e3 / ms3, 4)}
 
 
 def main(argv=None):

@@ -185,8 +185,25 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
  * is skipped, K = 0 writes zeros).  The descriptors and the memory they
  * point to are read on the GPU only; the library cannot check them on the
  * host, so they are a precondition (valid GPU pointers, C_g not overlapping
- * any operand).  One planning kernel and one persistent kernel; the
- * workspace needs no initialisation.  Mode: DESC_GEMM_F32.
+ * any operand).  The workspace needs no initialisation.  Modes:
+ *   DESC_GEMM_F32     one planning kernel and one persistent kernel;
+ *                     desc_gemm_grouped_workspace(G) bytes, 64-byte aligned.
+ *   DESC_GEMM_BF16X3  desc_gemm's BF16X3 arithmetic per problem: a planning
+ *                     kernel, a persistent kernel that splits every operand
+ *                     into bf16 planes padded to multiples of 64 (K at
+ *                     least 64) inside the workspace, and a persistent
+ *                     kernel over the 64 x 64 output tiles.  The workspace
+ *                     (256-byte aligned) must hold
+ *                     desc_gemm_grouped_workspace_for(DESC_GEMM_BF16X3, G,
+ *                     problems_host) bytes, computed from a host copy of
+ *                     the descriptors (only M, N, K are read).  The host
+ *                     can only check the planning part; the planning kernel
+ *                     checks the rest on the GPU, and if the planes do not
+ *                     fit, or a problem has M, N or K above 2^40, it
+ *                     computes nothing and sets the uint32 at byte 16 of
+ *                     the workspace to 1 (0 after a call that computed).
+ * desc_gemm_grouped_workspace_for returns 0 for an unsupported mode, G < 0,
+ * problems_host = NULL with G > 0, or a refused shape.
  * ---------------------------------------------------------------------- */
 typedef struct {
   int64_t M, N, K;
@@ -197,6 +214,8 @@ typedef struct {
 } desc_gemm_problem;
 
 size_t desc_gemm_grouped_workspace(int64_t G);
+size_t desc_gemm_grouped_workspace_for(desc_gemm_mode mode, int64_t G,
+                                       const desc_gemm_problem* problems_host);
 desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_problem* problems,
                               void* ws, size_t ws_bytes, void* stream);
 

@@ -35,7 +35,8 @@ __all__ = [
     "desc_quant_e4m3_cols_workspace", "desc_quant_e4m3_cols",
     "desc_reduce_segmented_i32_workspace", "desc_reduce_segmented_i32",
     "desc_scan_segmented_i32_workspace", "desc_scan_segmented_i32",
-    "desc_gemm_grouped_workspace", "desc_gemm_grouped", "grouped_descriptors",
+    "desc_gemm_grouped_workspace", "desc_gemm_grouped_workspace_for", "desc_gemm_grouped",
+    "grouped_descriptors",
 ]
 
 _P = ctypes.c_void_p
@@ -79,6 +80,7 @@ SIGNATURES = {
     "desc_scan_segmented_i32_workspace": (_SZ, [_I64, _I64]),
     "desc_scan_segmented_i32": (_ST, [_P, _P, _I64, _P, _I64, _P, _SZ, _P]),
     "desc_gemm_grouped_workspace": (_SZ, [_I64]),
+    "desc_gemm_grouped_workspace_for": (_SZ, [ctypes.c_int, _I64, _P]),
     "desc_gemm_grouped": (_ST, [ctypes.c_int, _I64, _P, _P, _SZ, _P]),
 }
 
@@ -473,14 +475,35 @@ def grouped_descriptors(problems, device) -> torch.Tensor:
     return torch.tensor(rows, dtype=torch.int64).reshape(-1, 9).to(device)
 
 
+def desc_gemm_grouped_workspace_for(mode, descriptors_host: torch.Tensor) -> int:
+    """Workspace bytes of a grouped call in `mode`, from a host copy of the
+    descriptor array (G x 9 int64); 0 for a refused mode or shape."""
+    d = descriptors_host
+    if d.device.type != "cpu" or d.dtype != torch.int64 or d.dim() != 2 or d.shape[1] != 9:
+        raise ValueError("descriptors_host must be a CPU int64 tensor of shape (G, 9)")
+    d = d.contiguous()
+    return lib().desc_gemm_grouped_workspace_for(_mode(mode), d.shape[0], d.data_ptr())
+
+
 def desc_gemm_grouped(descriptors: torch.Tensor, mode="f32", ws: torch.Tensor | None = None,
-                      stream=None) -> None:
+                      stream=None, descriptors_host: torch.Tensor | None = None) -> None:
     """C_g = A_g @ B_g for every problem of a descriptor array (see
-    grouped_descriptors); the tensors it points to must stay alive."""
+    grouped_descriptors); the tensors it points to must stay alive.  In mode
+    "bf16x3" the workspace depends on the shapes: pass `ws` sized by
+    desc_gemm_grouped_workspace_for, or `descriptors_host` (else the
+    descriptors are copied to the host to size it)."""
     _dev(descriptors, torch.int64, "descriptors")
     G = descriptors.shape[0]
-    need = desc_gemm_grouped_workspace(G)
-    w = ws if ws is not None else torch.empty(max(need, 64), dtype=torch.uint8,
+    if _mode(mode) == _mode("f32"):
+        need = desc_gemm_grouped_workspace(G)
+    elif ws is None:
+        host = descriptors_host if descriptors_host is not None else descriptors.cpu()
+        need = desc_gemm_grouped_workspace_for(mode, host)
+        if need == 0 and G > 0:
+            raise ValueError("a grouped problem has a shape the bf16x3 mode refuses")
+    else:
+        need = ws.numel()
+    w = ws if ws is not None else torch.empty(max(need, 256), dtype=torch.uint8,
                                               device=descriptors.device)
     _check(lib().desc_gemm_grouped(_mode(mode), G, _ptr(descriptors), _ptr(w), w.numel(),
                                    _stream(descriptors, stream)), "desc_gemm_grouped")

@@ -351,19 +351,41 @@ size_t desc_gemm_grouped_workspace(int64_t G) {
   return G < 0 ? 0 : desc::launch::gemm_grouped_workspace(G);
 }
 
+size_t desc_gemm_grouped_workspace_for(desc_gemm_mode mode, int64_t G,
+                                       const desc_gemm_problem* problems_host) {
+  if (G < 0 || G > INT32_MAX) return 0;
+  if (mode == DESC_GEMM_F32) return desc::launch::gemm_grouped_workspace(G);
+  if (mode != DESC_GEMM_BF16X3) return 0;
+  size_t total = desc::launch::gemm_grouped_bf16x3_head(G);
+  if (G > 0 && problems_host == nullptr) return 0;
+  for (int64_t g = 0; g < G; ++g) {
+    const desc_gemm_problem& p = problems_host[g];
+    const size_t b = desc::launch::gemm_grouped_bf16x3_planes(p.M, p.N, p.K);
+    if (b == SIZE_MAX || total + b < total) return 0;   // refused shape or overflow
+    total += b;
+  }
+  return total;
+}
+
 desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_problem* problems,
                               void* ws, size_t ws_bytes, void* stream) {
   if (G < 0) return DESC_ERR_SIZE;
-  if (mode != DESC_GEMM_F32) return DESC_ERR_UNSUPPORTED;
+  if (mode != DESC_GEMM_F32 && mode != DESC_GEMM_BF16X3) return DESC_ERR_UNSUPPORTED;
   if (G == 0) return DESC_OK;
   if (problems == nullptr || ws == nullptr) return DESC_ERR_NULL;
   const int64_t pb = bytes_of(G, (int64_t)sizeof(desc_gemm_problem));
   if (pb < 0 || G > INT32_MAX) return DESC_ERR_SIZE;
   DESC_TRY(check_device({problems, ws}));
-  if (misaligned(problems, 8) || misaligned(ws, 64)) return DESC_ERR_ALIGNMENT;
+  const size_t align = mode == DESC_GEMM_F32 ? 64 : 256;
+  if (misaligned(problems, 8) || misaligned(ws, align)) return DESC_ERR_ALIGNMENT;
   if (overlap({ws, (int64_t)ws_bytes}, {problems, pb})) return DESC_ERR_ALIAS;
-  if (ws_bytes < desc_gemm_grouped_workspace(G)) return DESC_ERR_WORKSPACE;
-  return hip_status(desc::launch::gemm_grouped_f32(problems, G, ws, (hipStream_t)stream));
+  if (mode == DESC_GEMM_F32) {
+    if (ws_bytes < desc_gemm_grouped_workspace(G)) return DESC_ERR_WORKSPACE;
+    return hip_status(desc::launch::gemm_grouped_f32(problems, G, ws, (hipStream_t)stream));
+  }
+  if (ws_bytes < desc::launch::gemm_grouped_bf16x3_head(G)) return DESC_ERR_WORKSPACE;
+  return hip_status(
+      desc::launch::gemm_grouped_bf16x3(problems, G, ws, ws_bytes, (hipStream_t)stream));
 }
 
 // ----------------------------------------------------------------- segmented

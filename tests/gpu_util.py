@@ -28,3 +28,14 @@ def to_dev(a, offset_elems: int = 0):
     view = buf[offset_elems:]
     view.copy_(flat)
     return view.view(t.shape)
+
+
+def bf16x3_bound(K: int) -> float:
+    """A-priori componentwise bound of the split-BF16 product (relative to
+    sum_k |a_ik| |b_kj|): two round-to-nearest bf16 planes (8 significant
+    bits each) leave |a - hi - lo| <= 2^-16 |a| per operand, the dropped
+    lo*lo term is at most 2^-16 |a b|, and the FP32 accumulation of the 3K
+    exact products adds at most 3K * 2^-24.  For short sums this exceeds the
+    1e-5 target, which random signs of the per-term errors only reach for
+    longer ones; the tests take 1e-5 for K >= 64 and this bound below."""
+    return 3 * 2.0 ** -16 + 3 * K * 2.0 ** -24

@@ -150,3 +150,58 @@ def test_transpose_checks(fake_pointers):
     assert st(D(0), D(96), 1, 5, 5, None) == ALIAS                  # 25 words from 0
     assert st(D(0), D(1 << 24), 70000, 5, 5, None) == UNSUP         # batch beyond grid z
     assert L.desc_transpose_f32(D(0), HOSTP, 3, 3, None) == HOST
+
+
+def _problems_host(shapes):
+    """A host desc_gemm_problem array (nine int64 words each) with the given
+    M, N, K and placeholder strides and pointers."""
+    words = []
+    for M, N, K in shapes:
+        words += [M, N, K, max(K, 1), max(N, 1), max(N, 1), 0, 0, 0]
+    return (ctypes.c_int64 * max(len(words), 1))(*words)
+
+
+def test_grouped_workspace_for():
+    L = desc.lib()
+    F32, BF16X3, FP8 = 0, 1, 2
+    # bf16x3: a head of 256 bytes + three 256-aligned arrays of G + 1 int64,
+    # then per problem four bf16 planes (Mp + Np) x Kp with M, N, K rounded
+    # up to multiples of 64 and K at least 64; empty problems take nothing
+    shapes = [(100, 90, 80), (0, 5, 5), (5, 7, 0), (64, 64, 64), (1, 1, 1000)]
+    head = 256 + 3 * 256
+    planes = [4 * (128 + 128) * 128, 0, 4 * (64 + 64) * 64, 4 * (64 + 64) * 64,
+              4 * (64 + 64) * 1024]
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == \
+        head + sum(planes)
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 0, None) == head
+    big_G = 100                                   # (101 * 8) rounded to 256 = 1024
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, big_G, _problems_host(
+        [(0, 0, 0)] * big_G)) == 256 + 3 * 1024
+    assert L.desc_gemm_grouped_workspace_for(F32, 7, None) == L.desc_gemm_grouped_workspace(7)
+    assert L.desc_gemm_grouped_workspace_for(FP8, 1, _problems_host(shapes[:1])) == 0
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, -1, None) == 0
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 2, None) == 0
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 1, _problems_host([(64, 64, 1 << 41)])) == 0
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 1, _problems_host([(1 << 40, 64, 64)])) == 0
+
+
+def test_grouped_checks(fake_pointers):
+    L = fake_pointers
+    F32, BF16X3, FP8 = 0, 1, 2
+    G = 3                                         # 3 x 72 descriptor bytes at D(0)
+    wsb = L.desc_gemm_grouped_workspace(G)
+    head3 = 256 + 3 * 256                         # (G + 1) * 8 = 32 bytes per array
+    st = lambda *a: L.desc_gemm_grouped(*a, None)
+    assert st(F32, 0, None, None, 0) == OK        # nothing to do
+    assert st(F32, -1, D(0), D(1 << 20), wsb) == SIZE
+    assert st(FP8, G, D(0), D(1 << 20), wsb) == UNSUP
+    assert st(F32, G, None, D(1 << 20), wsb) == NULL
+    assert st(F32, G, D(0), None, wsb) == NULL
+    assert st(F32, G, HOSTP, D(1 << 20), wsb) == HOST
+    assert st(F32, G, D(0), HOSTP, wsb) == HOST
+    assert st(F32, G, D(4), D(1 << 20), wsb) == ALIGN
+    assert st(F32, G, D(0), D((1 << 20) + 32), wsb) == ALIGN
+    assert st(BF16X3, G, D(0), D((1 << 20) + 64), 1 << 20) == ALIGN    # 256 needed
+    assert st(F32, G, D(0), D(192), wsb) == ALIAS  # ws starts inside the descriptors
+    assert st(F32, G, D(0), D(1 << 20), wsb - 1) == WS
+    assert st(BF16X3, G, D(0), D(1 << 20), head3 - 1) == WS

@@ -13,7 +13,7 @@ import torch
 import oracle
 import paper_2305_03448_amd as desc
 import workloads
-from gpu_util import case, dev, needs_gpu, to_dev
+from gpu_util import bf16x3_bound, case, dev, needs_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -92,6 +92,17 @@ def test_gemm_normal_within_bound(M, N, K, mode):
     A = workloads.matrix_f32(M, K, seed=4); B = workloads.matrix_f32(K, N, seed=5)
     C = _run(A, B, mode)
     _check_sampled(A, B, C, TOL[mode])
+
+
+@pytest.mark.parametrize("K", [1, 3, 16, 40])
+def test_gemm_bf16x3_short_k_within_a_priori_bound(K):
+    # short sums: the two-plane representation error dominates (see bf16x3_bound)
+    case(f"gemm bf16x3 N(0,1) 130x70x{K}")
+    A = workloads.matrix_f32(130, K, seed=20); B = workloads.matrix_f32(K, 70, seed=21)
+    C = _run(A, B, "bf16x3")
+    e = _check_sampled(A, B, C, bf16x3_bound(K), samples=130 * 70)
+    print(f"[result] gemm bf16x3 K={K} max componentwise error {e:.3e} "
+          f"(bound {bf16x3_bound(K):.3e})", flush=True)
 
 
 @pytest.mark.parametrize("mode", ["f32", "bf16x3"])

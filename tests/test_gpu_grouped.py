@@ -1,9 +1,10 @@
-"""Parity of the grouped GEMM with the FP64 oracle through the C ABI: 512
-problems with M, N, K uniform over {64, ..., 1024} (seed 12, entries N(0,1)
-seed 13, 64 sampled entries per problem seed 14) within the componentwise
-bound; exactness on small-integer operands; degenerate shapes; a single
-problem equal bit for bit to the plain GEMM (same tile shape); graph
-replay."""
+"""Parity of the grouped GEMM with the FP64 oracle through the C ABI, in the
+FP32 and the split-BF16 modes: 512 problems with M, N, K uniform over
+{64, ..., 1024} (seed 12, entries N(0,1) seed 13, 64 sampled entries per
+problem seed 14) within the componentwise bound; exactness on small-integer
+operands; degenerate shapes; a single FP32 problem equal bit for bit to the
+plain GEMM (same tile shape); graph replay; the split-BF16 mode's device-side
+refusal of a workspace too small for its planes."""
 import numpy as np
 import pytest
 import torch
@@ -11,7 +12,7 @@ import torch
 import oracle
 import paper_2305_03448_amd as desc
 import workloads
-from gpu_util import case, dev, needs_gpu, to_dev
+from gpu_util import bf16x3_bound, case, dev, needs_gpu, to_dev
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
@@ -32,7 +33,7 @@ def _problems(shapes, seed, integer=False):
     return out
 
 
-def _run(pairs, pad=0):
+def _run(pairs, pad=0, mode="f32"):
     dev_pairs = []
     for A, B in pairs:
         M, K = A.shape
@@ -44,7 +45,7 @@ def _run(pairs, pad=0):
         C = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
         dev_pairs.append((At, to_dev(B), C))
     d = desc.grouped_descriptors(dev_pairs, dev())
-    desc.desc_gemm_grouped(d)
+    desc.desc_gemm_grouped(d, mode=mode)
     torch.cuda.synchronize()
     return [c.cpu().numpy() for _, _, c in dev_pairs], dev_pairs, d
 
@@ -131,4 +132,110 @@ def test_grouped_workload_512(grouped_config):
         err = np.abs(C[ii, jj] - R) / np.maximum(D, 1e-300)
         worst = max(worst, float(err.max()))
     print(f"[result] grouped 512 worst componentwise error {worst:.3e}")
+    assert worst <= TOL
+
+
+# ----------------------------------------------------------------- split-BF16 mode
+def _tol_bf16x3(K):
+    return TOL if K >= 64 else bf16x3_bound(K)
+
+
+def _check_all(pairs, outs):
+    """Every entry against the oracle; returns the worst error as a fraction
+    of each problem's tolerance, and the worst error of the K >= 64 problems."""
+    worst_frac, worst_long = 0.0, 0.0
+    for (A, B), C in zip(pairs, outs):
+        if C.size == 0:
+            continue
+        K = A.shape[1]
+        ii, jj = np.meshgrid(np.arange(C.shape[0]), np.arange(C.shape[1]), indexing="ij")
+        R, D = oracle.gemm_ref_sampled(A, B, ii.ravel(), jj.ravel())
+        err = np.abs(C.ravel() - R) / np.maximum(D, 1e-300)
+        print(f"[result] bf16x3 {A.shape[0]}x{C.shape[1]}x{K} worst {err.max():.3e}")
+        worst_frac = max(worst_frac, float(err.max()) / _tol_bf16x3(K))
+        if K >= 64:
+            worst_long = max(worst_long, float(err.max()))
+    return worst_frac, worst_long
+
+
+MIXED = [(64, 64, 64), (1, 1, 1), (300, 257, 65), (256, 256, 16), (1024, 64, 128),
+         (70, 513, 3), (257, 300, 129), (5, 7, 0), (0, 5, 5), (5, 0, 5), (63, 65, 1000)]
+
+
+def test_grouped_bf16x3_integer_exact_mixed_shapes():
+    # entries in {-4..4} are bf16 numbers: hi = a, lo = 0, every product exact
+    case(f"grouped bf16x3 integer {len(MIXED)} problems")
+    pairs = _problems(MIXED, 3, integer=True)
+    outs, _, _ = _run(pairs, mode="bf16x3")
+    for (A, B), C in zip(pairs, outs):
+        exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
+        assert np.array_equal(C, exact), A.shape
+
+
+def test_grouped_bf16x3_strided_mixed_shapes():
+    case(f"grouped bf16x3 strided lda, {len(MIXED)} problems")
+    pairs = _problems(MIXED, 7)
+    outs, _, _ = _run(pairs, pad=3, mode="bf16x3")
+    frac, long_k = _check_all(pairs, outs)
+    print(f"[result] grouped bf16x3 mixed: worst K >= 64 error {long_k:.3e}, "
+          f"worst fraction of the tolerance {frac:.3f}")
+    assert frac <= 1.0
+
+
+def test_grouped_bf16x3_workspace_too_small_sets_error():
+    pairs = _problems([(100, 90, 80), (64, 64, 64)], 8)
+    dev_pairs = [(to_dev(A), to_dev(B),
+                  torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=torch.float32,
+                             device=dev())) for A, B in pairs]
+    d = desc.grouped_descriptors(dev_pairs, dev())
+    need = desc.desc_gemm_grouped_workspace_for("bf16x3", d.cpu())
+    case("grouped bf16x3 workspace 256 bytes short of the planes")
+    small = torch.zeros(need - 256, dtype=torch.uint8, device=dev())
+    desc.desc_gemm_grouped(d, mode="bf16x3", ws=small)
+    torch.cuda.synchronize()
+    assert small[16:20].view(torch.int32).item() == 1
+    for _, _, C in dev_pairs:
+        assert torch.isnan(C).all()           # nothing computed
+    case("grouped bf16x3 workspace of the full size")
+    ws = torch.full((need,), 0xAB, dtype=torch.uint8, device=dev())
+    desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws)
+    torch.cuda.synchronize()
+    assert ws[16:20].view(torch.int32).item() == 0
+    assert _check_all(pairs, [C.cpu().numpy() for _, _, C in dev_pairs])[0] <= 1.0
+
+
+def test_grouped_bf16x3_graph_replay():
+    pairs = _problems([(200, 100, 300), (64, 640, 64), (512, 512, 64), (3, 5, 0)], 6)
+    outs, dp, d = _run(pairs, mode="bf16x3")
+    need = desc.desc_gemm_grouped_workspace_for("bf16x3", d.cpu())
+    ws = torch.empty(need, dtype=torch.uint8, device=dev())
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws)
+    for rep in range(3):
+        case(f"grouped bf16x3 graph replay {rep}")
+        for _, _, C in dp:
+            C.fill_(0)
+        ws.fill_(0x5A)                        # planes and plan rewritten by every replay
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, C), want in zip(dp, outs):
+            assert np.array_equal(C.cpu().numpy(), want)
+
+
+def test_grouped_bf16x3_workload_512():
+    case("grouped bf16x3 512 problems (seeds 12/13/14)")
+    shapes = workloads.grouped_shapes()
+    pairs = workloads.grouped_operands(shapes)
+    outs, _, _ = _run(pairs, mode="bf16x3")
+    worst = 0.0
+    for p, ((A, B), C) in enumerate(zip(pairs, outs)):
+        ii, jj = workloads.sample_pairs(C.shape[0], C.shape[1], 64, seed=14 + p)
+        R, D = oracle.gemm_ref_sampled(A, B, ii, jj)
+        err = np.abs(C[ii, jj] - R) / np.maximum(D, 1e-300)
+        worst = max(worst, float(err.max()))
+    print(f"[result] grouped bf16x3 512 worst componentwise error {worst:.3e}")
     assert worst <= TOL

@@ -131,6 +131,21 @@ def test_bf16x3_reference_close_to_true_product():
     assert np.max(np.abs(R3 - R) / D) < 1e-5
 
 
+def test_bf16x3_short_sums_reach_past_1e5():
+    # K = 1: each entry is one product, so the split's error does not average
+    # out; the 3-product scheme exceeds 1e-5 on some entries and stays inside
+    # its a-priori bound 3 * 2^-16 on all (why the GPU tests use that bound
+    # for K < 64)
+    M, N, K = 64, 64, 1
+    A = workloads.matrix_f32(M, K, 24); B = workloads.matrix_f32(K, N, 25)
+    ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+    R, D = oracle.gemm_ref_sampled(A, B, ii.ravel(), jj.ravel())
+    R3, _ = oracle.gemm_bf16x3_sampled(A, B, ii.ravel(), jj.ravel())
+    e = np.abs(R3 - R) / D
+    assert e.max() > 1e-5
+    assert e.max() <= 3 * 2.0**-16
+
+
 # ------------------------------------------------------------------ e4m3
 def _e4m3_value_from_definition(code: int) -> float:
     s = -1.0 if code & 0x80 else 1.0
