@@ -365,10 +365,9 @@ def op_grouped(desc, torch, workloads):
     ws = torch.empty(desc.desc_gemm_grouped_workspace(len(pairs)), dtype=torch.uint8,
                      device="cuda")
     ms = graph_time_ms(torch, lambda: desc.desc_gemm_grouped(d, ws=ws), reps=5)
-    # split-BF16 mode: three bf16 products on the matrix cores; its floor is
-    # the larger of 3 x 2MNK at the bf16 peak and the bytes of reading A, B,
-    # writing and re-reading their bf16 planes (4 bytes per element each
-    # way) and writing C
+    # split-BF16 mode: three bf16 products on the matrix cores, the operands
+    # split while they are staged; its floor is the larger of 3 x 2MNK at the
+    # bf16 peak and the bytes of reading A and B once and writing C
     ws3 = torch.empty(desc.desc_gemm_grouped_workspace_for("bf16x3", d.cpu()),
                       dtype=torch.uint8, device="cuda")
     ms3 = graph_time_ms(torch, lambda: desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws3), reps=5)
@@ -376,7 +375,7 @@ def op_grouped(desc, torch, workloads):
     for M, N, K in shapes:
         M, N, K = int(M), int(N), int(K)
         roof3_s += max(6 * M * N * K / (PEAK_TFLOPS["bf16"] * 1e12),
-                       (12 * (M * K + K * N) + 4 * M * N) / (HBM_PEAK_GBS * 1e9))
+                       4 * (M * K + K * N + M * N) / (HBM_PEAK_GBS * 1e9))
     return {"problems": len(pairs), "flop": flops, "us": round(ms * 1e3, 1),
             "TFLOPs": round(flops / ms / 1e9, 2), "roofline_us": round(roof_s * 1e6, 1),
             "roofline_frac": round(roof_s * 1e3 / ms, 4),

@@ -188,20 +188,27 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
  * any operand).  The workspace needs no initialisation.  Modes:
  *   DESC_GEMM_F32     one planning kernel and one persistent kernel;
  *                     desc_gemm_grouped_workspace(G) bytes, 64-byte aligned.
- *   DESC_GEMM_BF16X3  desc_gemm's BF16X3 arithmetic per problem: a planning
- *                     kernel, a persistent kernel that splits every operand
- *                     into bf16 planes padded to multiples of 64 (K at
- *                     least 64) inside the workspace, and a persistent
- *                     kernel over the 64 x 64 output tiles.  The workspace
+ *   DESC_GEMM_BF16X3  desc_gemm's BF16X3 arithmetic per problem.  A planning
+ *                     kernel, then, in the built-in configuration, one
+ *                     persistent kernel over 128 x 128 output tiles that
+ *                     splits the FP32 operands into hi and lo while staging
+ *                     them (no operand copies).  Problems with lda or ldb
+ *                     above 2^24, and every problem in the "tile*"
+ *                     configurations, go through bf16 planes instead: a
+ *                     persistent kernel splits their operands into planes
+ *                     padded to multiples of 128 (M, N) and 64 (K, at least
+ *                     64) inside the workspace, and a persistent kernel
+ *                     computes their tiles from the planes.  The workspace
  *                     (256-byte aligned) must hold
  *                     desc_gemm_grouped_workspace_for(DESC_GEMM_BF16X3, G,
- *                     problems_host) bytes, computed from a host copy of
- *                     the descriptors (only M, N, K are read).  The host
- *                     can only check the planning part; the planning kernel
- *                     checks the rest on the GPU, and if the planes do not
- *                     fit, or a problem has M, N or K above 2^40, it
- *                     computes nothing and sets the uint32 at byte 16 of
- *                     the workspace to 1 (0 after a call that computed).
+ *                     problems_host) bytes, computed from a host copy of the
+ *                     descriptors (M, N, K, lda, ldb are read) for the
+ *                     configuration in effect when the call is made.  The
+ *                     host can only check the planning part; the planning
+ *                     kernel checks the rest on the GPU, and if the planes do
+ *                     not fit, or a problem has M, N or K above 2^40, it
+ *                     computes nothing and sets the uint32 at byte 32 of the
+ *                     workspace to 1 (0 after a call that computed).
  * desc_gemm_grouped_workspace_for returns 0 for an unsupported mode, G < 0,
  * problems_host = NULL with G > 0, or a refused shape.
  * ---------------------------------------------------------------------- */
@@ -267,13 +274,16 @@ typedef enum {
   DESC_OP_GEMM_FP8 = 6,
   DESC_OP_SEG_REDUCE_I32 = 7,
   DESC_OP_SEG_SCAN_I32 = 8,
-  DESC_OP_GEMM_GROUPED = 9
+  DESC_OP_GEMM_GROUPED = 9,
+  DESC_OP_GEMM_GROUPED_BF16X3 = 10
 } desc_op;
 
 int desc_config_count(desc_op op);                     /* 0 for an op not built */
 const char* desc_config_name(desc_op op, int cfg);     /* NULL if out of range */
 const char* desc_op_name(desc_op op);                  /* NULL if not built */
-/* Size class (0..3) of a problem: element count, or M*N*K for GEMM. */
+/* Size class (0..3) of a problem: element count, M*N*K for GEMM, and the
+ * problem count G for the grouped GEMM (on the GEMM scale: G < 2^24 is
+ * class 0). */
 int desc_size_class(desc_op op, int64_t size);
 /* cfg < 0 restores the built-in choice; DESC_ERR_UNSUPPORTED if out of range. */
 desc_status desc_config_set(desc_op op, int size_class, int cfg);

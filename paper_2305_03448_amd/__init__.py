@@ -90,7 +90,7 @@ GEMM_MODES = {"f32": 0, "bf16x3": 1, "fp8": 2}
 # desc_op values (include/desc.h)
 OPS = {"reduce_i32": 0, "scan_i32": 1, "transpose_32": 2, "copy_32": 3, "gemm_f32": 4,
        "gemm_bf16x3": 5, "gemm_fp8": 6, "seg_reduce_i32": 7, "seg_scan_i32": 8,
-       "gemm_grouped": 9}
+       "gemm_grouped": 9, "gemm_grouped_bf16x3": 10}
 TUNE_FILE = os.path.join(HERE, "tune_gfx950.txt")
 
 _lib = None

@@ -356,15 +356,9 @@ size_t desc_gemm_grouped_workspace_for(desc_gemm_mode mode, int64_t G,
   if (G < 0 || G > INT32_MAX) return 0;
   if (mode == DESC_GEMM_F32) return desc::launch::gemm_grouped_workspace(G);
   if (mode != DESC_GEMM_BF16X3) return 0;
-  size_t total = desc::launch::gemm_grouped_bf16x3_head(G);
   if (G > 0 && problems_host == nullptr) return 0;
-  for (int64_t g = 0; g < G; ++g) {
-    const desc_gemm_problem& p = problems_host[g];
-    const size_t b = desc::launch::gemm_grouped_bf16x3_planes(p.M, p.N, p.K);
-    if (b == SIZE_MAX || total + b < total) return 0;   // refused shape or overflow
-    total += b;
-  }
-  return total;
+  const size_t total = desc::launch::gemm_grouped_bf16x3_workspace(problems_host, G);
+  return total == SIZE_MAX ? 0 : total;   // refused shape or overflow
 }
 
 desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_problem* problems,

@@ -69,13 +69,8 @@ __global__ __launch_bounds__(kBlock) void split_rows_kernel(const float* __restr
 #pragma unroll
       for (int j = 0; j < 4; ++j) v[j] = (r < M && c + j < K) ? a.at(r, c + j) : 0.f;
     }
-    u16x4 vh, vl;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const lowp::Split sp = lowp::split_bf16(v[j]);
-      vh[j] = sp.hi;
-      vl[j] = sp.lo;
-    }
+    const lowp::Split4 sp = lowp::split_bf16x4(v[0], v[1], v[2], v[3]);
+    const u16x4 vh = sp.hi, vl = sp.lo;
     if (vec_out && c + 4 <= k_out) {
       *(u16x4*)&h.at(r, c) = vh;
       *(u16x4*)&l.at(r, c) = vl;
@@ -130,13 +125,9 @@ __global__ __launch_bounds__(kBlock) void split_cols_t_kernel(const float* __res
   for (int i = 0; i < 4; ++i) {                 // output rows (columns of B) ty + 16 i
     const idx_t c = ty + 16 * i, r = 4 * tx;
     if (n0 + c >= n_out) continue;
-    u16x4 vh, vl;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const lowp::Split sp = lowp::split_bf16(tile.at(r + j, c));
-      vh[j] = sp.hi;
-      vl[j] = sp.lo;
-    }
+    const lowp::Split4 sp = lowp::split_bf16x4(tile.at(r, c), tile.at(r + 1, c),
+                                               tile.at(r + 2, c), tile.at(r + 3, c));
+    const u16x4 vh = sp.hi, vl = sp.lo;
     if (vec_out && k0 + r + 4 <= k_out) {
       *(u16x4*)&h.at(n0 + c, k0 + r) = vh;
       *(u16x4*)&l.at(n0 + c, k0 + r) = vl;

@@ -18,6 +18,7 @@
 #pragma once
 #include "common.hpp"
 #include "gemm_f32.hpp"
+#include "lowp.hpp"
 #include "mfma.hpp"
 #include "view.hpp"
 
@@ -96,10 +97,219 @@ struct Frag<32> {
   }
 };
 
+// Stage sources.  A source fills the LDS buffer of one stage -- per plane,
+// BM rows of A then BN rows of B^T, BKB bytes of K each as 16-byte chunks --
+// in two steps: load(kt, R) issues the global loads of stage kt into
+// registers, store(R, plane) writes them to the buffer whose plane pl is
+// plane(pl).  stages() is the number of stages of the K loop.
+//
+// PlaneSource: padded planes prepared by an operand pre-pass (no guards).
 template <class C>
-__device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, uint8_t* lds) {
+struct PlaneSource {
   using Mode = typename C::mode;
-  constexpr int P = Mode::planes, LB = Mode::lane_bytes, BKB = C::bkb;
+  static constexpr int P = Mode::planes, T = C::threads, CPR = C::chunks;
+  struct Regs {
+    u32x4 a[P][C::a_chunks], b[P][C::b_chunks];
+  };
+  const NtOperands& p;
+  idx_t m0, n0;
+
+  __device__ __forceinline__ idx_t stages() const { return p.row_bytes / C::bkb; }
+  // 16-byte chunk q of a stage (q = thread + T i) is chunk q % CPR of row
+  // q / CPR: consecutive lanes read consecutive bytes of a row.
+  __device__ __forceinline__ void load(idx_t kt, Regs& R) const {
+    const idx_t k0b = kt * C::bkb;
+    const int t = (int)thread_x<T>().index();
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl) {
+      auto ag = matrix(p.a[pl], 0, p.row_bytes);
+      auto bg = matrix(p.b[pl], 0, p.row_bytes);
+#pragma unroll
+      for (int i = 0; i < C::a_chunks; ++i) {
+        const int q = t + T * i;
+        R.a[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
+      }
+#pragma unroll
+      for (int i = 0; i < C::b_chunks; ++i) {
+        const int q = t + T * i;
+        R.b[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
+      }
+    }
+  }
+  template <class PlaneFn>
+  __device__ __forceinline__ void store(const Regs& R, PlaneFn&& plane) const {
+    const int t = (int)thread_x<T>().index();
+#pragma unroll
+    for (int pl = 0; pl < P; ++pl) {
+      auto s = plane(pl);
+#pragma unroll
+      for (int i = 0; i < C::a_chunks; ++i) {
+        const int q = t + T * i;
+        s.at(q / CPR, q % CPR) = R.a[pl][i];
+      }
+#pragma unroll
+      for (int i = 0; i < C::b_chunks; ++i) {
+        const int q = t + T * i;
+        s.at(C::bm + q / CPR, q % CPR) = R.b[pl][i];
+      }
+    }
+  }
+};
+
+// Row-major FP32 operands as the caller holds them: A (M x K, stride lda),
+// B (K x N, stride ldb).
+struct F32Operands {
+  const float* A;
+  int64_t lda;
+  const float* B;
+  int64_t ldb;
+  int64_t M, N, K;
+};
+
+// A buffer resource over `bytes` bytes from `base` (raw, 32-bit elements):
+// a buffer load at a byte offset >= bytes returns zero without touching
+// memory, which is how the split source below handles every edge.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  constexpr int kRawDword3 = 0x00020000;   // gfx9 word 3: 32-bit data format, no swizzle
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kRawDword3);
+}
+constexpr uint32_t kOutside = 0x80000000u;   // an offset past any range used here
+
+// The strides the split source accepts: its buffer offsets, at most 16 rows
+// of A or 8 rows of B from a range's base, stay below 2^31.
+constexpr int64_t kSplitMaxLd = int64_t(1) << 24;
+
+// SplitSource (Bf16x3 mode): the FP32 operands split into hi and lo on the
+// way into LDS, so no pre-pass and no planes in memory.  A stage is KS = 8 x
+// chunks values of K; a thread takes whole octets (8 consecutive k of one row
+// of A or column of B: one 16-byte chunk of each plane) and writes them,
+// split, to chunk `octet` of row `row` (A) or BM + column (B^T).
+//   A: octet q is octet q % CPR of row q / CPR.  The 16 rows one wave reads
+//      per octet set are one buffer range (base at the stage's k0), read as
+//      two 16-byte loads per octet when kVec (A 16-byte aligned, lda and K
+//      multiples of 4), else as 8 single loads.
+//   B: octet q is column q % BN, octet q / BN, which is one octet per wave:
+//      its 8 rows are one buffer range, read as 8 single loads, each
+//      coalesced over the wave's 64 consecutive columns.
+// Edges: a range ends at the last valid element (past K in the last row of
+// A, past the valid rows of A or B), so loads beyond it return zero; inside a
+// range, k past K in the other rows of A and columns past N of B are sent
+// outside it by their offsets.  Every load is unconditional: branches around
+// loads would double the registers the staging sets take.  Any shape with M,
+// N, K >= 1 and lda, ldb <= kSplitMaxLd.
+template <class C, bool kVec>
+struct SplitSource {
+  static_assert(C::mode::planes == 2 && C::mode::step_bytes == 32, "Bf16x3 mode only");
+  static constexpr int T = C::threads, CPR = C::chunks, KS = 8 * C::chunks;
+  static constexpr int AO = C::bm * CPR / T, BO = C::bn * CPR / T;
+  static_assert(AO >= 1 && BO >= 1 && AO * T == C::bm * CPR && BO * T == C::bn * CPR,
+                "octets divide evenly among the threads");
+  static_assert(CPR == 4 && kWave % CPR == 0 && C::bn % kWave == 0,
+                "a wave covers 16 whole rows of A and one octet of B");
+  struct Regs {
+    f32x4 a[AO][2], b[BO][2];   // an octet as two groups of four values
+  };
+  const F32Operands& p;
+  idx_t m0, n0;
+
+  __device__ __forceinline__ idx_t stages() const { return (p.K + KS - 1) / KS; }
+
+  __device__ __forceinline__ void load(idx_t kt, Regs& R) const {
+    const idx_t k0 = kt * KS;
+    const int32_t cols = (int32_t)min_i(p.K - k0, KS);          // valid k of this stage
+    const int lane = (int)lane_of_wave().index();
+    const int w = __builtin_amdgcn_readfirstlane((int)wave_of_block<T>().index());
+    auto a = matrix(p.A, p.M, p.lda);
+    auto b = matrix(p.B, p.K, p.ldb);
+    const int lr = lane / CPR, o = lane % CPR;                   // row in the wave's 16, octet
+#pragma unroll
+    for (int i = 0; i < AO; ++i) {
+      const idx_t r0 = m0 + (T / CPR) * i + (kWave / CPR) * w;  // first of the wave's rows
+      const idx_t rv = max_i(min_i(p.M - r0, kWave / CPR), 0);   // its valid rows
+      const uint32_t bytes = rv > 0 ? (uint32_t)(((rv - 1) * p.lda + cols) * 4) : 0u;
+      const auto rs = buffer_rsrc(rv > 0 ? &a.at(r0, k0) : p.A, bytes);
+      const uint32_t row_off = (uint32_t)(lr * p.lda) * 4u;
+      if constexpr (kVec) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = 8 * o + 4 * h;
+          const uint32_t off = kk < cols ? row_off + 4u * kk : kOutside;
+          R.a[i][h] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                    rs, (int)off, 0, 0));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int kk = 8 * o + j;
+          const uint32_t off = kk < cols ? row_off + 4u * kk : kOutside;
+          R.a[i][j / 4][j % 4] =
+              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BO; ++i) {
+      const int q0 = T * i + kWave * w;                          // the wave's first octet index
+      const idx_t c = n0 + q0 % C::bn + lane;                     // this lane's column
+      const idx_t kb = k0 + 8 * (q0 / C::bn);                     // the wave's octet
+      const idx_t rv = max_i(min_i(p.K - kb, 8), 0);
+      const idx_t cv = min_i(p.N - (n0 + q0 % C::bn), kWave);     // valid columns of the wave
+      const uint32_t bytes = rv > 0 && cv > 0 ? (uint32_t)(((rv - 1) * p.ldb + cv) * 4) : 0u;
+      const auto rs = buffer_rsrc(rv > 0 && cv > 0 ? &b.at(kb, n0 + q0 % C::bn) : p.B, bytes);
+      const uint32_t col_off = c < p.N ? 4u * (uint32_t)lane : kOutside;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        R.b[i][j / 4][j % 4] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rs, (int)(col_off + (uint32_t)(j * p.ldb) * 4u), 0, 0));
+    }
+  }
+  __device__ __forceinline__ static idx_t min_i(idx_t x, idx_t y) { return x < y ? x : y; }
+  __device__ __forceinline__ static idx_t max_i(idx_t x, idx_t y) { return x > y ? x : y; }
+
+  template <class PlaneFn>
+  __device__ __forceinline__ void store(const Regs& R, PlaneFn&& plane) const {
+    const int t = (int)thread_x<T>().index();
+    auto hi = plane(0);
+    auto lo = plane(1);
+    auto put = [&](idx_t row, int oct, f32x4 v, f32x4 w) {
+      const lowp::Split4 x = lowp::split_bf16x4(v[0], v[1], v[2], v[3]);
+      const lowp::Split4 y = lowp::split_bf16x4(w[0], w[1], w[2], w[3]);
+      hi.at(row, oct) = join(x.hi, y.hi);
+      lo.at(row, oct) = join(x.lo, y.lo);
+    };
+#pragma unroll
+    for (int i = 0; i < AO; ++i) {
+      const int q = t + T * i;
+      put(q / CPR, q % CPR, R.a[i][0], R.a[i][1]);
+    }
+#pragma unroll
+    for (int i = 0; i < BO; ++i) {
+      const int q = t + T * i;
+      put(C::bm + q % C::bn, q / C::bn, R.b[i][0], R.b[i][1]);
+    }
+  }
+  __device__ __forceinline__ static u32x4 join(lowp::bf16x4_bits x, lowp::bf16x4_bits y) {
+    const lowp::u32x2_bits a = __builtin_bit_cast(lowp::u32x2_bits, x);
+    const lowp::u32x2_bits b = __builtin_bit_cast(lowp::u32x2_bits, y);
+    return u32x4{a[0], a[1], b[0], b[1]};
+  }
+};
+
+// Where the tile's FP32 result goes: C (M x N valid, stride ldc) and, in the
+// scaled mode, the row scales of A and column scales of B.
+struct NtEpilogue {
+  float* C;
+  int64_t ldc;
+  int64_t M, N;
+  const float* sa;
+  const float* sb;
+};
+
+template <class C, class Src>
+__device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, idx_t tm, idx_t tn,
+                                          uint8_t* lds) {
+  using Mode = typename C::mode;
+  constexpr int P = Mode::planes, LB = Mode::lane_bytes;
   constexpr int T = C::threads;
   auto thread = thread_x<T>();
   auto wv = wave_of_block<T>();
@@ -115,45 +325,11 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
   };
 
   // Two register staging sets: stage j travels through set j % 2.
-  struct Stage {
-    u32x4 a[P][C::a_chunks], b[P][C::b_chunks];
-  };
+  using Stage = typename Src::Regs;
   Stage R0, R1;
-  // 16-byte chunk q of a stage (q = thread + T i) is chunk q % CPR of row
-  // q / CPR: consecutive lanes read consecutive bytes of a row.
-  constexpr int CPR = C::chunks;
-  auto load = [&](idx_t k0b, Stage& R) {
-#pragma unroll
-    for (int pl = 0; pl < P; ++pl) {
-      auto ag = matrix(p.a[pl], 0, p.row_bytes);
-      auto bg = matrix(p.b[pl], 0, p.row_bytes);
-#pragma unroll
-      for (int i = 0; i < C::a_chunks; ++i) {
-        const int q = (int)thread.index() + T * i;
-        R.a[pl][i] = *(const u32x4*)&ag.at(m0 + q / CPR, k0b + 16 * (q % CPR));
-      }
-#pragma unroll
-      for (int i = 0; i < C::b_chunks; ++i) {
-        const int q = (int)thread.index() + T * i;
-        R.b[pl][i] = *(const u32x4*)&bg.at(n0 + q / CPR, k0b + 16 * (q % CPR));
-      }
-    }
-  };
+  auto load = [&](idx_t kt, Stage& R) { src.load(kt, R); };
   auto store = [&](const Stage& R, int stage) {
-#pragma unroll
-    for (int pl = 0; pl < P; ++pl) {
-      auto s = plane(stage, pl);
-#pragma unroll
-      for (int i = 0; i < C::a_chunks; ++i) {
-        const int q = (int)thread.index() + T * i;
-        s.at(q / CPR, q % CPR) = R.a[pl][i];
-      }
-#pragma unroll
-      for (int i = 0; i < C::b_chunks; ++i) {
-        const int q = (int)thread.index() + T * i;
-        s.at(C::bm + q / CPR, q % CPR) = R.b[pl][i];
-      }
-    }
+    src.store(R, [&](int pl) { return plane(stage, pl); });
   };
 
   mfma::f32x16 acc[C::fm][C::fn];
@@ -202,7 +378,7 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     }
   };
 
-  const idx_t nk = p.row_bytes / BKB;
+  const idx_t nk = src.stages();
   if constexpr (C::depth == 1) {
     // One stage ahead: iteration kt loads stage kt+1 into registers, computes
     // stage kt from LDS and writes stage kt+1 to the other buffer; the last
@@ -212,7 +388,7 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     sync(thread);
     for (idx_t kt = 0; kt + 1 < nk; ++kt) {
       const int stage = (int)(kt & 1);
-      load((kt + 1) * BKB, R0);
+      load(kt + 1, R0);
       __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the matrix ops
       compute(stage);
       __builtin_amdgcn_sched_barrier(0);
@@ -230,28 +406,39 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
     // statically) without branches; the last iterations are peeled.
     load(0, R0);
     store(R0, 0);
-    if (nk > 1) load(BKB, R1);
+    if (nk > 1) load(1, R1);
     sync(thread);
     idx_t kt = 0;
     for (; kt + 3 < nk; kt += 2) {
-      load((kt + 2) * BKB, R0);
+      load(kt + 2, R0);
       __builtin_amdgcn_sched_barrier(0);
       compute(0);
       __builtin_amdgcn_sched_barrier(0);
       store(R1, 1);
       sync(thread);
-      load((kt + 3) * BKB, R1);
+      load(kt + 3, R1);
       __builtin_amdgcn_sched_barrier(0);
       compute(1);
       __builtin_amdgcn_sched_barrier(0);
       store(R0, 0);
       sync(thread);
     }
-    for (; kt < nk; ++kt) {            // at most three iterations left
-      const bool even = (kt & 1) == 0;
-      if (kt + 2 < nk) load((kt + 2) * BKB, even ? R0 : R1);
-      compute((int)(kt & 1));
-      if (kt + 1 < nk) store(even ? R1 : R0, (int)((kt + 1) & 1));
+    // At most three iterations are left and kt is even; they are written
+    // out so that each names its register sets statically (a set chosen at
+    // run time would have to live in memory).
+    if (kt < nk) {
+      if (kt + 2 < nk) load(kt + 2, R0);
+      compute(0);
+      if (kt + 1 < nk) store(R1, 1);
+      sync(thread);
+    }
+    if (kt + 1 < nk) {
+      compute(1);
+      if (kt + 2 < nk) store(R0, 0);
+      sync(thread);
+    }
+    if (kt + 2 < nk) {
+      compute(0);
       sync(thread);
     }
   }
@@ -308,6 +495,23 @@ __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, ui
           }
     }
   }
+}
+
+// A tile of C from padded planes (the operand pre-pass layout).
+template <class C>
+__device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, uint8_t* lds) {
+  const PlaneSource<C> src{p, tm * C::bm, tn * C::bn};
+  tile_from<C>(src, NtEpilogue{p.C, p.ldc, p.M, p.N, p.sa, p.sb}, tm, tn, lds);
+}
+
+// A tile of C = A * B in the Bf16x3 mode straight from FP32 operands
+// (M, N, K >= 1).  kVec: A read in 16-byte groups (A 16-byte aligned, lda
+// and K multiples of 4).
+template <class C, bool kVec>
+__device__ __forceinline__ void tile_split(const F32Operands& f, float* Cp, int64_t ldc, idx_t tm,
+                                           idx_t tn, uint8_t* lds) {
+  const SplitSource<C, kVec> src{f, tm * C::bm, tn * C::bn};
+  tile_from<C>(src, NtEpilogue{Cp, ldc, f.M, f.N, nullptr, nullptr}, tm, tn, lds);
 }
 
 }  // namespace gemm_nt

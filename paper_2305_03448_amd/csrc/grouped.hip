@@ -24,6 +24,7 @@
 #include "lowp.hpp"
 #include "tuning.hpp"
 #include "view.hpp"
+#include "wave.hpp"
 
 #include "../../include/desc.h"
 
@@ -73,6 +74,25 @@ __device__ __forceinline__ int64_t block_excl(int64_t v, int64_t* excl, int64_t*
   sync(thread);
   *excl = before + incl - v;
   return tot;
+}
+
+// Last i in [0, G) with start[i] <= t, for a nondecreasing start with
+// start[0] <= t < start[G]: a 64-way search by one whole wave.  Each round
+// every lane reads one boundary and a ballot counts those <= t (a prefix of
+// the lanes), so G = 512 takes two rounds of parallel loads instead of nine
+// dependent ones.
+__device__ __forceinline__ idx_t wave_owner(const int64_t* start, int64_t G, int64_t t) {
+  auto st = array(start, G + 1);
+  const idx_t lane = lane_of_wave().index();
+  idx_t lo = 0, hi = G;
+  while (hi - lo > 1) {
+    const idx_t step = (hi - lo + kWave - 1) / kWave;
+    const idx_t i = lo + lane * step;
+    const bool le = i < hi && st[i] <= t;
+    lo += ((idx_t)__popcll(__ballot(le)) - 1) * step;
+    hi = lo + step < hi ? lo + step : hi;
+  }
+  return lo;
 }
 
 __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_problem* probs,
@@ -153,16 +173,12 @@ __global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_pr
   for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
     const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
     if (t >= T) break;
-    if (thread.index() == 0) {       // planned slot of tile t: last i with ts[i] <= t
-      idx_t lo = 0, hi = G;
-      while (hi - lo > 1) {
-        const idx_t mid = (lo + hi) / 2;
-        if (ts[mid] <= t) lo = mid; else hi = mid;
-      }
-      s_slot = lo;
+    if (thread.index() < kWave) {    // planned slot of tile t: last i with ts[i] <= t
+      const idx_t slot = wave_owner(tile_start, G, t);
+      if (thread.index() == 0) s_slot = slot;
     }
     sync(thread);
-    const idx_t slot = s_slot;
+    const idx_t slot = wave::uniform_i64(s_slot);
     const int32_t g = array(order, G)[slot];
     const desc_gemm_problem p = array(probs, G)[g];
     const bool b = array(big, G)[g] != 0;
@@ -216,72 +232,113 @@ int persistent_grid() {
 // otherwise, or 64 x 64 tiles throughout (more, smaller tiles balance better
 // over the CUs when the problems are small).
 // --------------------------------------------------------------------------
-// Split-BF16 (three products) mode.  Every problem is padded to multiples of
-// 64 in M, N and K (K at least 64, so K = 0 gives zero products through the
-// same path), and its operands are split into bf16 planes in the workspace:
-// Ah, Al as [Mp][Kp] and Bh^T, Bl^T as [Np][Kp].
+// Split-BF16 (three products) mode.  Every problem's operands are split into
+// bf16 planes in the workspace, Ah, Al as [Ma][Kp] and Bh^T, Bl^T as
+// [Na][Kp]: K rounded up to a multiple of 64 (at least 64, so K = 0 gives
+// zero products through the same path), M and N rounded up to multiples of
+// 128 so that either output tile size fits the planes whatever the
+// configuration.
 //   plan kernel (one block): per problem the NT tiles, the split work items
 //     and the byte offset of its planes, as exclusive prefixes; if the planes
 //     do not fit the workspace, the error word is set and nothing is planned.
 //   split kernel (persistent): 64 x 64 items -- A tiles split in place, B
-//     tiles split and transposed through LDS.
-//   NT kernel (persistent): 64 x 64 output tiles of the low-precision tile
-//     routine, runs of 64 tiles per XCD as in the FP32 mode.
+//     tiles split and transposed through LDS -- over M and N rounded up to
+//     64 and the whole of Kp.  Columns k >= K are written as zeros (they
+//     enter every product); rows past M, N up to the 128 rounding are not
+//     written: they only reach output rows or columns that are never stored.
+//   NT kernel (persistent): output tiles of the low-precision tile routine,
+//     64 x 64 or 128 x 128 per problem as the configuration says, runs of 64
+//     tiles per XCD as in the FP32 mode.
 // --------------------------------------------------------------------------
-constexpr int kPad = 64;
-using NtTile = NtCfg<64, 64, 64, Bf16x3Mode, 2, 2, 2>;
+constexpr int kPad = 64, kPadBig = 128;
+using NtSmall = NtCfg<64, 64, 64, Bf16x3Mode, 2, 2, 2>;
+using NtBig = NtCfg<128, 128, 64, Bf16x3Mode, 2, 2, 2>;
+static_assert(NtSmall::threads == kBlock && NtBig::threads == kBlock, "one block shape");
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int64_t kMaxDim = int64_t(1) << 40;         // larger M, N or K: refused
 constexpr int64_t kMaxPlaneBytes = int64_t(1) << 44;  // larger planes of one problem: refused
+__host__ __device__ inline int64_t round_up(int64_t v, int64_t p) { return (v + p - 1) / p * p; }
+
 struct Bf16Dims {
-  int64_t Mp, Np, Kp;
-  bool empty;   // M <= 0 or N <= 0: nothing to compute or store
-  bool huge;    // a dimension or the planes beyond the limits above
+  int64_t Ma, Na;   // plane rows: M, N rounded up to 128
+  int64_t Ms, Ns;   // rows the split writes: M, N rounded up to 64
+  int64_t Kp;       // K rounded up to 64, at least 64
+  bool empty;       // M <= 0 or N <= 0: nothing to compute or store
+  bool huge;        // a dimension or the planes beyond the limits above
 };
 __host__ __device__ inline Bf16Dims bf16_dims(int64_t M, int64_t N, int64_t K) {
   Bf16Dims d;
   d.empty = M <= 0 || N <= 0;
   d.huge = !d.empty && (M > kMaxDim || N > kMaxDim || K > kMaxDim);
   const bool none = d.empty || d.huge;
-  d.Mp = none ? 0 : (M + kPad - 1) / kPad * kPad;
-  d.Np = none ? 0 : (N + kPad - 1) / kPad * kPad;
-  d.Kp = none ? 0 : (K <= kPad ? kPad : (K + kPad - 1) / kPad * kPad);   // K <= 0: one zero step
-  d.huge = d.huge || (!none && d.Mp + d.Np > kMaxPlaneBytes / (4 * d.Kp));
-  if (d.huge) d.Mp = d.Np = d.Kp = 0;
+  d.Ma = none ? 0 : round_up(M, kPadBig);
+  d.Na = none ? 0 : round_up(N, kPadBig);
+  d.Ms = none ? 0 : round_up(M, kPad);
+  d.Ns = none ? 0 : round_up(N, kPad);
+  d.Kp = none ? 0 : (K <= kPad ? kPad : round_up(K, kPad));   // K <= 0: one zero step
+  d.huge = d.huge || (!none && d.Ma + d.Na > kMaxPlaneBytes / (4 * d.Kp));
+  if (d.huge) d.Ma = d.Na = d.Ms = d.Ns = d.Kp = 0;
   return d;
 }
-// Four planes, 256-byte aligned (none for a refused problem).
+// Four planes, 256-byte aligned (none for a refused or empty problem).
 __host__ __device__ inline int64_t bf16_plane_bytes(const Bf16Dims& d) {
-  return (4 * (d.Mp + d.Np) * d.Kp + 255) / 256 * 256;
+  return round_up(4 * (d.Ma + d.Na) * d.Kp, 256);
+}
+// Configurations: 0-2 split into planes first, 3-4 split while staging
+// (fused: no planes).  Output tile edge of a problem: 64 (0, 3), 128 (1, 4),
+// or 128 when M and N are both at least 256 (2).
+template <int kCfg>
+constexpr bool kFused = kCfg >= 3;
+template <int kCfg>
+constexpr bool kSmallOnly = kCfg == 0 || kCfg == 3;   // 64 x 64 tiles only
+template <int kCfg>
+__device__ __forceinline__ int64_t tile_edge(int64_t M, int64_t N) {
+  if constexpr (kCfg == 0 || kCfg == 3) return kPad;
+  if constexpr (kCfg == 1 || kCfg == 4) return kPadBig;
+  return M >= 256 && N >= 256 ? kPadBig : kPad;
 }
 
 struct Bf16Ws {
-  int64_t* totals;       // [0] NT tiles, [1] split items
+  int64_t* totals;       // [0] NT tiles, [1] split items, [2] fused tiles
   uint32_t* error;       // set when the planes do not fit
   int64_t* nt_start;     // [G + 1]
   int64_t* split_start;  // [G + 1]
   int64_t* plane_off;    // [G]
+  int64_t* fused_start;  // [G + 1]
   uint8_t* planes;
   int64_t planes_bytes;  // room for the planes
 };
 size_t bf16_head_bytes(int64_t G) {
-  return 256 + 3 * (((G + 1) * 8 + 255) & ~(size_t)255);   // planes start 256-byte aligned
+  return 256 + 4 * (((G + 1) * 8 + 255) & ~(size_t)255);   // planes start 256-byte aligned
 }
 Bf16Ws bf16_carve(void* ws, size_t ws_bytes, int64_t G) {
   uint8_t* w = (uint8_t*)ws;
   const size_t arr = ((G + 1) * 8 + 255) & ~(size_t)255;
   Bf16Ws r;
   r.totals = (int64_t*)w;
-  r.error = (uint32_t*)(w + 16);
+  r.error = (uint32_t*)(w + 32);   // after the three totals
   r.nt_start = (int64_t*)(w + 256);
   r.split_start = (int64_t*)(w + 256 + arr);
   r.plane_off = (int64_t*)(w + 256 + 2 * arr);
+  r.fused_start = (int64_t*)(w + 256 + 3 * arr);
   r.planes = w + bf16_head_bytes(G);
   r.planes_bytes = (int64_t)ws_bytes - (int64_t)bf16_head_bytes(G);
   return r;
 }
 
+// In the fused configurations a problem is staged straight from its FP32
+// operands when its strides allow (the split source's buffer ranges), and
+// through planes otherwise; the other configurations use planes throughout.
+__host__ __device__ inline bool fused_route(int cfg, int64_t lda, int64_t ldb) {
+  return cfg >= 3 && lda <= gemm_nt::kSplitMaxLd && ldb <= gemm_nt::kSplitMaxLd;
+}
+template <int kCfg>
+__device__ __forceinline__ bool fused_for(const desc_gemm_problem& p) {
+  return fused_route(kCfg, p.lda, p.ldb);
+}
+
+template <int kCfg>
 __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_problem* probs,
                                                            int64_t G, Bf16Ws w) {
   __shared__ int64_t lds[kBlock / kWave];
@@ -290,29 +347,42 @@ __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_probl
   auto nts = array(w.nt_start, G + 1);
   auto sps = array(w.split_start, G + 1);
   auto pof = array(w.plane_off, G);
-  int64_t c_nt = 0, c_sp = 0, c_pl = 0, c_huge = 0;
+  auto fts = array(w.fused_start, G + 1);
+  int64_t c_nt = 0, c_sp = 0, c_pl = 0, c_ft = 0, c_huge = 0;
   for (idx_t base = 0; base < G; base += kBlock) {
     const idx_t g = base + thread.index();
-    int64_t nt = 0, sp = 0, pl = 0, huge = 0;
+    int64_t nt = 0, sp = 0, pl = 0, ft = 0, huge = 0;
     if (g < G) {
-      const Bf16Dims d = bf16_dims(pr[g].M, pr[g].N, pr[g].K);
-      nt = (d.Mp / kPad) * (d.Np / kPad);
-      sp = (d.Mp / kPad) * (d.Kp / kPad) + (d.Kp / kPad) * (d.Np / kPad);
-      pl = bf16_plane_bytes(d);
+      const desc_gemm_problem p = pr[g];
+      const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
+      if (!d.empty && !d.huge) {
+        const int64_t e = tile_edge<kCfg>(p.M, p.N);
+        const int64_t tiles = (round_up(p.M, e) / e) * (round_up(p.N, e) / e);
+        if (fused_for<kCfg>(p)) {
+          ft = tiles;
+        } else {
+          nt = tiles;
+          sp = (d.Ms / kPad) * (d.Kp / kPad) + (d.Kp / kPad) * (d.Ns / kPad);
+          pl = bf16_plane_bytes(d);
+        }
+      }
       huge = d.huge;
     }
-    int64_t e_nt, e_sp, e_pl, e_huge;
+    int64_t e_nt, e_sp, e_pl, e_ft, e_huge;
     const int64_t t_nt = block_excl(nt, &e_nt, lds);
     const int64_t t_sp = block_excl(sp, &e_sp, lds);
     const int64_t t_pl = block_excl(pl, &e_pl, lds);
+    const int64_t t_ft = block_excl(ft, &e_ft, lds);
     c_huge += block_excl(huge, &e_huge, lds);
     if (g < G) {
       nts[g] = c_nt + e_nt;
       sps[g] = c_sp + e_sp;
       pof[g] = c_pl + e_pl;
+      fts[g] = c_ft + e_ft;
     }
     c_nt += t_nt;
     c_sp += t_sp;
+    c_ft += t_ft;
     // at most 256 * 2^44 bytes per round: held below 2^60, no overflow
     c_pl = c_pl + t_pl < (int64_t(1) << 60) ? c_pl + t_pl : (int64_t(1) << 60);
   }
@@ -320,21 +390,12 @@ __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_probl
     const bool fits = c_huge == 0 && c_pl <= w.planes_bytes;
     nts[G] = c_nt;
     sps[G] = c_sp;
+    fts[G] = c_ft;
     w.totals[0] = fits ? c_nt : 0;
     w.totals[1] = fits ? c_sp : 0;
+    w.totals[2] = fits ? c_ft : 0;
     w.error[0] = fits ? 0u : 1u;
   }
-}
-
-// Last i with start[i] <= t (the problem holding item t).
-__device__ __forceinline__ idx_t owner(const int64_t* start, int64_t G, int64_t t) {
-  auto st = array(start, G + 1);
-  idx_t lo = 0, hi = G;
-  while (hi - lo > 1) {
-    const idx_t mid = (lo + hi) / 2;
-    if (st[mid] <= t) lo = mid; else hi = mid;
-  }
-  return lo;
 }
 
 // The bf16 planes of problem g.
@@ -343,7 +404,7 @@ struct Planes {
 };
 __device__ __forceinline__ Planes planes_of(const Bf16Ws& w, idx_t g, const Bf16Dims& d) {
   uint16_t* p = (uint16_t*)(w.planes + array(w.plane_off, g + 1)[g]);
-  return {p, p + d.Mp * d.Kp, p + 2 * d.Mp * d.Kp, p + 2 * d.Mp * d.Kp + d.Np * d.Kp};
+  return {p, p + d.Ma * d.Kp, p + 2 * d.Ma * d.Kp, p + 2 * d.Ma * d.Kp + d.Na * d.Kp};
 }
 
 // Split item: a 64 x 64 tile of A (rows r0.., k0..) into Ah, Al, or a
@@ -359,19 +420,22 @@ __global__ __launch_bounds__(kBlock) void bf16_split_kernel(const desc_gemm_prob
   const int64_t T = w.totals[1];
   const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
   for (idx_t t = block.index(); t < T; t += block.count()) {
-    if (thread.index() == 0) s_g = owner(w.split_start, G, t);
+    if (thread.index() < kWave) {
+      const idx_t g = wave_owner(w.split_start, G, t);
+      if (thread.index() == 0) s_g = g;
+    }
     sync(thread);
-    const idx_t g = s_g;
+    const idx_t g = wave::uniform_i64(s_g);
     const desc_gemm_problem p = array(probs, G)[g];
     const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
     const Planes pl = planes_of(w, g, d);
     const idx_t local = t - array(w.split_start, G + 1)[g];
-    const idx_t kt = d.Kp / kPad, a_items = (d.Mp / kPad) * kt;
+    const idx_t kt = d.Kp / kPad, a_items = (d.Ms / kPad) * kt;
     if (local < a_items) {
       const idx_t r0 = (local / kt) * kPad, k0 = (local % kt) * kPad;
       auto a = matrix(p.A, p.M, p.lda);
-      auto h = matrix(pl.ah, d.Mp, d.Kp);
-      auto l = matrix(pl.al, d.Mp, d.Kp);
+      auto h = matrix(pl.ah, d.Ma, d.Kp);
+      auto l = matrix(pl.al, d.Ma, d.Kp);
       const bool vec = gemm_f32::vec_ok(p.A, p.lda, p.A, p.lda);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {            // rows ty + 16 i, k = 4 tx ..
@@ -383,22 +447,16 @@ __global__ __launch_bounds__(kBlock) void bf16_split_kernel(const desc_gemm_prob
 #pragma unroll
           for (int j = 0; j < 4; ++j) v[j] = (r < p.M && c + j < p.K) ? a.at(r, c + j) : 0.f;
         }
-        u16x4 vh, vl;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const lowp::Split sp = lowp::split_bf16(v[j]);
-          vh[j] = sp.hi;
-          vl[j] = sp.lo;
-        }
-        *(u16x4*)&h.at(r, c) = vh;
-        *(u16x4*)&l.at(r, c) = vl;
+        const lowp::Split4 sp = lowp::split_bf16x4(v[0], v[1], v[2], v[3]);
+        *(u16x4*)&h.at(r, c) = sp.hi;
+        *(u16x4*)&l.at(r, c) = sp.lo;
       }
     } else {
-      const idx_t j0 = local - a_items, ntl = d.Np / kPad;
+      const idx_t j0 = local - a_items, ntl = d.Ns / kPad;
       const idx_t k0 = (j0 / ntl) * kPad, n0 = (j0 % ntl) * kPad;
       auto b = matrix(p.B, p.K, p.ldb);
-      auto h = matrix(pl.bh, d.Np, d.Kp);
-      auto l = matrix(pl.bl, d.Np, d.Kp);
+      auto h = matrix(pl.bh, d.Na, d.Kp);
+      auto l = matrix(pl.bl, d.Na, d.Kp);
       const bool vec = gemm_f32::vec_ok(p.B, p.ldb, p.B, p.ldb);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {            // rows (k) ty + 16 i, columns (n) 4 tx ..
@@ -418,27 +476,28 @@ __global__ __launch_bounds__(kBlock) void bf16_split_kernel(const desc_gemm_prob
 #pragma unroll
       for (int i = 0; i < 4; ++i) {            // output rows (n) ty + 16 i, k = 4 tx ..
         const idx_t c = ty + 16 * i, r = 4 * tx;
-        u16x4 vh, vl;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const lowp::Split sp = lowp::split_bf16(tile.at(r + j, c));
-          vh[j] = sp.hi;
-          vl[j] = sp.lo;
-        }
-        *(u16x4*)&h.at(n0 + c, k0 + r) = vh;
-        *(u16x4*)&l.at(n0 + c, k0 + r) = vl;
+        const lowp::Split4 sp = lowp::split_bf16x4(tile.at(r, c), tile.at(r + 1, c),
+                                                   tile.at(r + 2, c), tile.at(r + 3, c));
+        *(u16x4*)&h.at(n0 + c, k0 + r) = sp.hi;
+        *(u16x4*)&l.at(n0 + c, k0 + r) = sp.lo;
       }
     }
     sync(thread);   // s_g and the LDS tile are reused by the next item
   }
 }
 
-__global__ __launch_bounds__(NtTile::threads) void bf16_nt_kernel(const desc_gemm_problem* probs,
-                                                                  int64_t G, Bf16Ws w) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[NtTile::lds_bytes];
+// Occupancy targets: four blocks per CU (a wave in 128 registers) with the
+// 64 x 64 tile alone, two (256 registers) when the 128 x 128 tile can run;
+// the tile coordinates and the problem index are kept in scalar registers
+// so that only the tile's own state takes vector ones.
+template <int kCfg>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOnly<kCfg> ? 4 : 2))) void bf16_nt_kernel(const desc_gemm_problem* probs,
+                                                         int64_t G, Bf16Ws w) {
+  __shared__ __attribute__((aligned(16)))
+  uint8_t lds[kSmallOnly<kCfg> ? NtSmall::lds_bytes : NtBig::lds_bytes];
   __shared__ int64_t s_g;
   auto block = block_x();
-  auto thread = thread_x<NtTile::threads>();
+  auto thread = thread_x<kBlock>();
   const int64_t T = w.totals[0];
   constexpr idx_t kRun = 64, kXcd = 8;
   const bool by_xcd = block.count() % kXcd == 0;
@@ -447,31 +506,117 @@ __global__ __launch_bounds__(NtTile::threads) void bf16_nt_kernel(const desc_gem
   for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
     const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
     if (t >= T) break;
-    if (thread.index() == 0) s_g = owner(w.nt_start, G, t);
+    if (thread.index() < kWave) {
+      const idx_t g = wave_owner(w.nt_start, G, t);
+      if (thread.index() == 0) s_g = g;
+    }
     sync(thread);
-    const idx_t g = s_g;
+    const idx_t g = wave::uniform_i64(s_g);
     const desc_gemm_problem p = array(probs, G)[g];
     const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
     const Planes pl = planes_of(w, g, d);
-    const idx_t local = t - array(w.nt_start, G + 1)[g], tn = d.Np / kPad;
-    NtOperands ops{{(const uint8_t*)pl.ah, (const uint8_t*)pl.al},
-                   {(const uint8_t*)pl.bh, (const uint8_t*)pl.bl},
-                   d.Kp * 2, p.C, p.ldc, p.M, p.N, nullptr, nullptr};
-    gemm_nt::tile<NtTile>(ops, local / tn, local % tn, lds);
+    const idx_t local = t - array(w.nt_start, G + 1)[g];
+    const NtOperands ops{{(const uint8_t*)pl.ah, (const uint8_t*)pl.al},
+                         {(const uint8_t*)pl.bh, (const uint8_t*)pl.bl},
+                         d.Kp * 2, p.C, p.ldc, p.M, p.N, nullptr, nullptr};
+    // the tile coordinates come out of a vector division: made scalar again
+    if (tile_edge<kCfg>(p.M, p.N) == kPadBig) {
+      const idx_t tn = round_up(p.N, kPadBig) / kPadBig;
+      gemm_nt::tile<NtBig>(ops, wave::uniform_i64(local / tn), wave::uniform_i64(local % tn),
+                           lds);
+    } else {
+      const idx_t tn = d.Ns / kPad;
+      gemm_nt::tile<NtSmall>(ops, wave::uniform_i64(local / tn), wave::uniform_i64(local % tn),
+                             lds);
+    }
     sync(thread);   // s_g and the LDS stages are reused by the next tile
   }
 }
 
+// The fused form: output tiles straight from the FP32 operands, split into
+// hi and lo while they are staged into LDS.
+template <int kCfg>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kCfg == 3 ? 4 : 2)))
+void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
+  static_assert(kFused<kCfg>, "fused configurations only");
+  __shared__ __attribute__((aligned(16)))
+  uint8_t lds[kCfg == 3 ? NtSmall::lds_bytes : NtBig::lds_bytes];
+  __shared__ int64_t s_g;
+  auto block = block_x();
+  auto thread = thread_x<kBlock>();
+  const int64_t T = w.totals[2];
+  constexpr idx_t kRun = 64, kXcd = 8;
+  const bool by_xcd = block.count() % kXcd == 0;
+  const idx_t x = by_xcd ? block.index() % kXcd : 0;
+  const idx_t per = by_xcd ? block.count() / kXcd : block.count();
+  for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
+    const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
+    if (t >= T) break;
+    if (thread.index() < kWave) {
+      const idx_t g = wave_owner(w.fused_start, G, t);
+      if (thread.index() == 0) s_g = g;
+    }
+    sync(thread);
+    const idx_t g = wave::uniform_i64(s_g);
+    const desc_gemm_problem p = array(probs, G)[g];
+    const idx_t local = t - array(w.fused_start, G + 1)[g];
+    constexpr int64_t e = kCfg == 3 ? kPad : kPadBig;
+    const idx_t tn = round_up(p.N, e) / e;
+    const idx_t tm = wave::uniform_i64(local / tn), tc = wave::uniform_i64(local % tn);
+    if (p.K <= 0) {                 // nothing to load: the tile is zero
+      auto c = matrix(p.C, p.M, p.ldc);
+      for (idx_t i = thread.index(); i < e * e; i += kBlock) {
+        const idx_t r = tm * e + i / e, col = tc * e + i % e;
+        if (r < p.M && col < p.N) c.at(r, col) = 0.f;
+      }
+    } else {
+      using Nt = typename std::conditional<kCfg == 3, NtSmall, NtBig>::type;
+      const gemm_nt::F32Operands f{p.A, p.lda, p.B, p.ldb, p.M, p.N, p.K};
+      if (gemm_f32::vec_ok(p.A, p.lda, p.A, p.lda) && p.K % 4 == 0)
+        gemm_nt::tile_split<Nt, true>(f, p.C, p.ldc, tm, tc, lds);
+      else
+        gemm_nt::tile_split<Nt, false>(f, p.C, p.ldc, tm, tc, lds);
+    }
+    sync(thread);   // s_g and the LDS stages are reused by the next tile
+  }
+}
+
+// Blocks of `kernel` that fit the device at once (per device, computed once).
 template <class K>
-int resident_grid(K kernel, int threads, int fallback_per_cu) {
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
-      per < 1)
-    per = fallback_per_cu;
-  return cus * per;
+int resident_grid(K kernel, int (&cache)[64], int fallback_per_cu) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess ||
+        per < 1)
+      per = fallback_per_cu;
+    cache[dev] = cus * per;
+  }
+  return cache[dev];
+}
+
+template <int kCfg>
+hipError_t launch_bf16x3(const desc_gemm_problem* problems, int64_t G, const Bf16Ws& w,
+                         hipStream_t s) {
+  static int split_grid[64] = {0}, nt_grid[64] = {0};
+  hipLaunchKernelGGL(bf16_plan_kernel<kCfg>, dim3(1), dim3(kBlock), 0, s, problems, G, w);
+  if constexpr (kFused<kCfg>) {
+    static int fused_grid[64] = {0};
+    const int gf = resident_grid(bf16_fused_kernel<kCfg>, fused_grid, 2);
+    hipLaunchKernelGGL(bf16_fused_kernel<kCfg>, dim3((unsigned)gf), dim3(kBlock), 0, s, problems,
+                       G, w);
+  }
+  // planes: every problem in configurations 0-2, those with strides past the
+  // split source's limit in the fused ones (the kernels exit at once if none)
+  const int gs = resident_grid(bf16_split_kernel, split_grid, 4);
+  const int gn = resident_grid(bf16_nt_kernel<kCfg>, nt_grid, 2);
+  hipLaunchKernelGGL(bf16_split_kernel, dim3((unsigned)gs), dim3(kBlock), 0, s, problems, G, w);
+  hipLaunchKernelGGL(bf16_nt_kernel<kCfg>, dim3((unsigned)gn), dim3(kBlock), 0, s, problems, G,
+                     w);
+  return hipGetLastError();
 }
 
 constexpr const char* kNames[] = {"tile128_or_64", "tile64"};
@@ -480,29 +625,47 @@ constexpr int64_t kBigMin[] = {256, INT64_MAX};
 const bool kRegistered =
     (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 2, kNames, kDefaults), true);
 
+constexpr const char* kNamesBf16[] = {"tile64", "tile128", "tile128_if_256", "fused64",
+                                      "fused128"};
+constexpr int kDefaultsBf16[tune::kClasses] = {4, 4, 4, 4};
+const bool kRegisteredBf16 =
+    (tune::register_op(tune::kGemmGroupedBf16x3, "gemm_grouped_bf16x3", 5, kNamesBf16,
+                       kDefaultsBf16), true);
+
 }  // namespace
 
 namespace launch {
 
 size_t gemm_grouped_bf16x3_head(int64_t G) { return bf16_head_bytes(G); }
 
-size_t gemm_grouped_bf16x3_planes(int64_t M, int64_t N, int64_t K) {
-  const Bf16Dims d = bf16_dims(M, N, K);
-  return d.huge ? SIZE_MAX : (size_t)bf16_plane_bytes(d);
+size_t gemm_grouped_bf16x3_workspace(const desc_gemm_problem* host, int64_t G) {
+  const int cfg =
+      tune::get(tune::kGemmGroupedBf16x3, tune::size_class(tune::kGemmGroupedBf16x3, G));
+  size_t total = bf16_head_bytes(G);
+  for (int64_t g = 0; g < G; ++g) {
+    const desc_gemm_problem& p = host[g];
+    const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
+    if (d.huge) return SIZE_MAX;
+    if (fused_route(cfg, p.lda, p.ldb)) continue;   // staged from FP32: no planes
+    const size_t b = (size_t)bf16_plane_bytes(d);
+    if (total + b < total) return SIZE_MAX;
+    total += b;
+  }
+  return total;
 }
 
 hipError_t gemm_grouped_bf16x3(const desc_gemm_problem* problems, int64_t G, void* ws,
                                size_t ws_bytes, hipStream_t s) {
+  (void)kRegisteredBf16;
   const Bf16Ws w = bf16_carve(ws, ws_bytes, G);
-  static int grid_split = 0, grid_nt = 0;
-  if (grid_split == 0) grid_split = resident_grid(bf16_split_kernel, kBlock, 4);
-  if (grid_nt == 0) grid_nt = resident_grid(bf16_nt_kernel, NtTile::threads, 2);
-  hipLaunchKernelGGL(bf16_plan_kernel, dim3(1), dim3(kBlock), 0, s, problems, G, w);
-  hipLaunchKernelGGL(bf16_split_kernel, dim3((unsigned)grid_split), dim3(kBlock), 0, s, problems,
-                     G, w);
-  hipLaunchKernelGGL(bf16_nt_kernel, dim3((unsigned)grid_nt), dim3(NtTile::threads), 0, s,
-                     problems, G, w);
-  return hipGetLastError();
+  // the size class is taken from the problem count
+  switch (tune::get(tune::kGemmGroupedBf16x3, tune::size_class(tune::kGemmGroupedBf16x3, G))) {
+    case 1: return launch_bf16x3<1>(problems, G, w, s);
+    case 2: return launch_bf16x3<2>(problems, G, w, s);
+    case 3: return launch_bf16x3<3>(problems, G, w, s);
+    case 4: return launch_bf16x3<4>(problems, G, w, s);
+    default: return launch_bf16x3<0>(problems, G, w, s);
+  }
 }
 
 size_t gemm_grouped_workspace(int64_t G) {

@@ -56,7 +56,9 @@ hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const 
 // grouped.hip
 size_t gemm_grouped_workspace(int64_t G);
 size_t gemm_grouped_bf16x3_head(int64_t G);
-size_t gemm_grouped_bf16x3_planes(int64_t M, int64_t N, int64_t K);   // SIZE_MAX: refused shape
+// head + the planes of the problems the current configuration stages
+// through planes; SIZE_MAX for a refused shape
+size_t gemm_grouped_bf16x3_workspace(const desc_gemm_problem* host, int64_t G);
 hipError_t gemm_grouped_bf16x3(const desc_gemm_problem* problems, int64_t G, void* ws,
                                size_t ws_bytes, hipStream_t s);
 hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* ws,

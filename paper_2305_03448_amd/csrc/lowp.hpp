@@ -4,7 +4,9 @@
 // bfloat16: the upper 16 bits of an IEEE binary32, rounded to nearest with
 // ties to even on the 16 dropped bits; a NaN keeps its upper payload bits
 // with the quiet bit set.  The operand split of the three-product GEMM is
-// hi = bf16(a), lo = bf16(a - hi), where a - hi is exact in FP32.
+// hi = bf16(a), lo = bf16(a - hi), where a - hi is exact in FP32.  Pairs of
+// values are rounded with the hardware conversion, which gives the same bits
+// as the definition on all 2^32 inputs.
 //
 // e4m3 (OCP 8-bit float "E4M3"): sign, 4 exponent bits with bias 7, 3
 // mantissa bits, no infinities, S.1111.111 is NaN, so the largest finite
@@ -28,14 +30,41 @@ __device__ __forceinline__ uint16_t bf16_rne(float a) {
   return (uint16_t)(upper + up);                            // may carry into the exponent
 }
 
-__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Two values rounded by the gfx950 conversion instruction (round to nearest
+// even), a in the low half.
+__device__ __forceinline__ uint32_t bf16x2_hw(float a, float b) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
 
-struct Split {
-  uint16_t hi, lo;
+// bf16_rne of two values, a in the low half.  The hardware conversion gives
+// the same bits as bf16_rne on every one of the 2^32 inputs, NaNs included
+// (checked exhaustively on the device), so it is used as is.
+__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) { return bf16x2_hw(a, b); }
+
+// The three-product split of two values: hi = bf16(a), lo = bf16(a - hi),
+// each pair packed with a in the low half.
+struct Split2 {
+  uint32_t hi, lo;
 };
-__device__ __forceinline__ Split split_bf16(float a) {
-  const uint16_t h = bf16_rne(a);
-  return {h, bf16_rne(a - bf16_value(h))};
+__device__ __forceinline__ Split2 split_bf16x2(float a, float b) {
+  const uint32_t h = bf16x2_rne(a, b);
+  const float ha = __uint_as_float(h << 16), hb = __uint_as_float(h & 0xffff0000u);
+  return {h, bf16x2_rne(a - ha, b - hb)};
+}
+
+// Four values: the bf16 bit patterns of hi and lo in element order.
+typedef uint16_t bf16x4_bits __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_bits __attribute__((ext_vector_type(2)));
+struct Split4 {
+  bf16x4_bits hi, lo;
+};
+__device__ __forceinline__ Split4 split_bf16x4(float a, float b, float c, float d) {
+  const Split2 p = split_bf16x2(a, b), q = split_bf16x2(c, d);
+  const u32x2_bits hi = {p.hi, q.hi}, lo = {p.lo, q.lo};
+  return {__builtin_bit_cast(bf16x4_bits, hi), __builtin_bit_cast(bf16x4_bits, lo)};
 }
 
 __device__ __forceinline__ uint8_t e4m3_rne_sat(float x) {

@@ -36,7 +36,8 @@ void register_op(int op, const char* name, int count, const char* const* names,
 
 int size_class(int op, int64_t size) {
   // element counts: < 2^16, < 2^20, < 2^24, larger;  M*N*K: < 2^24, < 2^30, < 2^36, larger
-  const bool gemm = op == kGemmF32 || op == kGemmBf16x3 || op == kGemmFp8 || op == kGemmGrouped;
+  const bool gemm = op == kGemmF32 || op == kGemmBf16x3 || op == kGemmFp8 || op == kGemmGrouped ||
+                    op == kGemmGroupedBf16x3;
   const int base = gemm ? 24 : 16, step = gemm ? 6 : 4;
   for (int c = 0; c < kClasses - 1; ++c)
     if (size < ((int64_t)1 << (base + step * c))) return c;

@@ -23,7 +23,8 @@ enum Op : int {
   kSegReduceI32 = 7,
   kSegScanI32 = 8,
   kGemmGrouped = 9,
-  kNumOps = 10
+  kGemmGroupedBf16x3 = 10,
+  kNumOps = 11
 };
 constexpr int kClasses = 4;
 

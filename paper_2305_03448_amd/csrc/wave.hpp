@@ -45,5 +45,14 @@ __device__ __forceinline__ uint32_t sum_u32(uint32_t v) {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// A value the caller knows to be equal in every lane (read back from LDS,
+// say), moved to a scalar register so that what is derived from it -- loads
+// of a descriptor, addresses -- stays scalar as well.
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 }  // namespace wave
 }  // namespace desc

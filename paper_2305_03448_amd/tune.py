@@ -100,8 +100,9 @@ def _problems(op: str, dev):
                       desc.desc_reduce_segmented_i32(x, off, r, ws=ws))
                 nbytes = 4 * n
             out.append((desc.desc_size_class(op, n), f"n={n} S={S}", nbytes, fn))
-    elif op == "gemm_grouped":
+    elif op in ("gemm_grouped", "gemm_grouped_bf16x3"):
         # G problems with M, N, K uniform over {64, 128, ..., 1024}
+        mode = "f32" if op == "gemm_grouped" else "bf16x3"
         for G in (64, 512):
             dims = torch.randint(1, 17, (G, 3), device=dev, generator=g) * 64
             probs = []
@@ -112,8 +113,11 @@ def _problems(op: str, dev):
                               torch.empty(M, N, device=dev)))
                 flops += 2 * M * N * K
             d = desc.grouped_descriptors(probs, dev)
-            ws = torch.empty(desc.desc_gemm_grouped_workspace(G), dtype=torch.uint8, device=dev)
-            fn = (lambda d=d, ws=ws, probs=probs: desc.desc_gemm_grouped(d, ws=ws))
+            need = (desc.desc_gemm_grouped_workspace(G) if mode == "f32"
+                    else desc.desc_gemm_grouped_workspace_for(mode, d.cpu()))
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            fn = (lambda d=d, ws=ws, probs=probs, mode=mode:
+                  desc.desc_gemm_grouped(d, mode=mode, ws=ws))
             out.append((desc.desc_size_class(op, G), f"G={G}", flops, fn))
     else:
         raise ValueError(f"no tuning problems for {op}")

@@ -339,6 +339,35 @@ __global__ __launch_bounds__(kCvtThreads) void e4m3_all_inputs(unsigned long lon
   }
 }
 
+// The hardware bf16 conversion against the library's software rounding:
+// every input x is converted once in the low and once in the high half
+// (paired with the bit-reversed pattern).  counts[0]: disagreements on
+// inputs that are not NaNs, counts[1]: on NaNs.
+__global__ __launch_bounds__(kCvtThreads) void bf16_all_inputs(unsigned long long* counts) {
+  __shared__ unsigned long long s_num, s_nan;
+  if (threadIdx.x == 0) { s_num = 0; s_nan = 0; }
+  __syncthreads();
+  unsigned long long n_num = 0, n_nan = 0;
+  const uint64_t base = (uint64_t)blockIdx.x * kCvtThreads * kCvtPer;
+  for (int j = 0; j < kCvtPer; ++j) {
+    const uint32_t i = (uint32_t)(base + (uint64_t)j * kCvtThreads + threadIdx.x);
+    const float x = __uint_as_float(i), y = __uint_as_float(__brev(i));
+    const uint32_t hw1 = desc::lowp::bf16x2_hw(x, y), hw2 = desc::lowp::bf16x2_hw(y, x);
+    const uint32_t sx = desc::lowp::bf16_rne(x), sy = desc::lowp::bf16_rne(y);
+    const bool bad_x = (hw1 & 0xffffu) != sx || (hw2 >> 16) != sx;
+    const bool bad_y = (hw1 >> 16) != sy || (hw2 & 0xffffu) != sy;
+    if (bad_x) { if (__builtin_isnan(x)) ++n_nan; else ++n_num; }
+    if (bad_y) { if (__builtin_isnan(y)) ++n_nan; else ++n_num; }
+  }
+  atomicAdd(&s_num, n_num);
+  atomicAdd(&s_nan, n_nan);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&counts[0], s_num);
+    atomicAdd(&counts[1], s_nan);
+  }
+}
+
 }  // namespace hand
 
 // ---------------------------------------------------------------- C interface
@@ -406,6 +435,13 @@ int hand_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols, 
 // counts: two zeroed unsigned 64-bit counters in GPU memory.
 int hand_e4m3_all_inputs(unsigned long long* counts, hipStream_t s) {
   hipLaunchKernelGGL(hand::e4m3_all_inputs, dim3((unsigned)hand::kCvtBlocks),
+                     dim3(hand::kCvtThreads), 0, s, counts);
+  return (int)hipGetLastError();
+}
+
+// counts: two zeroed unsigned 64-bit counters in GPU memory.
+int hand_bf16_all_inputs(unsigned long long* counts, hipStream_t s) {
+  hipLaunchKernelGGL(hand::bf16_all_inputs, dim3((unsigned)hand::kCvtBlocks),
                      dim3(hand::kCvtThreads), 0, s, counts);
   return (int)hipGetLastError();
 }

@@ -59,6 +59,7 @@ def lib() -> ctypes.CDLL:
             ("hand_transpose_f32", c.c_int, [c.c_void_p, c.c_void_p, c.c_int64, c.c_int64,
                                              c.c_void_p]),
             ("hand_e4m3_all_inputs", c.c_int, [c.c_void_p, c.c_void_p]),
+            ("hand_bf16_all_inputs", c.c_int, [c.c_void_p, c.c_void_p]),
         ):
             f = getattr(L, name)
             f.restype, f.argtypes = res, args
@@ -128,5 +129,16 @@ def e4m3_all_inputs():
     import torch
     counts = torch.zeros(2, dtype=torch.int64, device="cuda")
     _check(lib().hand_e4m3_all_inputs(counts.data_ptr(), _stream(counts)), "hand_e4m3_all_inputs")
+    torch.cuda.synchronize()
+    return int(counts[0].item()), int(counts[1].item())
+
+
+def bf16_all_inputs():
+    """(disagreements on non-NaN inputs, disagreements on NaNs) between the
+    hardware bf16 conversion and the library's software rounding over all
+    2^32 binary32 inputs, each in both halves of the packed pair."""
+    import torch
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda")
+    _check(lib().hand_bf16_all_inputs(counts.data_ptr(), _stream(counts)), "hand_bf16_all_inputs")
     torch.cuda.synchronize()
     return int(counts[0].item()), int(counts[1].item())

@@ -161,22 +161,46 @@ def _problems_host(shapes):
     return (ctypes.c_int64 * max(len(words), 1))(*words)
 
 
+def _problems_host_ld(rows):
+    """Like _problems_host, with explicit (M, N, K, lda, ldb) per problem."""
+    words = []
+    for M, N, K, lda, ldb in rows:
+        words += [M, N, K, lda, ldb, max(N, 1), 0, 0, 0]
+    return (ctypes.c_int64 * max(len(words), 1))(*words)
+
+
 def test_grouped_workspace_for():
     L = desc.lib()
     F32, BF16X3, FP8 = 0, 1, 2
-    # bf16x3: a head of 256 bytes + three 256-aligned arrays of G + 1 int64,
-    # then per problem four bf16 planes (Mp + Np) x Kp with M, N, K rounded
-    # up to multiples of 64 and K at least 64; empty problems take nothing
+    # bf16x3: a head of 256 bytes + four 256-aligned arrays of G + 1 int64,
+    # then, for each problem staged through planes, four bf16 planes
+    # (Ma + Na) x Kp with M, N rounded up to multiples of 128 (either tile
+    # size fits) and K to a multiple of 64 (at least 64); empty problems
+    # take nothing
     shapes = [(100, 90, 80), (0, 5, 5), (5, 7, 0), (64, 64, 64), (1, 1, 1000)]
-    head = 256 + 3 * 256
-    planes = [4 * (128 + 128) * 128, 0, 4 * (64 + 64) * 64, 4 * (64 + 64) * 64,
-              4 * (64 + 64) * 1024]
-    assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == \
-        head + sum(planes)
+    head = 256 + 4 * 256
+    planes = [4 * (128 + 128) * 128, 0, 4 * (128 + 128) * 64, 4 * (128 + 128) * 64,
+              4 * (128 + 128) * 1024]
+    op = desc.OPS["gemm_grouped_bf16x3"]
+    try:
+        for cfg, name in enumerate(["tile64", "tile128", "tile128_if_256"]):
+            assert desc.desc_config_name(op, cfg) == name
+            L.desc_config_set(op, 0, cfg)                 # G < 2^24: size class 0
+            assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == \
+                head + sum(planes)
+        for cfg in (3, 4):                                # fused: planes only past 2^24 strides
+            L.desc_config_set(op, 0, cfg)
+            assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == head
+            rows = [(100, 90, 80, 80, 1 << 24), (100, 90, 80, 80, (1 << 24) + 1),
+                    (100, 90, 80, (1 << 24) + 1, 90)]
+            assert L.desc_gemm_grouped_workspace_for(BF16X3, 3, _problems_host_ld(rows)) == \
+                head + 2 * planes[0]
+    finally:
+        L.desc_config_set(op, 0, -1)
     assert L.desc_gemm_grouped_workspace_for(BF16X3, 0, None) == head
     big_G = 100                                   # (101 * 8) rounded to 256 = 1024
     assert L.desc_gemm_grouped_workspace_for(BF16X3, big_G, _problems_host(
-        [(0, 0, 0)] * big_G)) == 256 + 3 * 1024
+        [(0, 0, 0)] * big_G)) == 256 + 4 * 1024
     assert L.desc_gemm_grouped_workspace_for(F32, 7, None) == L.desc_gemm_grouped_workspace(7)
     assert L.desc_gemm_grouped_workspace_for(FP8, 1, _problems_host(shapes[:1])) == 0
     assert L.desc_gemm_grouped_workspace_for(BF16X3, -1, None) == 0
@@ -190,7 +214,7 @@ def test_grouped_checks(fake_pointers):
     F32, BF16X3, FP8 = 0, 1, 2
     G = 3                                         # 3 x 72 descriptor bytes at D(0)
     wsb = L.desc_gemm_grouped_workspace(G)
-    head3 = 256 + 3 * 256                         # (G + 1) * 8 = 32 bytes per array
+    head3 = 256 + 4 * 256                         # (G + 1) * 8 = 32 bytes per array
     st = lambda *a: L.desc_gemm_grouped(*a, None)
     assert st(F32, 0, None, None, 0) == OK        # nothing to do
     assert st(F32, -1, D(0), D(1 << 20), wsb) == SIZE

@@ -62,6 +62,18 @@ def grouped_config(request):
 
 
 CONFIGS = [0, 1]   # tile128_or_64, tile64
+BF16_CONFIGS = [0, 1, 2, 3, 4]   # tile64, tile128, tile128_if_256, fused64, fused128
+
+
+@pytest.fixture
+def bf16_config(request):
+    """Force one tile configuration of the split-BF16 grouped GEMM."""
+    cfg = request.param
+    for cls in range(4):
+        desc.desc_config_set("gemm_grouped_bf16x3", cls, cfg)
+    yield cfg
+    for cls in range(4):
+        desc.desc_config_set("gemm_grouped_bf16x3", cls, -1)
 
 
 @pytest.mark.parametrize("grouped_config", CONFIGS, indirect=True)
@@ -162,9 +174,10 @@ MIXED = [(64, 64, 64), (1, 1, 1), (300, 257, 65), (256, 256, 16), (1024, 64, 128
          (70, 513, 3), (257, 300, 129), (5, 7, 0), (0, 5, 5), (5, 0, 5), (63, 65, 1000)]
 
 
-def test_grouped_bf16x3_integer_exact_mixed_shapes():
+@pytest.mark.parametrize("bf16_config", BF16_CONFIGS, indirect=True)
+def test_grouped_bf16x3_integer_exact_mixed_shapes(bf16_config):
     # entries in {-4..4} are bf16 numbers: hi = a, lo = 0, every product exact
-    case(f"grouped bf16x3 integer {len(MIXED)} problems")
+    case(f"grouped bf16x3 integer {len(MIXED)} problems config {bf16_config}")
     pairs = _problems(MIXED, 3, integer=True)
     outs, _, _ = _run(pairs, mode="bf16x3")
     for (A, B), C in zip(pairs, outs):
@@ -172,8 +185,9 @@ def test_grouped_bf16x3_integer_exact_mixed_shapes():
         assert np.array_equal(C, exact), A.shape
 
 
-def test_grouped_bf16x3_strided_mixed_shapes():
-    case(f"grouped bf16x3 strided lda, {len(MIXED)} problems")
+@pytest.mark.parametrize("bf16_config", BF16_CONFIGS, indirect=True)
+def test_grouped_bf16x3_strided_mixed_shapes(bf16_config):
+    case(f"grouped bf16x3 strided lda, {len(MIXED)} problems config {bf16_config}")
     pairs = _problems(MIXED, 7)
     outs, _, _ = _run(pairs, pad=3, mode="bf16x3")
     frac, long_k = _check_all(pairs, outs)
@@ -182,7 +196,8 @@ def test_grouped_bf16x3_strided_mixed_shapes():
     assert frac <= 1.0
 
 
-def test_grouped_bf16x3_workspace_too_small_sets_error():
+@pytest.mark.parametrize("bf16_config", [1], indirect=True)   # a configuration with planes
+def test_grouped_bf16x3_workspace_too_small_sets_error(bf16_config):
     pairs = _problems([(100, 90, 80), (64, 64, 64)], 8)
     dev_pairs = [(to_dev(A), to_dev(B),
                   torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=torch.float32,
@@ -193,18 +208,19 @@ def test_grouped_bf16x3_workspace_too_small_sets_error():
     small = torch.zeros(need - 256, dtype=torch.uint8, device=dev())
     desc.desc_gemm_grouped(d, mode="bf16x3", ws=small)
     torch.cuda.synchronize()
-    assert small[16:20].view(torch.int32).item() == 1
+    assert small[32:36].view(torch.int32).item() == 1
     for _, _, C in dev_pairs:
         assert torch.isnan(C).all()           # nothing computed
     case("grouped bf16x3 workspace of the full size")
     ws = torch.full((need,), 0xAB, dtype=torch.uint8, device=dev())
     desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws)
     torch.cuda.synchronize()
-    assert ws[16:20].view(torch.int32).item() == 0
+    assert ws[32:36].view(torch.int32).item() == 0
     assert _check_all(pairs, [C.cpu().numpy() for _, _, C in dev_pairs])[0] <= 1.0
 
 
-def test_grouped_bf16x3_graph_replay():
+@pytest.mark.parametrize("bf16_config", BF16_CONFIGS, indirect=True)
+def test_grouped_bf16x3_graph_replay(bf16_config):
     pairs = _problems([(200, 100, 300), (64, 640, 64), (512, 512, 64), (3, 5, 0)], 6)
     outs, dp, d = _run(pairs, mode="bf16x3")
     need = desc.desc_gemm_grouped_workspace_for("bf16x3", d.cpu())
@@ -215,7 +231,7 @@ def test_grouped_bf16x3_graph_replay():
     with torch.cuda.graph(g, stream=s):
         desc.desc_gemm_grouped(d, mode="bf16x3", ws=ws)
     for rep in range(3):
-        case(f"grouped bf16x3 graph replay {rep}")
+        case(f"grouped bf16x3 graph replay {rep} config {bf16_config}")
         for _, _, C in dp:
             C.fill_(0)
         ws.fill_(0x5A)                        # planes and plan rewritten by every replay
@@ -226,8 +242,10 @@ def test_grouped_bf16x3_graph_replay():
             assert np.array_equal(C.cpu().numpy(), want)
 
 
-def test_grouped_bf16x3_workload_512():
-    case("grouped bf16x3 512 problems (seeds 12/13/14)")
+@pytest.mark.parametrize("bf16_config", BF16_CONFIGS, indirect=True)
+def test_grouped_bf16x3_workload_512(bf16_config):
+    assert desc.desc_config_count("gemm_grouped_bf16x3") == len(BF16_CONFIGS)
+    case(f"grouped bf16x3 512 problems (seeds 12/13/14) config {bf16_config}")
     shapes = workloads.grouped_shapes()
     pairs = workloads.grouped_operands(shapes)
     outs, _, _ = _run(pairs, mode="bf16x3")
@@ -239,3 +257,25 @@ def test_grouped_bf16x3_workload_512():
         worst = max(worst, float(err.max()))
     print(f"[result] grouped bf16x3 512 worst componentwise error {worst:.3e}")
     assert worst <= TOL
+
+
+@pytest.mark.parametrize("bf16_config", [3, 4], indirect=True)
+def test_grouped_bf16x3_fused_routes_long_strides_through_planes(bf16_config):
+    # a B stride past the split source's limit (2^24 elements): that problem
+    # goes through the planes while the other is staged from FP32
+    case(f"grouped bf16x3 ldb = 2^24 + 7 next to a plain problem, config {bf16_config}")
+    g = workloads.rng(30)
+    M, N, K, ldb = 70, 50, 3, (1 << 24) + 7
+    A1 = g.standard_normal((M, K)).astype(np.float32)
+    B1 = g.standard_normal((K, N)).astype(np.float32)
+    Bbig = torch.zeros((K, ldb), dtype=torch.float32, device=dev())
+    Bbig[:, :N] = torch.from_numpy(B1).to(dev())
+    A2, B2 = _problems([(130, 90, 70)], 31)[0]
+    C1 = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
+    C2 = torch.full((130, 90), float("nan"), dtype=torch.float32, device=dev())
+    d = desc.grouped_descriptors([(to_dev(A1), Bbig[:, :N], C1), (to_dev(A2), to_dev(B2), C2)],
+                                 dev())
+    desc.desc_gemm_grouped(d, mode="bf16x3")
+    torch.cuda.synchronize()
+    frac, _ = _check_all([(A1, B1), (A2, B2)], [C1.cpu().numpy(), C2.cpu().numpy()])
+    assert frac <= 1.0

@@ -70,3 +70,11 @@ def test_hardware_e4m3_matches_encoder_on_every_input():
     inside, outside = handlib.e4m3_all_inputs()
     assert inside == 0
     assert outside > 0   # NaN codes from 464 up: why larger magnitudes use the software path
+
+
+def test_hardware_bf16_matches_rounding_on_every_input():
+    # the split uses the hardware conversion for every input
+    case("bf16 hardware vs software over all 2^32 inputs")
+    numbers, nans = handlib.bf16_all_inputs()
+    print(f"[result] bf16 hardware disagreements: {numbers} numbers, {nans} NaNs")
+    assert numbers == 0 and nans == 0
