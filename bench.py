@@ -293,7 +293,7 @@ def op_gemm(desc, torch, workloads, oracle, n, seeds, modes):
     for mode in modes:
         need = desc.desc_gemm_workspace(mode, n, n, n)
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
-        ms = events_time_ms(torch, lambda: desc.desc_gemm(A, B, C, mode=mode, ws=ws), reps=5)
+        ms = graph_time_ms(torch, lambda: desc.desc_gemm(A, B, C, mode=mode, ws=ws), reps=5)
         Cs = C.cpu().numpy()[ii, jj].astype(np.float64)
         comp = np.abs(Cs - R) / D
         rel = np.abs(Cs - R) / np.maximum(np.abs(R), 1e-300)

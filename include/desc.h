@@ -193,8 +193,8 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
  *                     persistent kernel over 128 x 128 output tiles that
  *                     splits the FP32 operands into hi and lo while staging
  *                     them (no operand copies).  Problems with lda or ldb
- *                     above 2^24, and every problem in the "tile*"
- *                     configurations, go through bf16 planes instead: a
+ *                     above 2^24, and every problem in the "tile64" and
+ *                     "tile128" configurations, go through bf16 planes: a
  *                     persistent kernel splits their operands into planes
  *                     padded to multiples of 128 (M, N) and 64 (K, at least
  *                     64) inside the workspace, and a persistent kernel

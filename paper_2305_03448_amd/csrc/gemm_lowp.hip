@@ -383,6 +383,29 @@ __global__ __launch_bounds__(C::threads) void gemm_nt_kernel(NtOperands p, int64
   gemm_nt::tile<C>(p, t / tiles_n, t % tiles_n, lds);
 }
 
+// Split-BF16 tiles straight from the FP32 operands (no pre-pass).
+template <class C, bool kVec>
+__global__ __launch_bounds__(C::threads) void gemm_split_kernel(gemm_nt::F32Operands f,
+                                                                float* __restrict__ Cm,
+                                                                int64_t ldc, int64_t tiles_m,
+                                                                int64_t tiles_n) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[C::lds_bytes];
+  const idx_t t = gemm_f32::xcd_tile(block_x(), tiles_m, tiles_n);
+  gemm_nt::tile_split<C, kVec>(f, Cm, ldc, t / tiles_n, t % tiles_n, lds);
+}
+
+template <class C>
+hipError_t launch_split(const gemm_nt::F32Operands& f, float* Cm, int64_t ldc, hipStream_t s) {
+  const int64_t tm = (f.M + C::bm - 1) / C::bm, tn = (f.N + C::bn - 1) / C::bn;
+  if (gemm_f32::vec_ok(f.A, f.lda, f.A, f.lda) && f.K % 4 == 0)
+    hipLaunchKernelGGL((gemm_split_kernel<C, true>), dim3((unsigned)(tm * tn)), dim3(C::threads),
+                       0, s, f, Cm, ldc, tm, tn);
+  else
+    hipLaunchKernelGGL((gemm_split_kernel<C, false>), dim3((unsigned)(tm * tn)),
+                       dim3(C::threads), 0, s, f, Cm, ldc, tm, tn);
+  return hipGetLastError();
+}
+
 template <class C>
 hipError_t launch_nt(const NtOperands& p, int64_t Mp, int64_t Np, hipStream_t s) {
   const int64_t tm = Mp / C::bm, tn = Np / C::bn;
@@ -430,14 +453,16 @@ unsigned grid_for(int64_t items) {
   return (unsigned)(g < 1 ? 1 : g);
 }
 
-// "_w8": eight waves (2 x 4) share the tile instead of four (2 x 2).
+// "_w8": eight waves (2 x 4) share the tile instead of four (2 x 2);
+// "_fused": the operands split while they are staged (no pre-pass).
 constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32",
-                                      "m256n256k32_d1", "m256n256k32_w8d1"};
+                                      "m256n256k32_d1", "m256n256k32_w8d1",
+                                      "m128n128k32_fused", "m256n256k32_w8d1_fused"};
 constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
                                      "m128n256k128", "m256n128k64", "m256n256k64_w8d1"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 5, kNamesBf16, kDefaults),
+    (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 7, kNamesBf16, kDefaults),
      tune::register_op(tune::kGemmFp8, "gemm_fp8", 6, kNamesFp8, kDefaults), true);
 
 }  // namespace
@@ -496,6 +521,14 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
 hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
                        int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws, hipStream_t s) {
   (void)kRegistered;
+  const int cfg = tune::get(tune::kGemmBf16x3, tune::size_class(tune::kGemmBf16x3, M * N * K));
+  if (cfg >= 5 && K > 0 && lda <= gemm_nt::kSplitMaxLd && ldb <= gemm_nt::kSplitMaxLd) {
+    const gemm_nt::F32Operands f{A, lda, B, ldb, M, N, K};
+    if (cfg == 6) return launch_split<NtCfg<256, 256, 64, Bf16x3Mode, 1, 2, 4>>(f, Cm, ldc, s);
+    return launch_split<NtCfg<128, 128, 64, Bf16x3Mode>>(f, Cm, ldc, s);
+  }
+  // the pre-pass form (also the fused configurations' path for K = 0 and
+  // strides past the split source's limit)
   const LowpLayout L = layout(1, M, N, K);
   uint8_t* w = (uint8_t*)ws;
   uint16_t *ah = (uint16_t*)(w + L.off[0]), *al = (uint16_t*)(w + L.off[1]);
@@ -507,11 +540,12 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
   NtOperands p{{(const uint8_t*)ah, (const uint8_t*)al},
                {(const uint8_t*)bh, (const uint8_t*)bl},
                L.Kp * 2, Cm, ldc, M, N, nullptr, nullptr};
-  switch (tune::get(tune::kGemmBf16x3, tune::size_class(tune::kGemmBf16x3, M * N * K))) {
+  switch (cfg) {
     case 1: return launch_nt<NtCfg<256, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
     case 2: return launch_nt<NtCfg<128, 256, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
     case 3: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1>>(p, L.Mp, L.Np, s);
-    case 4: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
+    case 4:
+    case 6: return launch_nt<NtCfg<256, 256, 64, Bf16x3Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 64, Bf16x3Mode>>(p, L.Mp, L.Np, s);
   }
 }

@@ -111,6 +111,7 @@ struct PlaneSource {
   struct Regs {
     u32x4 a[P][C::a_chunks], b[P][C::b_chunks];
   };
+  static constexpr bool kStaticTail = false;
   const NtOperands& p;
   idx_t m0, n0;
 
@@ -209,6 +210,7 @@ struct SplitSource {
   struct Regs {
     f32x4 a[AO][2], b[BO][2];   // an octet as two groups of four values
   };
+  static constexpr bool kStaticTail = true;
   const F32Operands& p;
   idx_t m0, n0;
 
@@ -423,23 +425,34 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
       store(R0, 0);
       sync(thread);
     }
-    // At most three iterations are left and kt is even; they are written
-    // out so that each names its register sets statically (a set chosen at
-    // run time would have to live in memory).
-    if (kt < nk) {
-      if (kt + 2 < nk) load(kt + 2, R0);
-      compute(0);
-      if (kt + 1 < nk) store(R1, 1);
-      sync(thread);
-    }
-    if (kt + 1 < nk) {
-      compute(1);
-      if (kt + 2 < nk) store(R0, 0);
-      sync(thread);
-    }
-    if (kt + 2 < nk) {
-      compute(0);
-      sync(thread);
+    // At most three iterations are left, kt even.  With the split source
+    // they are written out so that each names its register sets statically:
+    // a set chosen at run time lives in memory when its values are not plain
+    // copies.  The plane source keeps the loop, which allocates better there.
+    if constexpr (Src::kStaticTail) {
+      if (kt < nk) {
+        if (kt + 2 < nk) load(kt + 2, R0);
+        compute(0);
+        if (kt + 1 < nk) store(R1, 1);
+        sync(thread);
+      }
+      if (kt + 1 < nk) {
+        compute(1);
+        if (kt + 2 < nk) store(R0, 0);
+        sync(thread);
+      }
+      if (kt + 2 < nk) {
+        compute(0);
+        sync(thread);
+      }
+    } else {
+      for (; kt < nk; ++kt) {
+        const bool even = (kt & 1) == 0;
+        if (kt + 2 < nk) load(kt + 2, even ? R0 : R1);
+        compute((int)(kt & 1));
+        if (kt + 1 < nk) store(even ? R1 : R0, (int)((kt + 1) & 1));
+        sync(thread);
+      }
     }
   }
 

@@ -285,18 +285,15 @@ __host__ __device__ inline Bf16Dims bf16_dims(int64_t M, int64_t N, int64_t K) {
 __host__ __device__ inline int64_t bf16_plane_bytes(const Bf16Dims& d) {
   return round_up(4 * (d.Ma + d.Na) * d.Kp, 256);
 }
-// Configurations: 0-2 split into planes first, 3-4 split while staging
-// (fused: no planes).  Output tile edge of a problem: 64 (0, 3), 128 (1, 4),
-// or 128 when M and N are both at least 256 (2).
+// Configurations: 0-1 split into planes first, 2-3 split while staging
+// (fused: no planes).  Output tiles of 64 x 64 (0, 2) or 128 x 128 (1, 3).
 template <int kCfg>
-constexpr bool kFused = kCfg >= 3;
+constexpr bool kFused = kCfg >= 2;
 template <int kCfg>
-constexpr bool kSmallOnly = kCfg == 0 || kCfg == 3;   // 64 x 64 tiles only
+constexpr bool kSmallOnly = kCfg == 0 || kCfg == 2;   // 64 x 64 tiles
 template <int kCfg>
-__device__ __forceinline__ int64_t tile_edge(int64_t M, int64_t N) {
-  if constexpr (kCfg == 0 || kCfg == 3) return kPad;
-  if constexpr (kCfg == 1 || kCfg == 4) return kPadBig;
-  return M >= 256 && N >= 256 ? kPadBig : kPad;
+__device__ __forceinline__ int64_t tile_edge(int64_t, int64_t) {
+  return kSmallOnly<kCfg> ? kPad : kPadBig;
 }
 
 struct Bf16Ws {
@@ -331,7 +328,7 @@ Bf16Ws bf16_carve(void* ws, size_t ws_bytes, int64_t G) {
 // operands when its strides allow (the split source's buffer ranges), and
 // through planes otherwise; the other configurations use planes throughout.
 __host__ __device__ inline bool fused_route(int cfg, int64_t lda, int64_t ldb) {
-  return cfg >= 3 && lda <= gemm_nt::kSplitMaxLd && ldb <= gemm_nt::kSplitMaxLd;
+  return cfg >= 2 && lda <= gemm_nt::kSplitMaxLd && ldb <= gemm_nt::kSplitMaxLd;
 }
 template <int kCfg>
 __device__ __forceinline__ bool fused_for(const desc_gemm_problem& p) {
@@ -520,14 +517,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOn
                          {(const uint8_t*)pl.bh, (const uint8_t*)pl.bl},
                          d.Kp * 2, p.C, p.ldc, p.M, p.N, nullptr, nullptr};
     // the tile coordinates come out of a vector division: made scalar again
-    if (tile_edge<kCfg>(p.M, p.N) == kPadBig) {
-      const idx_t tn = round_up(p.N, kPadBig) / kPadBig;
-      gemm_nt::tile<NtBig>(ops, wave::uniform_i64(local / tn), wave::uniform_i64(local % tn),
-                           lds);
-    } else {
+    if constexpr (kSmallOnly<kCfg>) {
       const idx_t tn = d.Ns / kPad;
       gemm_nt::tile<NtSmall>(ops, wave::uniform_i64(local / tn), wave::uniform_i64(local % tn),
                              lds);
+    } else {
+      const idx_t tn = round_up(p.N, kPadBig) / kPadBig;
+      gemm_nt::tile<NtBig>(ops, wave::uniform_i64(local / tn), wave::uniform_i64(local % tn),
+                           lds);
     }
     sync(thread);   // s_g and the LDS stages are reused by the next tile
   }
@@ -536,11 +533,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOn
 // The fused form: output tiles straight from the FP32 operands, split into
 // hi and lo while they are staged into LDS.
 template <int kCfg>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kCfg == 3 ? 4 : 2)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOnly<kCfg> ? 3 : 2)))
 void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
   static_assert(kFused<kCfg>, "fused configurations only");
   __shared__ __attribute__((aligned(16)))
-  uint8_t lds[kCfg == 3 ? NtSmall::lds_bytes : NtBig::lds_bytes];
+  uint8_t lds[kSmallOnly<kCfg> ? NtSmall::lds_bytes : NtBig::lds_bytes];
   __shared__ int64_t s_g;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
@@ -560,7 +557,7 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
     const idx_t g = wave::uniform_i64(s_g);
     const desc_gemm_problem p = array(probs, G)[g];
     const idx_t local = t - array(w.fused_start, G + 1)[g];
-    constexpr int64_t e = kCfg == 3 ? kPad : kPadBig;
+    constexpr int64_t e = kSmallOnly<kCfg> ? kPad : kPadBig;
     const idx_t tn = round_up(p.N, e) / e;
     const idx_t tm = wave::uniform_i64(local / tn), tc = wave::uniform_i64(local % tn);
     if (p.K <= 0) {                 // nothing to load: the tile is zero
@@ -570,7 +567,7 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
         if (r < p.M && col < p.N) c.at(r, col) = 0.f;
       }
     } else {
-      using Nt = typename std::conditional<kCfg == 3, NtSmall, NtBig>::type;
+      using Nt = typename std::conditional<kSmallOnly<kCfg>, NtSmall, NtBig>::type;
       const gemm_nt::F32Operands f{p.A, p.lda, p.B, p.ldb, p.M, p.N, p.K};
       if (gemm_f32::vec_ok(p.A, p.lda, p.A, p.lda) && p.K % 4 == 0)
         gemm_nt::tile_split<Nt, true>(f, p.C, p.ldc, tm, tc, lds);
@@ -625,11 +622,10 @@ constexpr int64_t kBigMin[] = {256, INT64_MAX};
 const bool kRegistered =
     (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 2, kNames, kDefaults), true);
 
-constexpr const char* kNamesBf16[] = {"tile64", "tile128", "tile128_if_256", "fused64",
-                                      "fused128"};
-constexpr int kDefaultsBf16[tune::kClasses] = {4, 4, 4, 4};
+constexpr const char* kNamesBf16[] = {"tile64", "tile128", "fused64", "fused128"};
+constexpr int kDefaultsBf16[tune::kClasses] = {3, 3, 3, 3};
 const bool kRegisteredBf16 =
-    (tune::register_op(tune::kGemmGroupedBf16x3, "gemm_grouped_bf16x3", 5, kNamesBf16,
+    (tune::register_op(tune::kGemmGroupedBf16x3, "gemm_grouped_bf16x3", 4, kNamesBf16,
                        kDefaultsBf16), true);
 
 }  // namespace
@@ -663,7 +659,6 @@ hipError_t gemm_grouped_bf16x3(const desc_gemm_problem* problems, int64_t G, voi
     case 1: return launch_bf16x3<1>(problems, G, w, s);
     case 2: return launch_bf16x3<2>(problems, G, w, s);
     case 3: return launch_bf16x3<3>(problems, G, w, s);
-    case 4: return launch_bf16x3<4>(problems, G, w, s);
     default: return launch_bf16x3<0>(problems, G, w, s);
   }
 }

@@ -183,12 +183,12 @@ def test_grouped_workspace_for():
               4 * (128 + 128) * 1024]
     op = desc.OPS["gemm_grouped_bf16x3"]
     try:
-        for cfg, name in enumerate(["tile64", "tile128", "tile128_if_256"]):
+        for cfg, name in enumerate(["tile64", "tile128"]):
             assert desc.desc_config_name(op, cfg) == name
             L.desc_config_set(op, 0, cfg)                 # G < 2^24: size class 0
             assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == \
                 head + sum(planes)
-        for cfg in (3, 4):                                # fused: planes only past 2^24 strides
+        for cfg in (2, 3):                                # fused: planes only past 2^24 strides
             L.desc_config_set(op, 0, cfg)
             assert L.desc_gemm_grouped_workspace_for(BF16X3, 5, _problems_host(shapes)) == head
             rows = [(100, 90, 80, 80, 1 << 24), (100, 90, 80, 80, (1 << 24) + 1),

@@ -105,6 +105,31 @@ def test_gemm_bf16x3_short_k_within_a_priori_bound(K):
           f"(bound {bf16x3_bound(K):.3e})", flush=True)
 
 
+@pytest.mark.parametrize("cfg", ["m128n128k32_fused", "m256n256k32_w8d1_fused"])
+def test_gemm_bf16x3_fused_shapes(cfg):
+    # operands split while staged: ragged edges, K not a multiple of the
+    # stage, an unaligned row stride (single loads), K = 0 (pre-pass form)
+    op = "gemm_bf16x3"
+    names = [desc.desc_config_name(op, c) for c in range(desc.desc_config_count(op))]
+    idx = names.index(cfg)
+    try:
+        for M, N, K, pad in [(77, 53, 45, 3), (300, 260, 100, 0), (1, 1, 1, 0),
+                             (257, 129, 1000, 1), (64, 300, 0, 0), (513, 70, 96, 0)]:
+            case(f"gemm bf16x3 {cfg} {M}x{N}x{K} lda pad {pad}")
+            for cls in range(4):
+                desc.desc_config_set(op, cls, idx)
+            A = workloads.matrix_f32(M, K, seed=40); B = workloads.matrix_f32(K, N, seed=41)
+            C = _run(A, B, "bf16x3", lda_pad=pad, ldc_pad=2)
+            if K == 0:
+                assert (C == 0).all()
+                continue
+            tol = TOL["bf16x3"] if K >= 64 else bf16x3_bound(K)
+            _check_sampled(A, B, C, tol, samples=min(M * N, 4096))
+    finally:
+        for cls in range(4):
+            desc.desc_config_set(op, cls, -1)
+
+
 @pytest.mark.parametrize("mode", ["f32", "bf16x3"])
 def test_gemm_strided_rows(mode):
     case(f"gemm {mode} strided lda/ldc")

@@ -62,7 +62,7 @@ def grouped_config(request):
 
 
 CONFIGS = [0, 1]   # tile128_or_64, tile64
-BF16_CONFIGS = [0, 1, 2, 3, 4]   # tile64, tile128, tile128_if_256, fused64, fused128
+BF16_CONFIGS = [0, 1, 2, 3]   # tile64, tile128, fused64, fused128
 
 
 @pytest.fixture
@@ -259,7 +259,7 @@ def test_grouped_bf16x3_workload_512(bf16_config):
     assert worst <= TOL
 
 
-@pytest.mark.parametrize("bf16_config", [3, 4], indirect=True)
+@pytest.mark.parametrize("bf16_config", [2, 3], indirect=True)
 def test_grouped_bf16x3_fused_routes_long_strides_through_planes(bf16_config):
     # a B stride past the split source's limit (2^24 elements): that problem
     # goes through the planes while the other is staged from FP32
