@@ -49,6 +49,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_reduce_i32.restype = I64
         L.oracle_scan_i32.argtypes = [P, P, I64, P]
         L.oracle_scan_i32.restype = ctypes.c_int
+        L.oracle_scan_exclusive_i32.argtypes = [P, P, I64]
         L.oracle_transpose_u32.argtypes = [P, P, I64, I64]
         L.oracle_gemm_ref_sampled.argtypes = [P, I64, P, I64, I64, P, P, I64, P, P]
         L.oracle_bf16_rne.argtypes = [F]
@@ -92,6 +93,14 @@ def scan_i32(x, return_info: bool = False):
     wrapped = lib().oracle_scan_i32(_p(x), _p(y), x.size, ctypes.byref(m))
     if return_info:
         return y, bool(wrapped), int(m.value)
+    return y
+
+
+def scan_exclusive_i32(x):
+    """y[0] = 0, y[i] = (x[0] + ... + x[i-1]) mod 2^32 as int32."""
+    x = _c(x, np.int32)
+    y = np.empty_like(x)
+    lib().oracle_scan_exclusive_i32(_p(x), _p(y), x.size)
     return y
 
 

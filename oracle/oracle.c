@@ -14,7 +14,8 @@
  *   - scan        : inclusive prefix sum, wrapping modulo 2^32 (Sec. 5,
  *                   "scan"; the paper fixes neither the kind of scan nor
  *                   its overflow behaviour: inclusive, int32 in and out,
- *                   two's-complement wrap is the reading taken here)
+ *                   two's-complement wrap is the reading taken here);
+ *                   the exclusive form shifts it by one place, from 0
  *   - transpose   : out[c][r] = in[r][c] as a 32-bit pattern move (Sec. 1,
  *                   Listings 1 and 2; Sec. 5 "matrix transposition")
  *   - GEMM        : C = A*B, reference entries in FP64 with the absolute
@@ -64,6 +65,18 @@ int oracle_scan_i32(const int32_t *x, int32_t *y, int64_t n, int64_t *max_abs)
     }
     if (max_abs) *max_abs = m;
     return m > INT32_MAX ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exclusive scan: y_0 = 0, y_i = (x_0 + ... + x_(i-1)) mod 2^32.       */
+/* ------------------------------------------------------------------ */
+void oracle_scan_exclusive_i32(const int32_t *x, int32_t *y, int64_t n)
+{
+    uint32_t acc = 0;          /* modular total of the elements before i */
+    for (int64_t i = 0; i < n; ++i) {
+        y[i] = (int32_t)acc;
+        acc += (uint32_t)x[i];
+    }
 }
 
 /* ------------------------------------------------------------------ */

@@ -120,3 +120,37 @@ def test_scan_workload_never_wraps():
     x = workloads.int_uniform(1 << 24, seed=2)
     _, wrapped, m = oracle.scan_i32(x, return_info=True)
     assert not wrapped and m < 2**28
+
+
+# ----------------------------------------------------------------- exclusive scan
+@pytest.mark.parametrize("n,a,d", [(1, -7, 0), (1000, -500, 1), (5000, 1024, -1), (70000, 3, 2)])
+def test_scan_exclusive_arithmetic_closed_form(n, a, d):
+    # x_k = a + d k: the sum of the k terms before position k is k a + d k (k - 1) / 2
+    x = workloads.arithmetic_i32(n, a, d)
+    y = oracle.scan_exclusive_i32(x)
+    expect = [_wrap32(int(k) * a + d * int(k) * (int(k) - 1) // 2) for k in range(n)]
+    assert y.tolist() == expect
+
+
+def test_scan_exclusive_bruteforce_tiny():
+    vals = (-2, 0, 1, 2)
+    for length in range(0, 5):
+        for xs in itertools.product(vals, repeat=length):
+            y = oracle.scan_exclusive_i32(np.array(xs, dtype=np.int32))
+            assert y.tolist() == [sum(xs[:k]) for k in range(length)]
+
+
+def test_scan_exclusive_invariants_random():
+    x = workloads.int_uniform(1 << 20, seed=2)
+    y = oracle.scan_exclusive_i32(x)
+    assert y[0] == 0
+    # the last exclusive prefix plus the last element is the total
+    assert int(y[-1]) + int(x[-1]) == oracle.reduce_i32(x)
+    # differences recover the input
+    assert np.array_equal(np.diff(y.astype(np.int64)), x[:-1].astype(np.int64))
+
+
+def test_scan_exclusive_wraps_modulo_2_32():
+    x = np.full(5, 2**31 - 1, np.int32)
+    y = oracle.scan_exclusive_i32(x)
+    assert y.tolist() == [_wrap32(k * (2**31 - 1)) for k in range(5)]
