@@ -210,6 +210,12 @@ def op_variants(desc, torch, workloads, reps: int = 20):
     out["scan_two_kernels"] = {"us": round(two, 2), "GBs_algorithmic": round(8 * n / two / 1e3, 1),
                                "GBs_moved": round(12 * n / two / 1e3, 1),
                                "equal": bool(torch.equal(y1, y2))}
+    excl = median_us(lambda: desc.desc_scan_exclusive_i32(x, y2))
+    y1_last = int(y1[-1].item()); y2_last = int(y2[-1].item()); x_last = int(x[-1].item())
+    out["scan_exclusive_single_pass"] = {
+        "us": round(excl, 2), "GBs": round(8 * n / excl / 1e3, 1),
+        "consistent": bool(int(y2[0].item()) == 0 and
+                           (y2_last + x_last - y1_last) % (1 << 32) == 0)}
     full = median_us(lambda: desc.desc_reduce_i32(x, r))
     out["reduce_full"] = {"us": round(full, 2), "GBs": round(4 * n / full / 1e3, 1)}
     for E, o in blocks.items():
@@ -308,6 +314,12 @@ def op_gemm(desc, torch, workloads, oracle, n, seeds, modes):
                      "err_elementwise_median": float(f"{np.median(rel):.3e}"),
                      "err_normwise": float(f"{np.abs(Cs - R).max() / np.abs(R).max():.3e}"),
                      "within_1e-5": bool(comp.max() <= 1e-5)}
+    # context, not this library: the vendor FP32 GEMM behind torch.mm (hipBLASLt / rocBLAS)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    ms = graph_time_ms(torch, lambda: torch.mm(A, B, out=C), reps=5)
+    Cs = C.cpu().numpy()[ii, jj].astype(np.float64)
+    out["vendor_sgemm_context"] = {"us": round(ms * 1e3, 1), "TFLOPs": round(2 * n ** 3 / ms / 1e9, 2),
+                                   "err_componentwise_max": float(f"{(np.abs(Cs - R) / D).max():.3e}")}
     del A, B, C
     torch.cuda.empty_cache()
     return out

@@ -90,6 +90,12 @@ size_t desc_scan_i32_workspace(int64_t n);
 desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
                           size_t ws_bytes, void* stream);
 
+/* Exclusive form of the same scan: out[0] = 0, out[i] = in[0] + ... +
+ * in[i-1] modulo 2^32.  Same single pass, same workspace
+ * (desc_scan_i32_workspace(n) bytes), same checks. */
+desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                                    size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * The paper's own forms of the two operations above (Sec. 5), for
  * comparison with the single-pass forms.

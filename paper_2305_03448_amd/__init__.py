@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libdesc.so")
 __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
-    "desc_scan_i32_workspace", "desc_scan_i32", "desc_reduce_blocks_i32",
+    "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_copy_32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
@@ -54,6 +54,7 @@ SIGNATURES = {
     "desc_reduce_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
     "desc_scan_i32_workspace": (_SZ, [_I64]),
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
+    "desc_scan_exclusive_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_reduce_blocks_i32": (_ST, [_P, _I64, _I64, _P, _P]),
     "desc_scan_two_pass_i32_workspace": (_SZ, [_I64]),
     "desc_scan_two_pass_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
@@ -213,6 +214,20 @@ def desc_scan_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = 
     w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
     _check(lib().desc_scan_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
            "desc_scan_i32")
+    return out
+
+
+def desc_scan_exclusive_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                            stream=None) -> torch.Tensor:
+    """Exclusive scan of int32 ``x`` into ``out``: out[0] = 0, out[i] = x[0] + ... + x[i-1]
+    (wrapping modulo 2^32)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many elements as x")
+    n = x.numel()
+    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
+    _check(lib().desc_scan_exclusive_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(),
+                                         _stream(x, stream)), "desc_scan_exclusive_i32")
     return out
 
 

@@ -132,8 +132,9 @@ size_t desc_scan_i32_workspace(int64_t n) {
   return desc::launch::scan_i32_workspace(n < 0 ? 0 : n);
 }
 
-desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
-                          size_t ws_bytes, void* stream) {
+namespace {
+desc_status scan_checked(const int32_t* in, int32_t* out, int64_t n, void* ws, size_t ws_bytes,
+                         void* stream, bool exclusive) {
   if (ws == nullptr || ((in == nullptr || out == nullptr) && n > 0)) return DESC_ERR_NULL;
   const int64_t nb = bytes_of(n, 4);
   if (nb < 0) return DESC_ERR_SIZE;
@@ -144,7 +145,18 @@ desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
       overlap({ws, (int64_t)ws_bytes}, {out, nb}))
     return DESC_ERR_ALIAS;
   if (ws_bytes < desc_scan_i32_workspace(n)) return DESC_ERR_WORKSPACE;
-  return hip_status(desc::launch::scan_i32(in, out, n, ws, (hipStream_t)stream));
+  return hip_status(desc::launch::scan_i32(in, out, n, ws, (hipStream_t)stream, exclusive));
+}
+}  // namespace
+
+desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return scan_checked(in, out, n, ws, ws_bytes, stream, false);
+}
+
+desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return scan_checked(in, out, n, ws, ws_bytes, stream, true);
 }
 
 // ----------------------------------------------------------------- the paper's forms

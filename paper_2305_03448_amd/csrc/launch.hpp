@@ -18,7 +18,8 @@ hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipS
 
 // scan.hip
 size_t scan_i32_workspace(int64_t n);
-hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s);
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
+                    bool exclusive = false);
 
 // transpose.hip
 int64_t transpose_max_rows();

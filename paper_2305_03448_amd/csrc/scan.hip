@@ -56,7 +56,9 @@ struct ScanCfg {
 };
 constexpr int kMinTile = 8192;   // smallest tile of any configuration below
 
-template <class C, bool kVec>
+// kExcl: exclusive scan (out[i] = sum of the elements before i), the same
+// pass with each group of four shifted by one place after its in-group scan.
+template <class C, bool kVec, bool kExcl>
 __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __restrict__ in,
                                                             int32_t* __restrict__ out, int64_t n,
                                                             WsHeader* __restrict__ hdr,
@@ -143,6 +145,12 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
     const uint32_t t = x[r][3];
     const uint32_t incl = wave::inclusive_add_u32(t);
     const uint32_t ex = carry + incl - t;
+    if constexpr (kExcl) {
+      x[r][3] = x[r][2];
+      x[r][2] = x[r][1];
+      x[r][1] = x[r][0];
+      x[r][0] = 0u;
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[r][k] += ex;
     carry += wave::lane_read_u32(incl, kWave - 1);
@@ -172,19 +180,36 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
   }
 }
 
-template <class C>
+template <class C, bool kExcl>
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
   const int64_t ntiles = (n + C::tile - 1) / C::tile;
   WsHeader* hdr = (WsHeader*)ws;
   uint64_t* status = (uint64_t*)((char*)ws + sizeof(WsHeader));
   const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
   if (vec)
-    hipLaunchKernelGGL((scan_i32_kernel<C, true>), dim3((unsigned)ntiles), dim3(C::block), 0, s,
-                       in, out, n, hdr, status);
+    hipLaunchKernelGGL((scan_i32_kernel<C, true, kExcl>), dim3((unsigned)ntiles), dim3(C::block),
+                       0, s, in, out, n, hdr, status);
   else
-    hipLaunchKernelGGL((scan_i32_kernel<C, false>), dim3((unsigned)ntiles), dim3(C::block), 0, s,
-                       in, out, n, hdr, status);
+    hipLaunchKernelGGL((scan_i32_kernel<C, false, kExcl>), dim3((unsigned)ntiles), dim3(C::block),
+                       0, s, in, out, n, hdr, status);
   return hipGetLastError();
+}
+
+template <bool kExcl>
+hipError_t scan_any(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+  switch (tune::get(tune::kScanI32, tune::size_class(tune::kScanI32, n))) {
+    case 1: return launch_scan<ScanCfg<256, 8, false>, kExcl>(in, out, n, ws, s);
+    case 2: return launch_scan<ScanCfg<512, 8, true>, kExcl>(in, out, n, ws, s);
+    case 3: return launch_scan<ScanCfg<256, 16, true>, kExcl>(in, out, n, ws, s);
+    case 4: return launch_scan<ScanCfg<1024, 4, true>, kExcl>(in, out, n, ws, s);
+    case 5: return launch_scan<ScanCfg<512, 4, true>, kExcl>(in, out, n, ws, s);
+    case 6: return launch_scan<ScanCfg<256, 32, true>, kExcl>(in, out, n, ws, s);
+    case 7: return launch_scan<ScanCfg<512, 16, true>, kExcl>(in, out, n, ws, s);
+    case 8: return launch_scan<ScanCfg<1024, 8, true>, kExcl>(in, out, n, ws, s);
+    case 9: return launch_scan<ScanCfg<512, 32, true>, kExcl>(in, out, n, ws, s);
+    case 10: return launch_scan<ScanCfg<1024, 16, true>, kExcl>(in, out, n, ws, s);
+    default: return launch_scan<ScanCfg<256, 8, true>, kExcl>(in, out, n, ws, s);
+  }
 }
 
 constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
@@ -203,22 +228,11 @@ size_t scan_i32_workspace(int64_t n) {
   return sizeof(WsHeader) + sizeof(uint64_t) * (size_t)(ntiles > 0 ? ntiles : 1);
 }
 
-hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
+                    bool exclusive) {
   if (n == 0) return hipSuccess;
   (void)kRegistered;
-  switch (tune::get(tune::kScanI32, tune::size_class(tune::kScanI32, n))) {
-    case 1: return launch_scan<ScanCfg<256, 8, false>>(in, out, n, ws, s);
-    case 2: return launch_scan<ScanCfg<512, 8, true>>(in, out, n, ws, s);
-    case 3: return launch_scan<ScanCfg<256, 16, true>>(in, out, n, ws, s);
-    case 4: return launch_scan<ScanCfg<1024, 4, true>>(in, out, n, ws, s);
-    case 5: return launch_scan<ScanCfg<512, 4, true>>(in, out, n, ws, s);
-    case 6: return launch_scan<ScanCfg<256, 32, true>>(in, out, n, ws, s);
-    case 7: return launch_scan<ScanCfg<512, 16, true>>(in, out, n, ws, s);
-    case 8: return launch_scan<ScanCfg<1024, 8, true>>(in, out, n, ws, s);
-    case 9: return launch_scan<ScanCfg<512, 32, true>>(in, out, n, ws, s);
-    case 10: return launch_scan<ScanCfg<1024, 16, true>>(in, out, n, ws, s);
-    default: return launch_scan<ScanCfg<256, 8, true>>(in, out, n, ws, s);
-  }
+  return exclusive ? scan_any<true>(in, out, n, ws, s) : scan_any<false>(in, out, n, ws, s);
 }
 
 }  // namespace launch

@@ -85,12 +85,14 @@ def test_reduce_checks(fake_pointers):
     assert st(D(0), 100, D(4096), D(1 << 20), wsb - 1) == WS
 
 
-def test_scan_checks(fake_pointers):
+@pytest.mark.parametrize("entry", ["desc_scan_i32", "desc_scan_exclusive_i32"])
+def test_scan_checks(fake_pointers, entry):
     L = fake_pointers
     n = 10_000
     wsb = L.desc_scan_i32_workspace(n)
     assert wsb >= 64 + 8
-    st = lambda *a: L.desc_scan_i32(*a, None)
+    fn = getattr(L, entry)
+    st = lambda *a: fn(*a, None)
     assert st(D(0), D(1 << 20), 0, D(1 << 24), wsb) == OK           # empty: nothing to do
     assert st(None, D(1 << 20), n, D(1 << 24), wsb) == NULL
     assert st(D(0), D(1 << 20), -5, D(1 << 24), wsb) == SIZE

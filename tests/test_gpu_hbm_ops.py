@@ -236,3 +236,52 @@ def test_copy_every_config(n, restore_configs):
         y = torch.empty(n, dtype=torch.int32, device=dev())
         desc.desc_copy_32(xt, y)
         assert np.array_equal(y.cpu().numpy(), x), name
+
+
+# ------------------------------------------------------------------ exclusive scan
+@pytest.mark.parametrize("n", [0] + EDGE_SIZES)
+def test_scan_exclusive_edge_sizes(n):
+    case(f"exclusive scan n={n}")
+    x = workloads.int_uniform(n, seed=500 + n % 89)
+    y = torch.full((n,), 7, dtype=torch.int32, device=dev())
+    desc.desc_scan_exclusive_i32(to_dev(x), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_exclusive_i32(x))
+
+
+@pytest.mark.parametrize("offset", [1, 3])
+@pytest.mark.parametrize("n", [5, 65537, 300_001])
+def test_scan_exclusive_unaligned(n, offset):
+    case(f"exclusive scan unaligned n={n} offset={offset}")
+    x = workloads.int_uniform(n, seed=9)
+    y = torch.empty(n, dtype=torch.int32, device=dev())
+    desc.desc_scan_exclusive_i32(to_dev(x, offset), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_exclusive_i32(x))
+
+
+@pytest.mark.parametrize("n", [8193, (1 << 22) + 5])
+def test_scan_exclusive_every_config(n, restore_configs):
+    x = workloads.int_uniform(n, seed=600 + n % 7)
+    want = oracle.scan_exclusive_i32(x)
+    xt = to_dev(x)
+    cls = desc.desc_size_class("scan_i32", n)
+    for cfg, name in _each_config("scan_i32"):
+        case(f"exclusive scan config {name} n={n}")
+        desc.desc_config_set("scan_i32", cls, cfg)
+        y = torch.empty(n, dtype=torch.int32, device=dev())
+        desc.desc_scan_exclusive_i32(xt, y)
+        assert np.array_equal(y.cpu().numpy(), want), name
+
+
+def test_scan_exclusive_workload_2_28_shares_workspace():
+    # the benchmark's 2^28 input, alternating with the inclusive scan on one
+    # workspace (the generation tags keep the calls apart)
+    x = workloads.int_uniform(1 << 28, seed=2)
+    xt = to_dev(x)
+    ws = torch.zeros(desc.desc_scan_i32_workspace(1 << 28), dtype=torch.uint8, device=dev())
+    y = torch.empty(1 << 28, dtype=torch.int32, device=dev())
+    case("exclusive scan 2^28")
+    desc.desc_scan_exclusive_i32(xt, y, ws=ws)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_exclusive_i32(x))
+    case("inclusive scan 2^28 after it")
+    desc.desc_scan_i32(xt, y, ws=ws)
+    assert np.array_equal(y.cpu().numpy(), oracle.scan_i32(x))
