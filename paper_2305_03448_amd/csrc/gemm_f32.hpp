@@ -180,5 +180,211 @@ __device__ __forceinline__ void tile(const GemmProblemF32& p, idx_t tm, idx_t tn
   }
 }
 
+// Second form of the tile, for the plain GEMM: kWM x kWN waves, and A kept
+// in LDS as it is in memory, [m][k] with pitch BK + 4, so that it is written
+// with 16-byte stores and read with 16-byte loads.  The reduction index is
+// assigned to the matrix instruction's two k slots by halves of the stage:
+// lanes 0-31 carry k = kk and lanes 32-63 k = BK/2 + kk at step kk, so a
+// lane's A values for a stage are contiguous (the same assignment for A and
+// B keeps the product exact).  B stays [k][n] with pitch BN + 4.
+template <int kBM, int kBN, int kBK, int kWM, int kWN, int kDepth = 1>
+struct GemmCfgF32W {
+  static constexpr int bm = kBM, bn = kBN, bk = kBK, threads = 64 * kWM * kWN, depth = kDepth;
+  static constexpr int wm = kWM, wn = kWN;
+  static constexpr int wtm = kBM / kWM, wtn = kBN / kWN;
+  static constexpr int fm = wtm / 32, fn = wtn / 32;
+  static constexpr int pa = kBK + 4, pb = kBN + 4;        // LDS pitches (words)
+  static constexpr int a_vec = kBM * kBK / 4 / threads;    // float4 per thread per stage
+  static constexpr int b_vec = kBK * kBN / 4 / threads;
+  static constexpr int lds_floats = 2 * kBM * pa + 2 * kBK * pb;
+  static_assert(fm >= 1 && fn >= 1 && a_vec >= 1 && b_vec >= 1, "tile too small");
+  static_assert(a_vec * threads * 4 == kBM * kBK && b_vec * threads * 4 == kBK * kBN,
+                "stage divides evenly among the threads");
+  static_assert(kBK % 8 == 0 && kBN % 4 == 0, "whole 16-byte groups per half stage");
+};
+
+template <class C, bool kVec>
+__device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm, idx_t tn,
+                                              float* lds) {
+  constexpr int BM = C::bm, BN = C::bn, BK = C::bk, T = C::threads, HK = BK / 2;
+  auto thread = thread_x<T>();
+  auto wv = wave_of_block<T>();
+  const int lane = (int)lane_of_wave().index();
+  const int half = lane / 32, col32 = lane % 32;
+  const int wm = (int)wv.index() / C::wn, wn = (int)wv.index() % C::wn;
+  const idx_t m0 = tm * BM, n0 = tn * BN;
+
+  auto a_lds = matrices(lds, 2, BM, C::pa);                          // [buf][m][k]
+  auto b_lds = matrices(lds + 2 * BM * C::pa, 2, BK, C::pb);         // [buf][k][n]
+  auto a_g = matrix(p.A, p.M, p.lda);
+  auto b_g = matrix(p.B, p.K, p.ldb);
+
+  // Register staging sets: stage j travels through set j % depth.
+  struct Regs {
+    f32x4 a[C::a_vec], b[C::b_vec];
+  };
+  Regs R0, R1;
+  // kVec (16-byte aligned rows, K and N multiples of 4): every group of four
+  // is wholly inside or wholly outside the operand, so it is loaded from a
+  // clamped position and zeroed when outside -- no branch per load, which
+  // would keep a second set of registers live.  Otherwise single guarded
+  // loads.
+  auto load = [&](idx_t kt, Regs& R) {
+    const idx_t k0 = kt * BK;
+#pragma unroll
+    for (int i = 0; i < C::a_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      const idx_t r = m0 + q / (BK / 4), c = k0 + 4 * (q % (BK / 4));
+      if constexpr (kVec) {
+        const bool in = r < p.M && c < p.K;
+        const f32x4 v = *(const f32x4*)&a_g.at(r < p.M ? r : p.M - 1, c < p.K ? c : p.K - 4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.a[i][j] = in ? v[j] : 0.f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.a[i][j] = (r < p.M && c + j < p.K) ? a_g.at(r, c + j) : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < C::b_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      const idx_t r = k0 + q / (BN / 4), c = n0 + 4 * (q % (BN / 4));
+      if constexpr (kVec) {
+        const bool in = r < p.K && c < p.N;
+        const f32x4 v = *(const f32x4*)&b_g.at(r < p.K ? r : p.K - 1, c < p.N ? c : p.N - 4);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.b[i][j] = in ? v[j] : 0.f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.b[i][j] = (r < p.K && c + j < p.N) ? b_g.at(r, c + j) : 0.f;
+      }
+    }
+  };
+  auto store = [&](const Regs& R, int buf) {
+    auto as = a_lds.idx(buf);
+    auto bs = b_lds.idx(buf);
+#pragma unroll
+    for (int i = 0; i < C::a_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      *(f32x4*)&as.at(q / (BK / 4), 4 * (q % (BK / 4))) = R.a[i];
+    }
+#pragma unroll
+    for (int i = 0; i < C::b_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      *(f32x4*)&bs.at(q / (BN / 4), 4 * (q % (BN / 4))) = R.b[i];
+    }
+  };
+
+  mfma::f32x16 acc[C::fm][C::fn];
+#pragma unroll
+  for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // matrix ops of the stage in LDS buffer `buf`
+  auto compute = [&](int buf) {
+    auto as = a_lds.idx(buf);
+    auto bs = b_lds.idx(buf);
+#pragma unroll
+    for (int k4 = 0; k4 < HK; k4 += 4) {
+      // this lane's four k values of the step group: k = half * HK + k4 + 0..3
+      f32x4 a[C::fm];
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i)
+        a[i] = *(const f32x4*)&as.at(wm * C::wtm + i * 32 + col32, half * HK + k4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        float b[C::fn];
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j)
+          b[j] = bs.at(half * HK + k4 + kk, wn * C::wtn + j * 32 + col32);
+#pragma unroll
+        for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+          for (int j = 0; j < C::fn; ++j) acc[i][j] = mfma::f32_32x32x2(a[i][kk], b[j], acc[i][j]);
+      }
+    }
+  };
+
+  const idx_t nk = (p.K + BK - 1) / BK;
+  if constexpr (C::depth == 1) {
+    // stage kt+1's loads are issued before stage kt's matrix ops
+    if (nk > 0) {
+      load(0, R0);
+      store(R0, 0);
+    }
+    sync(thread);
+    for (idx_t kt = 0; kt < nk; ++kt) {
+      const int buf = (int)(kt & 1);
+      if (kt + 1 < nk) load(kt + 1, R0);
+      compute(buf);
+      if (kt + 1 < nk) store(R0, buf ^ 1);
+      sync(thread);
+    }
+  } else {
+    // two stages ahead: iteration kt issues stage kt+2's loads, computes
+    // stage kt and writes stage kt+1 (loaded one iteration earlier); pairs
+    // of iterations name their register sets statically
+    if (nk > 0) {
+      load(0, R0);
+      store(R0, 0);
+    }
+    if (nk > 1) load(1, R1);
+    sync(thread);
+    idx_t kt = 0;
+    for (; kt + 3 < nk; kt += 2) {
+      load(kt + 2, R0);
+      compute(0);
+      store(R1, 1);
+      sync(thread);
+      load(kt + 3, R1);
+      compute(1);
+      store(R0, 0);
+      sync(thread);
+    }
+    // at most three stages left, kt even
+    if (kt < nk) {
+      if (kt + 2 < nk) load(kt + 2, R0);
+      compute(0);
+      if (kt + 1 < nk) store(R1, 1);
+      sync(thread);
+    }
+    if (kt + 1 < nk) {
+      compute(1);
+      if (kt + 2 < nk) store(R0, 0);
+      sync(thread);
+    }
+    if (kt + 2 < nk) {
+      compute(0);
+      sync(thread);
+    }
+  }
+
+  auto c_g = matrix(p.C, p.M, p.ldc);
+  if (m0 + BM <= p.M && n0 + BN <= p.N) {
+#pragma unroll
+    for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          c_g.at(m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane),
+                 n0 + wn * C::wtn + j * 32 + col32) = acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+      for (int j = 0; j < C::fn; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+          const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+          if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
+        }
+  }
+}
+
 }  // namespace gemm_f32
 }  // namespace desc

@@ -34,6 +34,7 @@ namespace {
 constexpr int kBlock = 256;
 using BigTile = GemmCfgF32<128, 128, 16>;
 using SmallTile = GemmCfgF32<64, 64, 16>;
+using SmallTileRm = gemm_f32::GemmCfgF32W<64, 64, 16, 2, 2, 2>;   // row-major A, two stages ahead
 
 struct GroupedWs {
   int64_t* total;        // tiles over all problems
@@ -149,13 +150,17 @@ __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_pr
 
 // kBig: whether any problem may use the large tile (the LDS is sized for the
 // largest tile the launch can meet, which bounds how many blocks fit a CU).
-template <bool kBig>
-__global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_problem* probs,
+// kRm: 64 x 64 tiles of the row-major-A tile form.
+template <bool kBig, bool kRm = false>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kRm ? 3 : 1)))
+void grouped_gemm_kernel(const desc_gemm_problem* probs,
                                                               int64_t G, const int64_t* total,
                                                               const int64_t* tile_start,
                                                               const int32_t* order,
                                                               const int32_t* big) {
-  __shared__ float lds[kBig ? gemm_f32::lds_floats<BigTile>() : gemm_f32::lds_floats<SmallTile>()];
+  __shared__ __attribute__((aligned(16))) float
+      lds[kRm ? SmallTileRm::lds_floats
+              : (kBig ? gemm_f32::lds_floats<BigTile>() : gemm_f32::lds_floats<SmallTile>())];
   __shared__ int64_t s_slot;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
@@ -185,7 +190,13 @@ __global__ __launch_bounds__(kBlock) void grouped_gemm_kernel(const desc_gemm_pr
     const GemmProblemF32 q{p.A, p.lda, p.B, p.ldb, p.C, p.ldc, p.M, p.N, p.K};
     const idx_t local = t - ts[slot];
     const bool vec = gemm_f32::vec_ok(p.A, p.lda, p.B, p.ldb);
-    if (kBig && b) {
+    if constexpr (kRm) {
+      const idx_t tn = (p.N + 63) / 64;
+      if (vec && p.K % 4 == 0 && p.N % 4 == 0 && p.K > 0)
+        gemm_f32::tile_rowmajor<SmallTileRm, true>(q, local / tn, local % tn, lds);
+      else
+        gemm_f32::tile_rowmajor<SmallTileRm, false>(q, local / tn, local % tn, lds);
+    } else if (kBig && b) {
       const idx_t tn = (p.N + 127) / 128;
       if (vec) gemm_f32::tile<BigTile, true>(q, local / tn, local % tn, lds);
       else gemm_f32::tile<BigTile, false>(q, local / tn, local % tn, lds);
@@ -211,7 +222,7 @@ GroupedWs carve(void* ws, int64_t G) {
   return r;
 }
 
-template <bool kBig>
+template <bool kBig, bool kRm>
 int persistent_grid() {
   static int cached[64] = {0};
   int dev = 0;
@@ -220,17 +231,14 @@ int persistent_grid() {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, grouped_gemm_kernel<kBig>, kBlock,
-                                                     0) != hipSuccess || per < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, grouped_gemm_kernel<kBig, kRm>,
+                                                     kBlock, 0) != hipSuccess || per < 1)
       per = 1;
     cached[dev] = cus * per;
   }
   return cached[dev];
 }
 
-// Tile choice: 128 x 128 tiles for problems with M, N >= 256 and 64 x 64
-// otherwise, or 64 x 64 tiles throughout (more, smaller tiles balance better
-// over the CUs when the problems are small).
 // --------------------------------------------------------------------------
 // Split-BF16 (three products) mode.  Every problem's operands are split into
 // bf16 planes in the workspace, Ah, Al as [Ma][Kp] and Bh^T, Bl^T as
@@ -616,11 +624,15 @@ hipError_t launch_bf16x3(const desc_gemm_problem* problems, int64_t G, const Bf1
   return hipGetLastError();
 }
 
-constexpr const char* kNames[] = {"tile128_or_64", "tile64"};
+// FP32 tile choice: 128 x 128 tiles for problems with M, N >= 256 and 64 x 64
+// otherwise, or 64 x 64 tiles throughout (more, smaller tiles balance better
+// over the CUs when the problems are small), in the first or the row-major-A
+// tile form.
+constexpr const char* kNames[] = {"tile128_or_64", "tile64", "tile64_rm_d2"};
 constexpr int kDefaults[tune::kClasses] = {1, 1, 1, 1};
-constexpr int64_t kBigMin[] = {256, INT64_MAX};
+constexpr int64_t kBigMin[] = {256, INT64_MAX, INT64_MAX};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 2, kNames, kDefaults), true);
+    (tune::register_op(tune::kGemmGrouped, "gemm_grouped", 3, kNames, kDefaults), true);
 
 constexpr const char* kNamesBf16[] = {"tile64", "tile128", "fused64", "fused128"};
 constexpr int kDefaultsBf16[tune::kClasses] = {3, 3, 3, 3};
@@ -674,13 +686,20 @@ hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* 
   // the size class is taken from the problem count
   const int cfg = tune::get(tune::kGemmGrouped, tune::size_class(tune::kGemmGrouped, G));
   hipLaunchKernelGGL(grouped_plan_kernel, dim3(1), dim3(kBlock), 0, s, problems, G,
-                     kBigMin[cfg == 1 ? 1 : 0], w.total, w.tile_start, w.order, w.big);
-  if (cfg == 1)
-    hipLaunchKernelGGL(grouped_gemm_kernel<false>, dim3((unsigned)persistent_grid<false>()),
-                       dim3(kBlock), 0, s, problems, G, w.total, w.tile_start, w.order, w.big);
+                     kBigMin[cfg >= 0 && cfg < 3 ? cfg : 1], w.total, w.tile_start, w.order,
+                     w.big);
+  if (cfg == 2)
+    hipLaunchKernelGGL((grouped_gemm_kernel<false, true>),
+                       dim3((unsigned)persistent_grid<false, true>()), dim3(kBlock), 0, s,
+                       problems, G, w.total, w.tile_start, w.order, w.big);
+  else if (cfg == 1)
+    hipLaunchKernelGGL((grouped_gemm_kernel<false, false>),
+                       dim3((unsigned)persistent_grid<false, false>()), dim3(kBlock), 0, s,
+                       problems, G, w.total, w.tile_start, w.order, w.big);
   else
-    hipLaunchKernelGGL(grouped_gemm_kernel<true>, dim3((unsigned)persistent_grid<true>()),
-                       dim3(kBlock), 0, s, problems, G, w.total, w.tile_start, w.order, w.big);
+    hipLaunchKernelGGL((grouped_gemm_kernel<true, false>),
+                       dim3((unsigned)persistent_grid<true, false>()), dim3(kBlock), 0, s,
+                       problems, G, w.total, w.tile_start, w.order, w.big);
   return hipGetLastError();
 }
 

@@ -138,16 +138,18 @@ def test_gemm_strided_rows(mode):
     _check_sampled(A, B, C, TOL[mode], samples=77 * 53)
 
 
-def test_gemm_f32_every_config():
-    M, N, K = 300, 200, 136
+@pytest.mark.parametrize("M,N,K,pad", [(300, 200, 136, 0), (77, 53, 45, 3), (260, 516, 68, 0)])
+def test_gemm_f32_every_config(M, N, K, pad):
+    # aligned groups of four with ragged tiles, then single loads (odd K, N,
+    # unaligned rows)
     A = _int_matrix(M, K, 11); B = _int_matrix(K, N, 12)
     exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
     cls = desc.desc_size_class("gemm_f32", M * N * K)
     try:
         for cfg in range(desc.desc_config_count("gemm_f32")):
-            case(f"gemm f32 config {desc.desc_config_name('gemm_f32', cfg)}")
+            case(f"gemm f32 config {desc.desc_config_name('gemm_f32', cfg)} {M}x{N}x{K}")
             desc.desc_config_set("gemm_f32", cls, cfg)
-            assert np.array_equal(_run(A, B, "f32"), exact)
+            assert np.array_equal(_run(A, B, "f32", lda_pad=pad, ldc_pad=pad), exact)
     finally:
         desc.desc_config_set("gemm_f32", cls, -1)
 

@@ -61,7 +61,7 @@ def grouped_config(request):
         desc.desc_config_set("gemm_grouped", cls, -1)
 
 
-CONFIGS = [0, 1]   # tile128_or_64, tile64
+CONFIGS = [0, 1, 2]   # tile128_or_64, tile64, tile64_rm_d2
 BF16_CONFIGS = [0, 1, 2, 3]   # tile64, tile128, fused64, fused128
 
 
