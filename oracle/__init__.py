@@ -51,6 +51,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_scan_i32.restype = ctypes.c_int
         L.oracle_scan_exclusive_i32.argtypes = [P, P, I64]
         L.oracle_transpose_u32.argtypes = [P, P, I64, I64]
+        L.oracle_transpose_bytes.argtypes = [P, P, I64, I64, I64]
         L.oracle_gemm_ref_sampled.argtypes = [P, I64, P, I64, I64, P, P, I64, P, P]
         L.oracle_bf16_rne.argtypes = [F]
         L.oracle_bf16_rne.restype = ctypes.c_uint16
@@ -112,6 +113,16 @@ def transpose_u32(m) -> np.ndarray:
     rows, cols = m.shape
     out = np.empty((cols, rows), dtype=m.dtype)
     lib().oracle_transpose_u32(_p(m), _p(out), rows, cols)
+    return out
+
+
+def transpose_bytes(m) -> np.ndarray:
+    """Transpose of a 2-D array of 1-, 2-, 4- or 8-byte elements (bits kept)."""
+    m = np.ascontiguousarray(m)
+    assert m.ndim == 2 and m.dtype.itemsize in (1, 2, 4, 8)
+    rows, cols = m.shape
+    out = np.empty((cols, rows), dtype=m.dtype)
+    lib().oracle_transpose_bytes(_p(m), _p(out), rows, cols, m.dtype.itemsize)
     return out
 
 

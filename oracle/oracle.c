@@ -92,6 +92,18 @@ void oracle_transpose_u32(const uint32_t *in, uint32_t *out, int64_t rows, int64
 }
 
 /* ------------------------------------------------------------------ */
+/* The same transposition for elements of `elem` bytes (1, 2, 4 or 8):  */
+/* element (r, c) of `in` is copied to element (c, r) of `out`.         */
+/* ------------------------------------------------------------------ */
+void oracle_transpose_bytes(const uint8_t *in, uint8_t *out, int64_t rows, int64_t cols,
+                            int64_t elem)
+{
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t c = 0; c < cols; ++c)
+            memcpy(&out[(c * rows + r) * elem], &in[(r * cols + c) * elem], (size_t)elem);
+}
+
+/* ------------------------------------------------------------------ */
 /* GEMM reference on sampled entries.                                   */
 /* A is M x K (row stride lda), B is K x N (row stride ldb), row-major. */
 /* For each sample s: R[s] = sum_k a[i][k]*b[k][j] in FP64 (every FP32  */
