@@ -256,6 +256,24 @@ def cpu_baseline(x_np, m_np, budget_s: float = 20.0):
 
 
 # ------------------------------------------------------------------ per-op measurements
+def op_transpose_elems(desc, torch):
+    """Transposes of 1-, 2- and 8-byte elements, 256 MiB in and 256 MiB out
+    each (the paper's 512 MB size): graph-replay time and algorithmic GB/s."""
+    out = {}
+    for name, dtype, rows, cols in (("u8", torch.uint8, 16384, 16384),
+                                    ("u16", torch.int16, 16384, 8192),
+                                    ("f64", torch.float64, 8192, 4096)):
+        x = torch.zeros((rows, cols), dtype=dtype, device="cuda")
+        y = torch.empty((cols, rows), dtype=dtype, device="cuda")
+        ms = graph_time_ms(torch, lambda: desc.desc_transpose_batched(x, y), reps=10)
+        nbytes = 2 * x.numel() * x.element_size()
+        out[name] = {"shape": [rows, cols], "us": round(ms * 1e3, 1),
+                     "GBs": round(nbytes / ms / 1e6, 1), "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def op_copy(desc, torch):
     n = 1 << 28
     x = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -402,7 +420,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views,variants",
+    ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views,variants,"
+                                     "transpose_elems",
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -506,6 +525,9 @@ def main(argv=None):
     if "views" in extra:
         log("view kernels against hand-indexed twins")
         result["ops"]["views_vs_hand"] = op_views(desc, torch, workloads)
+    if "transpose_elems" in extra:
+        log("transposes of 1-, 2- and 8-byte elements")
+        result["ops"]["transpose_elems_512MB"] = op_transpose_elems(desc, torch)
     if "copy" in extra:
         log("copy ceiling")
         result["ops"]["copy_2^28"] = op_copy(desc, torch)

@@ -131,6 +131,13 @@ desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_
 desc_status desc_transpose_batched_f32(const float* in, float* out, int64_t batch,
                                        int64_t rows, int64_t cols, void* stream);
 
+/* The same transposition for elements of elem_bytes = 1, 2, 4 or 8 bytes
+ * (8: the doubles of the paper's own example), moved as bit patterns;
+ * pointers aligned to the element size.  Other sizes return
+ * DESC_ERR_UNSUPPORTED; elem_bytes = 4 is desc_transpose_batched_f32. */
+desc_status desc_transpose_batched(const void* in, void* out, int64_t elem_bytes, int64_t batch,
+                                   int64_t rows, int64_t cols, void* stream);
+
 /* ------------------------------------------------------------------------
  * Matrix multiplication (Sec. 5, "matrix multiplication"; the paper fixes
  * neither precision nor layout): C = A * B with A M x K, B K x N and C

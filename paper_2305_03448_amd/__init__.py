@@ -27,7 +27,7 @@ __all__ = [
     "desc_reduce_i32_workspace", "desc_reduce_i32",
     "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
-    "desc_transpose_f32", "desc_transpose_batched_f32", "desc_copy_32",
+    "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
     "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
     "desc_gemm_workspace", "desc_gemm", "GEMM_MODES",
@@ -60,6 +60,7 @@ SIGNATURES = {
     "desc_scan_two_pass_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_transpose_f32": (_ST, [_P, _P, _I64, _I64, _P]),
     "desc_transpose_batched_f32": (_ST, [_P, _P, _I64, _I64, _I64, _P]),
+    "desc_transpose_batched": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _P]),
     "desc_copy_32": (_ST, [_P, _P, _I64, _P]),
     "desc_config_count": (ctypes.c_int, [ctypes.c_int]),
     "desc_config_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
@@ -285,6 +286,21 @@ def desc_transpose_batched_f32(x: torch.Tensor, out: torch.Tensor, stream=None) 
     _check(lib().desc_transpose_batched_f32(_ptr(x), _ptr(o), x.shape[0], x.shape[1],
                                             x.shape[2], _stream(x, stream)),
            "desc_transpose_batched_f32")
+    return out
+
+
+def desc_transpose_batched(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[b] = transpose of x[b] for a (rows, cols) or (batch, rows, cols) ``x`` of 1-, 2-,
+    4- or 8-byte elements (bit patterns moved; any dtype of that size)."""
+    if x.device.type != "cuda" or out.device.type != "cuda":
+        raise ValueError("x and out must be in GPU memory")
+    if not (x.is_contiguous() and out.is_contiguous()) or x.element_size() != out.element_size():
+        raise ValueError("x and out must be contiguous with the same element size")
+    xs = x.shape if x.dim() == 3 else (1,) + tuple(x.shape)
+    if x.dim() not in (2, 3) or tuple(out.shape) != tuple(x.shape[:-2]) + (x.shape[-1], x.shape[-2]):
+        raise ValueError("x must be (rows, cols) or (batch, rows, cols), out the transposes")
+    _check(lib().desc_transpose_batched(_ptr(x), _ptr(out), x.element_size(), xs[0], xs[1], xs[2],
+                                        _stream(x, stream)), "desc_transpose_batched")
     return out
 
 

@@ -218,6 +218,30 @@ desc_status desc_transpose_f32(const float* in, float* out, int64_t rows, int64_
   return desc_transpose_batched_f32(in, out, 1, rows, cols, stream);
 }
 
+desc_status desc_transpose_batched(const void* in, void* out, int64_t elem_bytes, int64_t batch,
+                                   int64_t rows, int64_t cols, void* stream) {
+  if (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8)
+    return DESC_ERR_UNSUPPORTED;
+  if (elem_bytes == 4)
+    return desc_transpose_batched_f32((const float*)in, (float*)out, batch, rows, cols, stream);
+  if (batch < 0 || rows < 0 || cols < 0) return DESC_ERR_SIZE;
+  const int64_t per = bytes_of(rows, cols);
+  const int64_t cnt = per < 0 ? -1 : bytes_of(per, batch);
+  const int64_t nb = cnt < 0 ? -1 : bytes_of(cnt, elem_bytes);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (nb > 0 && (in == nullptr || out == nullptr)) return DESC_ERR_NULL;
+  if (nb == 0) return DESC_OK;
+  if (rows > desc::launch::transpose_elem_max_rows(elem_bytes) || batch > 65535 ||
+      cols > INT32_MAX)
+    return DESC_ERR_UNSUPPORTED;
+  DESC_TRY(check_device({in, out}));
+  if (misaligned(in, (size_t)elem_bytes) || misaligned(out, (size_t)elem_bytes))
+    return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb})) return DESC_ERR_ALIAS;
+  return hip_status(
+      desc::launch::transpose_elem(in, out, elem_bytes, batch, rows, cols, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- GEMM
 size_t desc_gemm_workspace(desc_gemm_mode mode, int64_t M, int64_t N, int64_t K) {
   if (M < 0 || N < 0 || K < 0) return 0;

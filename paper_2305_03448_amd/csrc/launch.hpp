@@ -25,6 +25,9 @@ hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStr
 int64_t transpose_max_rows();
 hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_t rows,
                         int64_t cols, hipStream_t s);
+int64_t transpose_elem_max_rows(int64_t elem_bytes);
+hipError_t transpose_elem(const void* in, void* out, int64_t elem_bytes, int64_t batch,
+                          int64_t rows, int64_t cols, hipStream_t s);
 
 // gemm_f32.hip
 hipError_t gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,

@@ -31,28 +31,29 @@ DESC_HD auto block_striped(const V& elems, idx_t tile, const T& thread) {
       thread);
 }
 
-// Tiled transposition.  `m` is a [rows][cols / 4] view of int32x4 groups;
-// tile (by, bx) is T x T words, read by a [T / kItems][T / 4] block of
-// threads, thread (y, x) taking rows y, y + T/kItems, ... of the tile
-// (group_by_tile, then group_by_row).
-template <int T, int kItems, class V, class BY, class BX, class TY, class TX>
+// Tiled transposition.  `m` is a [rows][cols / kV] view of 16-byte groups of
+// kV elements (kV = 4 for 32-bit words); tile (by, bx) is T x T elements,
+// read by a [T / kItems][T / kV] block of threads, thread (y, x) taking rows
+// y, y + T/kItems, ... of the tile (group_by_tile, then group_by_row).
+template <int T, int kItems, int kV = 4, class V, class BY, class BX, class TY, class TX>
 DESC_HD auto tile_rows(const V& m, const BY& by, const BX& bx, const TY& ty, const TX& tx) {
-  return group_by_row<T, kItems>(group_by_tile<T, T / 4>(m).select(by).select(bx)).select(ty).select(
-      tx);
+  return group_by_row<T, kItems>(group_by_tile<T, T / kV>(m).select(by).select(bx))
+      .select(ty)
+      .select(tx);
 }
 
-// The same thread's slots of the T x T LDS tile ([T][T] words): [kItems][4],
-// row y + (T/kItems) i, words 4x..4x+3.
-template <int T, int kItems, class V, class TY, class TX>
+// The same thread's slots of the T x T LDS tile ([T][T] elements):
+// [kItems][kV], row y + (T/kItems) i, elements kV x .. kV x + kV - 1.
+template <int T, int kItems, int kV = 4, class V, class TY, class TX>
 DESC_HD auto lds_rows(const V& tile, const TY& ty, const TX& tx) {
-  return group_by_row<T, kItems>(tile.template group<4, 1>()).select(ty).select(tx);
+  return group_by_row<T, kItems>(tile.template group<kV, 1>()).select(ty).select(tx);
 }
 
-// The LDS tile read column-wise for the write-out: [kItems][4], element
-// (i, k) = tile[4x + k][y + (T/kItems) i].
-template <int T, int kItems, class V, class TY, class TX>
+// The LDS tile read column-wise for the write-out: [kItems][kV], element
+// (i, k) = tile[kV x + k][y + (T/kItems) i].
+template <int T, int kItems, int kV = 4, class V, class TY, class TX>
 DESC_HD auto lds_cols(const V& tile, const TY& ty, const TX& tx) {
-  return group_by_row<T, kItems>(tile.transpose().template group<4, 1>()).select(ty).select(tx);
+  return group_by_row<T, kItems>(tile.transpose().template group<kV, 1>()).select(ty).select(tx);
 }
 
 }  // namespace layout

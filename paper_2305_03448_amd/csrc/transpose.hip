@@ -130,6 +130,96 @@ hipError_t launch_transpose(const uint32_t* in, uint32_t* out, int64_t batch, in
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------------- other element sizes
+// The same kernel for elements of 1, 2 or 8 bytes (the paper's own example
+// moves doubles): a 16-byte group holds kV = 16 / sizeof(E) elements, a tile
+// is T x T elements read by a [256 / (T/kV)][T/kV] block, and the LDS pitch
+// is padded by 4 bytes (8 for doubles) so that a column read walks the banks.
+template <class E, int kT>
+struct TransposeCfgE {
+  static constexpr int v = 16 / (int)sizeof(E);            // elements per 16-byte group
+  static constexpr int t = kT;
+  static constexpr int pad = sizeof(E) >= 4 ? 1 : 4 / (int)sizeof(E);
+  static constexpr int pitch = kT + pad;
+  static constexpr int tx = kT / v;
+  static constexpr int ty = kBlock / tx;
+  static constexpr int items = kT / ty;
+  static_assert(tx * ty == kBlock && ty * items == kT, "tile rows must divide among the threads");
+};
+
+template <class C, class E, bool kVec>
+__global__ __launch_bounds__(kBlock) void transpose_elem_kernel(const E* __restrict__ in,
+                                                                E* __restrict__ out, int64_t rows,
+                                                                int64_t cols) {
+  constexpr int T = C::t, TY = C::ty, TX = C::tx, IT = C::items, V = C::v;
+  typedef E vec_t __attribute__((ext_vector_type(V)));
+  __shared__ __attribute__((aligned(16))) E lds[T * C::pitch];
+  auto bx = block_x();
+  auto by = block_y();
+  auto thread = thread_x<kBlock>();
+  const Block bz{(idx_t)blockIdx.z, (idx_t)gridDim.z};
+  auto tile = matrix(lds, T, C::pitch).template fst<1>(T);            // [T][T]
+
+  const bool full = kVec && (by.index() + 1) * T <= rows && (bx.index() + 1) * T <= cols;
+  if (full) {
+    auto t2 = thread_yx<TY, TX>();
+    auto a_mine = layout::tile_rows<T, IT, V>(
+        matrices((const vec_t*)in, bz.count(), rows, cols / V).select(bz), by, bx, t2.y, t2.x);
+    auto l_mine = layout::lds_rows<T, IT, V>(tile, t2.y, t2.x);                        // [IT][V]
+    vec_t g[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) g[i] = __builtin_nontemporal_load(&a_mine[i]);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      auto l = l_mine.idx(i);
+#pragma unroll
+      for (int k = 0; k < V; ++k) l[k] = g[i][k];
+    }
+    sync(thread);
+    auto b_mine = layout::tile_rows<T, IT, V>(
+        matrices((vec_t*)out, bz.count(), cols, rows / V).select(bz), bx, by, t2.y, t2.x);
+    auto lt = layout::lds_cols<T, IT, V>(tile, t2.y, t2.x);
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      auto l = lt.idx(i);
+      vec_t w;
+#pragma unroll
+      for (int k = 0; k < V; ++k) w[k] = l[k];
+      __builtin_nontemporal_store(w, &b_mine[i]);
+    }
+  } else {
+    auto a = matrices(in, bz.count(), rows, cols).select(bz);
+    auto b = matrices(out, bz.count(), cols, rows).select(bz);
+    const idx_t r0 = by.index() * T, c0 = bx.index() * T;
+    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+      const idx_t r = e / T, c = e % T;
+      if (r0 + r < rows && c0 + c < cols) tile.at(r, c) = a.at(r0 + r, c0 + c);
+    }
+    sync(thread);
+    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+      const idx_t c = e / T, r = e % T;
+      if (r0 + r < rows && c0 + c < cols) b.at(c0 + c, r0 + r) = tile.at(r, c);
+    }
+  }
+}
+
+template <class E, int kT>
+hipError_t launch_transpose_elem(const void* in, void* out, int64_t batch, int64_t rows,
+                                 int64_t cols, hipStream_t s) {
+  using C = TransposeCfgE<E, kT>;
+  const dim3 grid((unsigned)((cols + kT - 1) / kT), (unsigned)((rows + kT - 1) / kT),
+                  (unsigned)batch);
+  const bool vec = rows % C::v == 0 && cols % C::v == 0 &&
+                   (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL((transpose_elem_kernel<C, E, true>), grid, dim3(kBlock), 0, s,
+                       (const E*)in, (E*)out, rows, cols);
+  else
+    hipLaunchKernelGGL((transpose_elem_kernel<C, E, false>), grid, dim3(kBlock), 0, s,
+                       (const E*)in, (E*)out, rows, cols);
+  return hipGetLastError();
+}
+
 constexpr const char* kNames[] = {"t64_nt", "t64", "t32_nt", "t32", "t128_nt", "t128"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
@@ -155,6 +245,24 @@ hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_
     case 4: return launch_transpose<TransposeCfg<128, true>>(in, out, batch, rows, cols, s);
     case 5: return launch_transpose<TransposeCfg<128, false>>(in, out, batch, rows, cols, s);
     default: return launch_transpose<TransposeCfg<64, true>>(in, out, batch, rows, cols, s);
+  }
+}
+
+// Tiles of 128 elements for 1- and 2-byte elements, 64 for doubles (eight
+// 16-byte groups per thread either way).
+int64_t transpose_elem_max_rows(int64_t elem_bytes) {
+  return (int64_t)65535 * (elem_bytes == 8 ? 64 : 128);
+}
+
+hipError_t transpose_elem(const void* in, void* out, int64_t elem_bytes, int64_t batch,
+                          int64_t rows, int64_t cols, hipStream_t s) {
+  if (batch == 0 || rows == 0 || cols == 0) return hipSuccess;
+  switch (elem_bytes) {
+    case 1: return launch_transpose_elem<uint8_t, 128>(in, out, batch, rows, cols, s);
+    case 2: return launch_transpose_elem<uint16_t, 128>(in, out, batch, rows, cols, s);
+    case 4:
+      return transpose_32((const uint32_t*)in, (uint32_t*)out, batch, rows, cols, s);
+    default: return launch_transpose_elem<uint64_t, 64>(in, out, batch, rows, cols, s);
   }
 }
 

@@ -154,6 +154,26 @@ def test_transpose_checks(fake_pointers):
     assert L.desc_transpose_f32(D(0), HOSTP, 3, 3, None) == HOST
 
 
+def test_transpose_any_element_size_checks(fake_pointers):
+    L = fake_pointers
+    st = lambda *a: L.desc_transpose_batched(*a, None)
+    for es in (3, 0, 16, -8):
+        assert st(D(0), D(1 << 24), es, 1, 5, 5) == UNSUP
+    for es in (1, 2, 8):
+        assert st(D(0), D(1 << 24), es, 1, 0, 5) == OK                 # nothing to move
+        assert st(None, D(1 << 24), es, 1, 5, 5) == NULL
+        assert st(D(0), D(1 << 24), es, 1, -1, 5) == SIZE
+        assert st(D(0), D(1 << 24), es, 1, 1 << 40, 1 << 40) == SIZE
+        assert st(D(0), HOSTP, es, 1, 5, 5) == HOST
+        assert st(D(0), D(1 << 24), es, 70000, 5, 5) == UNSUP          # batch beyond grid z
+        # 25 elements from 0 end at byte 25 es; out starting inside overlaps
+        assert st(D(0), D(24 * es), es, 1, 5, 5) == ALIAS
+    assert st(D(1), D(1 << 24), 2, 1, 5, 5) == ALIGN
+    assert st(D(4), D(1 << 24), 8, 1, 5, 5) == ALIGN
+    assert st(D(0), D(1 << 24), 8, 1, 64 * 65535 + 1, 5) == UNSUP      # rows beyond the grid
+    assert st(D(0), D(2), 4, 1, 5, 5) == ALIGN                          # the 32-bit path
+
+
 def _problems_host(shapes):
     """A host desc_gemm_problem array (nine int64 words each) with the given
     M, N, K and placeholder strides and pointers."""

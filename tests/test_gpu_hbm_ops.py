@@ -285,3 +285,58 @@ def test_scan_exclusive_workload_2_28_shares_workspace():
     case("inclusive scan 2^28 after it")
     desc.desc_scan_i32(xt, y, ws=ws)
     assert np.array_equal(y.cpu().numpy(), oracle.scan_i32(x))
+
+
+# ------------------------------------------------------------------ 1-, 2-, 8-byte transpose
+ELEM_DTYPES = [(1, torch.uint8, np.uint8), (2, torch.int16, np.uint16), (8, torch.float64, np.uint64)]
+
+
+def _bits(shape, dtype_np, seed):
+    g = workloads.rng(seed)
+    return g.integers(0, np.iinfo(dtype_np).max, size=shape, dtype=dtype_np, endpoint=True)
+
+
+@pytest.mark.parametrize("es,tdt,ndt", ELEM_DTYPES)
+@pytest.mark.parametrize("rows,cols", [(1, 1), (37, 1), (1, 45), (64, 64), (128, 128), (129, 130),
+                                       (200, 136), (256, 512), (1000, 17), (513, 1024)])
+def test_transpose_elem_sizes(es, tdt, ndt, rows, cols):
+    case(f"transpose {es}-byte {rows}x{cols}")
+    m = _bits((rows, cols), ndt, seed=700 + rows % 13 + cols % 7)
+    x = torch.from_numpy(m).view(tdt).to(dev())
+    y = torch.empty((cols, rows), dtype=tdt, device=dev())
+    desc.desc_transpose_batched(x, y)
+    got = y.cpu().view(torch.uint8).numpy().view(ndt)
+    assert np.array_equal(got, oracle.transpose_bytes(m))
+
+
+@pytest.mark.parametrize("es,tdt,ndt", ELEM_DTYPES)
+def test_transpose_elem_batched_unaligned(es, tdt, ndt):
+    # a batch of 3, then a start one element past a 16-byte boundary
+    m = _bits((3, 70, 250), ndt, seed=710)
+    x = torch.from_numpy(m).view(tdt).to(dev())
+    y = torch.empty((3, 250, 70), dtype=tdt, device=dev())
+    case(f"transpose {es}-byte batch 3")
+    desc.desc_transpose_batched(x, y)
+    got = y.cpu().view(torch.uint8).numpy().view(ndt)
+    for b in range(3):
+        assert np.array_equal(got[b], oracle.transpose_bytes(m[b]))
+    buf = torch.empty(64 * 96 + 1, dtype=tdt, device=dev())
+    xs = buf[1:].view(64, 96)
+    m2 = _bits((64, 96), ndt, seed=711)
+    xs.copy_(torch.from_numpy(m2).view(tdt).to(dev()))
+    y2 = torch.empty((96, 64), dtype=tdt, device=dev())
+    case(f"transpose {es}-byte unaligned start")
+    desc.desc_transpose_batched(xs, y2)
+    assert np.array_equal(y2.cpu().view(torch.uint8).numpy().view(ndt), oracle.transpose_bytes(m2))
+
+
+def test_transpose_f64_bit_patterns():
+    # the paper's example type: NaN payloads, -0.0, subnormals, infinities
+    pats = np.array([0x7FF8000000000001, 0xFFF0DEADBEEF0001, 0x8000000000000000,
+                     0x0000000000000001, 0x7FF0000000000000, 0x3FF0000000000000], dtype=np.uint64)
+    m = np.tile(pats, (128, 22))[:, :128]                               # 128 x 128, full tiles
+    x = torch.from_numpy(m).view(torch.float64).to(dev())
+    y = torch.empty((128, 128), dtype=torch.float64, device=dev())
+    case("transpose f64 bit patterns")
+    desc.desc_transpose_batched(x, y)
+    assert np.array_equal(y.cpu().view(torch.uint8).numpy().view(np.uint64), m.T)
