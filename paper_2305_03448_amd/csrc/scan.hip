@@ -56,32 +56,16 @@ struct ScanCfg {
 };
 constexpr int kMinTile = 8192;   // smallest tile of any configuration below
 
-// kExcl: exclusive scan (out[i] = sum of the elements before i), the same
-// pass with each group of four shifted by one place after its in-group scan.
-template <class C, bool kVec, bool kExcl>
-__global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __restrict__ in,
-                                                            int32_t* __restrict__ out, int64_t n,
-                                                            WsHeader* __restrict__ hdr,
-                                                            uint64_t* __restrict__ status) {
+// A tile's values: [tiles][waves][rounds][lanes] of 4-element groups; the
+// last tile may be partial, so the nominal extent is rounded up and
+// positions >= n read as zero.
+template <class C, bool kVec>
+__device__ __forceinline__ void load_tile(const int32_t* __restrict__ in, int64_t n, idx_t tile,
+                                          idx_t ntiles, uint32_t (&x)[C::rounds][4]) {
   constexpr int R = C::rounds, NW = C::waves, TILE = C::tile;
-  __shared__ uint32_t s_gen, s_prefix;
-  __shared__ uint32_t s_wtot[NW];
-  auto tile_res = block_x();
-  auto thread = thread_x<C::block>();
   auto wv = wave_of_block<C::block>();
   auto lane = lane_of_wave();
-  const idx_t ntiles = tile_res.count();
-  const idx_t tile = tile_res.index();
-
-  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
-  sync(thread);
-  const uint32_t gen = s_gen;
-
-  // [tiles][waves][rounds][lanes] of 4-element groups; the last tile may be
-  // partial, so the nominal extent is rounded up and positions >= n guarded.
-  const bool full = kVec && (tile + 1) * TILE <= n;
-  uint32_t x[R][4];
-  if (full) {
+  if (kVec && (tile + 1) * TILE <= n) {
     auto mine = layout::wave_striped<NW, R>(array((const i32x4*)in, ntiles * (TILE / 4)), tile,
                                             wv, lane);                   // [rounds]
 #pragma unroll
@@ -100,18 +84,40 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
       for (int k = 0; k < 4; ++k) x[r][k] = grp.pos(k) < n ? (uint32_t)grp[k] : 0u;
     }
   }
+}
+
+// The scan of one loaded tile, from its aggregate to its stores.  kExcl:
+// exclusive scan (out[i] = sum of the elements before i), the same pass
+// with each group of four shifted by one place after its in-group scan.
+// The LDS words are reused by the block's next tile: every read of them
+// comes before the second barrier here.
+constexpr int kWaveMax = 1024 / kWave;   // waves of the largest block
+struct alignas(16) ScanLds {
+  uint32_t wtot[kWaveMax];   // first: 16-byte aligned, read as 16-byte words
+  uint32_t prefix;
+};
+template <class C, bool kVec, bool kExcl>
+__device__ __forceinline__ void scan_tile(int32_t* __restrict__ out, int64_t n, idx_t tile,
+                                          idx_t ntiles, uint32_t gen, WsHeader* __restrict__ hdr,
+                                          uint64_t* __restrict__ status,
+                                          uint32_t (&x)[C::rounds][4], ScanLds& sl) {
+  constexpr int R = C::rounds, NW = C::waves, TILE = C::tile;
+  auto thread = thread_x<C::block>();
+  auto wv = wave_of_block<C::block>();
+  auto lane = lane_of_wave();
+  const bool full = kVec && (tile + 1) * TILE <= n;
 
   // Tile aggregate first, so that it can be published before the scan.
   uint32_t lsum = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) lsum += x[r][0] + x[r][1] + x[r][2] + x[r][3];
   const uint32_t wsum = wave::sum_u32(lsum);
-  if (lane.index() == 0) s_wtot[wv.index()] = wsum;
+  if (lane.index() == 0) sl.wtot[wv.index()] = wsum;
   sync(thread);
   uint32_t wex = 0, agg = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    const uint32_t v = s_wtot[w];
+    const uint32_t v = sl.wtot[w];
     wex += (w < wv.index()) ? v : 0u;
     agg += v;
   }
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
       if (lane.index() == 0) store_status(&st[tile], pack(kFlagPrefix, gen, excl + agg));
     }
     if (lane.index() == 0) {
-      s_prefix = excl;
+      sl.prefix = excl;
       // Every tile before the last has published, so every block of this
       // call has read the generation: the last tile may advance it.
       if (tile == ntiles - 1) store_u32(&hdr->gen, gen + 1u);
@@ -156,7 +162,7 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
     carry += wave::lane_read_u32(incl, kWave - 1);
   }
   sync(thread);
-  const uint32_t add = s_prefix + wex;
+  const uint32_t add = sl.prefix + wex;
 
   if (full) {
     auto mine = layout::wave_striped<NW, R>(array((i32x4*)out, ntiles * (TILE / 4)), tile, wv,
@@ -180,6 +186,57 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
   }
 }
 
+// One block per tile.
+template <class C, bool kVec, bool kExcl>
+__global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __restrict__ in,
+                                                            int32_t* __restrict__ out, int64_t n,
+                                                            WsHeader* __restrict__ hdr,
+                                                            uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_gen;
+  __shared__ ScanLds sl;
+  auto tile_res = block_x();
+  auto thread = thread_x<C::block>();
+  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
+  sync(thread);
+  const uint32_t gen = s_gen;
+  uint32_t x[C::rounds][4];
+  load_tile<C, kVec>(in, n, tile_res.index(), tile_res.count(), x);
+  scan_tile<C, kVec, kExcl>(out, n, tile_res.index(), tile_res.count(), gen, hdr, status, x, sl);
+}
+
+// Persistent form: as many blocks as fit the device at once, block b taking
+// tiles b, b + G, b + 2G, ... in order, and the loads of its next tile
+// issued before the scan of the current one, into a second register set,
+// so that they travel while the block waits on its look-back and stores.
+// Every block is resident and takes its tiles in increasing order, so the
+// lowest unfinished tile can always finish: no block waits on one that has
+// not started.
+template <class C, bool kVec, bool kExcl>
+__global__ __launch_bounds__(C::block) void scan_i32_persist_kernel(
+    const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n, idx_t ntiles,
+    WsHeader* __restrict__ hdr, uint64_t* __restrict__ status) {
+  __shared__ uint32_t s_gen;
+  __shared__ ScanLds sl;
+  auto block = block_x();
+  auto thread = thread_x<C::block>();
+  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
+  sync(thread);
+  const uint32_t gen = s_gen;
+  const idx_t G = block.count();
+  uint32_t x[C::rounds][4], y[C::rounds][4];
+  idx_t t = block.index();
+  if (t < ntiles) load_tile<C, kVec>(in, n, t, ntiles, x);
+  while (t < ntiles) {
+    if (t + G < ntiles) load_tile<C, kVec>(in, n, t + G, ntiles, y);
+    scan_tile<C, kVec, kExcl>(out, n, t, ntiles, gen, hdr, status, x, sl);
+    t += G;
+    if (t >= ntiles) break;
+    if (t + G < ntiles) load_tile<C, kVec>(in, n, t + G, ntiles, x);
+    scan_tile<C, kVec, kExcl>(out, n, t, ntiles, gen, hdr, status, y, sl);
+    t += G;
+  }
+}
+
 template <class C, bool kExcl>
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
   const int64_t ntiles = (n + C::tile - 1) / C::tile;
@@ -192,6 +249,41 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hip
   else
     hipLaunchKernelGGL((scan_i32_kernel<C, false, kExcl>), dim3((unsigned)ntiles), dim3(C::block),
                        0, s, in, out, n, hdr, status);
+  return hipGetLastError();
+}
+
+// The persistent form: a grid of the blocks that fit the device at once
+// (computed once per device and configuration).
+template <class C, bool kExcl>
+hipError_t launch_scan_persist(const int32_t* in, int32_t* out, int64_t n, void* ws,
+                               hipStream_t s) {
+  static int cached[64][2] = {};
+  const int64_t ntiles = (n + C::tile - 1) / C::tile;
+  WsHeader* hdr = (WsHeader*)ws;
+  uint64_t* status = (uint64_t*)((char*)ws + sizeof(WsHeader));
+  const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int& resident = cached[dev][vec ? 1 : 0];
+  if (resident == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const hipError_t e =
+        vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per, scan_i32_persist_kernel<C, true, kExcl>, C::block, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &per, scan_i32_persist_kernel<C, false, kExcl>, C::block, 0);
+    if (e != hipSuccess || per < 1) per = 1;
+    resident = cus * per;
+  }
+  const int64_t grid = ntiles < resident ? ntiles : resident;
+  if (vec)
+    hipLaunchKernelGGL((scan_i32_persist_kernel<C, true, kExcl>), dim3((unsigned)grid),
+                       dim3(C::block), 0, s, in, out, n, (idx_t)ntiles, hdr, status);
+  else
+    hipLaunchKernelGGL((scan_i32_persist_kernel<C, false, kExcl>), dim3((unsigned)grid),
+                       dim3(C::block), 0, s, in, out, n, (idx_t)ntiles, hdr, status);
   return hipGetLastError();
 }
 
@@ -208,16 +300,22 @@ hipError_t scan_any(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStr
     case 8: return launch_scan<ScanCfg<1024, 8, true>, kExcl>(in, out, n, ws, s);
     case 9: return launch_scan<ScanCfg<512, 32, true>, kExcl>(in, out, n, ws, s);
     case 10: return launch_scan<ScanCfg<1024, 16, true>, kExcl>(in, out, n, ws, s);
+    case 11: return launch_scan_persist<ScanCfg<1024, 8, true>, kExcl>(in, out, n, ws, s);
+    case 12: return launch_scan_persist<ScanCfg<512, 16, true>, kExcl>(in, out, n, ws, s);
+    case 13: return launch_scan_persist<ScanCfg<1024, 4, true>, kExcl>(in, out, n, ws, s);
     default: return launch_scan<ScanCfg<256, 8, true>, kExcl>(in, out, n, ws, s);
   }
 }
 
+// "_persist": the persistent form with the next tile's loads in flight.
 constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
                                    "b1024_r4_nt", "b512_r4_nt", "b256_r32_nt", "b512_r16_nt",
-                                   "b1024_r8_nt", "b512_r32_nt", "b1024_r16_nt"};
+                                   "b1024_r8_nt", "b512_r32_nt", "b1024_r16_nt",
+                                   "b1024_r8_nt_persist", "b512_r16_nt_persist",
+                                   "b1024_r4_nt_persist"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kScanI32, "scan_i32", 11, kNames, kDefaults), true);
+    (tune::register_op(tune::kScanI32, "scan_i32", 14, kNames, kDefaults), true);
 
 }  // namespace
 
