@@ -204,39 +204,6 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
   scan_tile<C, kVec, kExcl>(out, n, tile_res.index(), tile_res.count(), gen, hdr, status, x, sl);
 }
 
-// Persistent form: as many blocks as fit the device at once, block b taking
-// tiles b, b + G, b + 2G, ... in order, and the loads of its next tile
-// issued before the scan of the current one, into a second register set,
-// so that they travel while the block waits on its look-back and stores.
-// Every block is resident and takes its tiles in increasing order, so the
-// lowest unfinished tile can always finish: no block waits on one that has
-// not started.
-template <class C, bool kVec, bool kExcl>
-__global__ __launch_bounds__(C::block) void scan_i32_persist_kernel(
-    const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n, idx_t ntiles,
-    WsHeader* __restrict__ hdr, uint64_t* __restrict__ status) {
-  __shared__ uint32_t s_gen;
-  __shared__ ScanLds sl;
-  auto block = block_x();
-  auto thread = thread_x<C::block>();
-  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
-  sync(thread);
-  const uint32_t gen = s_gen;
-  const idx_t G = block.count();
-  uint32_t x[C::rounds][4], y[C::rounds][4];
-  idx_t t = block.index();
-  if (t < ntiles) load_tile<C, kVec>(in, n, t, ntiles, x);
-  while (t < ntiles) {
-    if (t + G < ntiles) load_tile<C, kVec>(in, n, t + G, ntiles, y);
-    scan_tile<C, kVec, kExcl>(out, n, t, ntiles, gen, hdr, status, x, sl);
-    t += G;
-    if (t >= ntiles) break;
-    if (t + G < ntiles) load_tile<C, kVec>(in, n, t + G, ntiles, x);
-    scan_tile<C, kVec, kExcl>(out, n, t, ntiles, gen, hdr, status, y, sl);
-    t += G;
-  }
-}
-
 template <class C, bool kExcl>
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s) {
   const int64_t ntiles = (n + C::tile - 1) / C::tile;
@@ -249,41 +216,6 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, void* ws, hip
   else
     hipLaunchKernelGGL((scan_i32_kernel<C, false, kExcl>), dim3((unsigned)ntiles), dim3(C::block),
                        0, s, in, out, n, hdr, status);
-  return hipGetLastError();
-}
-
-// The persistent form: a grid of the blocks that fit the device at once
-// (computed once per device and configuration).
-template <class C, bool kExcl>
-hipError_t launch_scan_persist(const int32_t* in, int32_t* out, int64_t n, void* ws,
-                               hipStream_t s) {
-  static int cached[64][2] = {};
-  const int64_t ntiles = (n + C::tile - 1) / C::tile;
-  WsHeader* hdr = (WsHeader*)ws;
-  uint64_t* status = (uint64_t*)((char*)ws + sizeof(WsHeader));
-  const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  int& resident = cached[dev][vec ? 1 : 0];
-  if (resident == 0) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const hipError_t e =
-        vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &per, scan_i32_persist_kernel<C, true, kExcl>, C::block, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                  &per, scan_i32_persist_kernel<C, false, kExcl>, C::block, 0);
-    if (e != hipSuccess || per < 1) per = 1;
-    resident = cus * per;
-  }
-  const int64_t grid = ntiles < resident ? ntiles : resident;
-  if (vec)
-    hipLaunchKernelGGL((scan_i32_persist_kernel<C, true, kExcl>), dim3((unsigned)grid),
-                       dim3(C::block), 0, s, in, out, n, (idx_t)ntiles, hdr, status);
-  else
-    hipLaunchKernelGGL((scan_i32_persist_kernel<C, false, kExcl>), dim3((unsigned)grid),
-                       dim3(C::block), 0, s, in, out, n, (idx_t)ntiles, hdr, status);
   return hipGetLastError();
 }
 
@@ -300,22 +232,16 @@ hipError_t scan_any(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStr
     case 8: return launch_scan<ScanCfg<1024, 8, true>, kExcl>(in, out, n, ws, s);
     case 9: return launch_scan<ScanCfg<512, 32, true>, kExcl>(in, out, n, ws, s);
     case 10: return launch_scan<ScanCfg<1024, 16, true>, kExcl>(in, out, n, ws, s);
-    case 11: return launch_scan_persist<ScanCfg<1024, 8, true>, kExcl>(in, out, n, ws, s);
-    case 12: return launch_scan_persist<ScanCfg<512, 16, true>, kExcl>(in, out, n, ws, s);
-    case 13: return launch_scan_persist<ScanCfg<1024, 4, true>, kExcl>(in, out, n, ws, s);
     default: return launch_scan<ScanCfg<256, 8, true>, kExcl>(in, out, n, ws, s);
   }
 }
 
-// "_persist": the persistent form with the next tile's loads in flight.
 constexpr const char* kNames[] = {"b256_r8_nt", "b256_r8", "b512_r8_nt", "b256_r16_nt",
                                    "b1024_r4_nt", "b512_r4_nt", "b256_r32_nt", "b512_r16_nt",
-                                   "b1024_r8_nt", "b512_r32_nt", "b1024_r16_nt",
-                                   "b1024_r8_nt_persist", "b512_r16_nt_persist",
-                                   "b1024_r4_nt_persist"};
+                                   "b1024_r8_nt", "b512_r32_nt", "b1024_r16_nt"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kScanI32, "scan_i32", 14, kNames, kDefaults), true);
+    (tune::register_op(tune::kScanI32, "scan_i32", 11, kNames, kDefaults), true);
 
 }  // namespace
 
