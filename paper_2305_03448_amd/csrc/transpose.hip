@@ -132,14 +132,20 @@ hipError_t launch_transpose(const uint32_t* in, uint32_t* out, int64_t batch, in
 
 // ----------------------------------------------------------------- other element sizes
 // The same kernel for elements of 1, 2 or 8 bytes (the paper's own example
-// moves doubles): a 16-byte group holds kV = 16 / sizeof(E) elements, a tile
-// is T x T elements read by a [256 / (T/kV)][T/kV] block, and the LDS pitch
-// is padded by 4 bytes (8 for doubles) so that a column read walks the banks.
+// moves doubles): a 16-byte group holds kV = 16 / sizeof(E) elements and a
+// tile is T x T elements read by a [256 / (T/kV)][T/kV] block.  A column
+// read of the LDS tile must spread over the banks: bytes pad the rows by 4
+// bytes; 2- and 8-byte elements keep unpadded rows and XOR-swizzle the
+// column index with the row (a whole-element pad cannot separate the 64
+// rows one wave reads): doubles by c ^ ((r / 2) % 32), which gives the 32
+// rows a half-wave reads 32 different 8-byte bank pairs, and 2-byte elements
+// by c ^ 4 ((r / 8) % 16), which gives the 16 rows of a wave different
+// dword columns while keeping element pairs in one dword.
 template <class E, int kT>
 struct TransposeCfgE {
   static constexpr int v = 16 / (int)sizeof(E);            // elements per 16-byte group
   static constexpr int t = kT;
-  static constexpr int pad = sizeof(E) >= 4 ? 1 : 4 / (int)sizeof(E);
+  static constexpr int pad = sizeof(E) == 1 ? 4 : 0;
   static constexpr int pitch = kT + pad;
   static constexpr int tx = kT / v;
   static constexpr int ty = kBlock / tx;
@@ -158,7 +164,14 @@ __global__ __launch_bounds__(kBlock) void transpose_elem_kernel(const E* __restr
   auto by = block_y();
   auto thread = thread_x<kBlock>();
   const Block bz{(idx_t)blockIdx.z, (idx_t)gridDim.z};
-  auto tile = matrix(lds, T, C::pitch).template fst<1>(T);            // [T][T]
+  auto tile = [&] {
+    if constexpr (sizeof(E) == 8)
+      return matrix(lds, T, T).template xor_swizzle_by<2, 32, 1>();     // [T][T]
+    else if constexpr (sizeof(E) == 2)
+      return matrix(lds, T, T).template xor_swizzle_by<8, 16, 4>();
+    else
+      return matrix(lds, T, C::pitch).template fst<1>(T);
+  }();
 
   const bool full = kVec && (by.index() + 1) * T <= rows && (bx.index() + 1) * T <= cols;
   if (full) {

@@ -132,10 +132,11 @@ struct SplitMap {
 };
 
 // xor_swizzle at depth D: in a [rows][chunks] pair of dimensions, chunk c of
-// row r is stored at chunk c ^ ((r / kDiv) % kMod) of that row -- a
-// permutation within every row, so the view is a bijection onto the same
-// storage.  Used to spread the LDS accesses of consecutive rows over banks.
-template <class P, int D, idx_t kDiv, idx_t kMod>
+// row r is stored at chunk c ^ (((r / kDiv) % kMod) * kMul) of that row -- a
+// permutation within every row (for a power-of-two row length above
+// (kMod - 1) * kMul), so the view is a bijection onto the same storage.  Used
+// to spread the LDS accesses of consecutive rows over banks.
+template <class P, int D, idx_t kDiv, idx_t kMod, idx_t kMul = 1>
 struct XorMap {
   static constexpr int rank = P::rank;
   static_assert(D + 1 < P::rank, "xor_swizzle needs two dimensions");
@@ -143,7 +144,7 @@ struct XorMap {
   DESC_HD idx_t ext(int d) const { return p.ext(d); }
   DESC_HD Idx<rank> to_parent(const Idx<rank>& i) const {
     Idx<rank> j = i;
-    j[D + 1] = i[D + 1] ^ ((i[D] / kDiv) % kMod);
+    j[D + 1] = i[D + 1] ^ (((i[D] / kDiv) % kMod) * kMul);
     return j;
   }
 };
@@ -294,6 +295,8 @@ struct View {
   DESC_HD View<T, ReverseMap<M, D>> reverse() const { return {base, {m}}; }
   template <idx_t kDiv, idx_t kMod, int D = 0>
   DESC_HD View<T, XorMap<M, D, kDiv, kMod>> xor_swizzle() const { return {base, {m}}; }
+  template <idx_t kDiv, idx_t kMod, idx_t kMul, int D = 0>
+  DESC_HD View<T, XorMap<M, D, kDiv, kMod, kMul>> xor_swizzle_by() const { return {base, {m}}; }
   template <int D = 0>
   DESC_HD View<T, SplitMap<M, D>> fst(idx_t pos) const { return {base, {m, pos, false}}; }
   template <int D = 0>

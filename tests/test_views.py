@@ -23,7 +23,7 @@ EXPECTED = [
     "scan_wave_striped_groups_bijection_and_coalesced", "scan_wave_striped_elements_bijection",
     "reduce_block_striped_bijection", "transpose_kernel_maps_T32", "transpose_kernel_maps_T64",
     "transpose_kernel_maps_T128", "gemm_lds_xor_swizzle_bkb32", "gemm_lds_xor_swizzle_bkb64",
-    "gemm_lds_xor_swizzle_bkb128",
+    "gemm_lds_xor_swizzle_bkb128", "transpose_f64_lds_swizzle", "transpose_u16_lds_swizzle",
     # access checking (tests/access_check.hpp): clean kernels, and the
     # conflicts the paper's type system rejects
     "access_check_listing1_racy_conflicts_corrected_clean", "access_check_rev_per_block_needs_barrier",

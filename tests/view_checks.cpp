@@ -325,6 +325,47 @@ int main(int argc, char** argv) {
   transpose_case(std::integral_constant<int, 64>{});
   transpose_case(std::integral_constant<int, 128>{});
 
+  // the LDS swizzles of the 2- and 8-byte transposes: a bijection on the
+  // tile, and the column reads of the write-out spread over the banks
+  // (doubles: the 32 rows 2x + k of a half-wave land on 32 different 8-byte
+  // bank pairs; 2-byte elements: the 16 rows 8x + k of a wave on 16
+  // different dwords mod 64 banks, element pairs sharing a dword)
+  {
+    const int T = 64;
+    std::vector<unsigned long long> lds(T * T);
+    auto v = matrix(lds.data(), T, T).xor_swizzle_by<2, 32, 1>();
+    Access all(T * T);
+    for (int r = 0; r < T; ++r)
+      for (int c = 0; c < T; ++c) all.add(&v.at(r, c) - lds.data(), r * T + c);
+    bool spread = true;
+    for (int k = 0; k < 2; ++k)
+      for (int c = 0; c < T; ++c) {
+        std::set<long> banks;
+        for (int x = 0; x < 32; ++x) banks.insert(((&v.at(2 * x + k, c) - lds.data()) * 2) % 64);
+        spread &= banks.size() == 32;
+      }
+    check(all.bijection() && spread, "transpose_f64_lds_swizzle");
+  }
+  {
+    const int T = 128;
+    std::vector<unsigned short> lds(T * T);
+    auto v = matrix(lds.data(), T, T).xor_swizzle_by<8, 16, 4>();
+    Access all(T * T);
+    for (int r = 0; r < T; ++r)
+      for (int c = 0; c < T; ++c) all.add(&v.at(r, c) - lds.data(), r * T + c);
+    bool spread = true, pairs = true;
+    for (int k = 0; k < 8; ++k)
+      for (int c = 0; c < T; ++c) {
+        std::set<long> dwords;
+        for (int x = 0; x < 16; ++x) dwords.insert(((&v.at(8 * x + k, c) - lds.data()) / 2) % 64);
+        spread &= dwords.size() == 16;
+      }
+    for (int r = 0; r < T; ++r)
+      for (int c = 0; c < T; c += 2)
+        pairs &= (&v.at(r, c) - lds.data()) / 2 == (&v.at(r, c + 1) - lds.data()) / 2;
+    check(all.bijection() && spread && pairs, "transpose_u16_lds_swizzle");
+  }
+
   // --- access checking over the kernels' own maps (access_check.hpp) ----------
   // Listing 1 as printed: the 256 threads of a 32 x 8 block write tmp through
   // the racy index in one interval; the corrected index writes disjointly.
