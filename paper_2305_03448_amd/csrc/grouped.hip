@@ -299,6 +299,9 @@ template <int kCfg>
 constexpr bool kFused = kCfg >= 2;
 template <int kCfg>
 constexpr bool kSmallOnly = kCfg == 0 || kCfg == 2;   // 64 x 64 tiles
+// the fused kernel's tile routine configuration
+template <int kCfg>
+using FusedNt = typename std::conditional<kSmallOnly<kCfg>, NtSmall, NtBig>::type;
 template <int kCfg>
 __device__ __forceinline__ int64_t tile_edge(int64_t, int64_t) {
   return kSmallOnly<kCfg> ? kPad : kPadBig;
@@ -541,14 +544,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOn
 // The fused form: output tiles straight from the FP32 operands, split into
 // hi and lo while they are staged into LDS.
 template <int kCfg>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOnly<kCfg> ? 3 : 2)))
+__global__ __launch_bounds__(FusedNt<kCfg>::threads)
+__attribute__((amdgpu_waves_per_eu(kSmallOnly<kCfg> ? 3 : 2)))
 void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
   static_assert(kFused<kCfg>, "fused configurations only");
-  __shared__ __attribute__((aligned(16)))
-  uint8_t lds[kSmallOnly<kCfg> ? NtSmall::lds_bytes : NtBig::lds_bytes];
+  using Nt = FusedNt<kCfg>;
+  constexpr int kThreads = Nt::threads;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[Nt::lds_bytes];
   __shared__ int64_t s_g;
   auto block = block_x();
-  auto thread = thread_x<kBlock>();
+  auto thread = thread_x<kThreads>();
   const int64_t T = w.totals[2];
   constexpr idx_t kRun = 64, kXcd = 8;
   const bool by_xcd = block.count() % kXcd == 0;
@@ -570,12 +575,11 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
     const idx_t tm = wave::uniform_i64(local / tn), tc = wave::uniform_i64(local % tn);
     if (p.K <= 0) {                 // nothing to load: the tile is zero
       auto c = matrix(p.C, p.M, p.ldc);
-      for (idx_t i = thread.index(); i < e * e; i += kBlock) {
+      for (idx_t i = thread.index(); i < e * e; i += kThreads) {
         const idx_t r = tm * e + i / e, col = tc * e + i % e;
         if (r < p.M && col < p.N) c.at(r, col) = 0.f;
       }
     } else {
-      using Nt = typename std::conditional<kSmallOnly<kCfg>, NtSmall, NtBig>::type;
       const gemm_nt::F32Operands f{p.A, p.lda, p.B, p.ldb, p.M, p.N, p.K};
       if (gemm_f32::vec_ok(p.A, p.lda, p.A, p.lda) && p.K % 4 == 0)
         gemm_nt::tile_split<Nt, true>(f, p.C, p.ldc, tm, tc, lds);
@@ -588,14 +592,14 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
 
 // Blocks of `kernel` that fit the device at once (per device, computed once).
 template <class K>
-int resident_grid(K kernel, int (&cache)[64], int fallback_per_cu) {
+int resident_grid(K kernel, int (&cache)[64], int fallback_per_cu, int threads = kBlock) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   if (cache[dev] == 0) {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
         per < 1)
       per = fallback_per_cu;
     cache[dev] = cus * per;
@@ -610,9 +614,10 @@ hipError_t launch_bf16x3(const desc_gemm_problem* problems, int64_t G, const Bf1
   hipLaunchKernelGGL(bf16_plan_kernel<kCfg>, dim3(1), dim3(kBlock), 0, s, problems, G, w);
   if constexpr (kFused<kCfg>) {
     static int fused_grid[64] = {0};
-    const int gf = resident_grid(bf16_fused_kernel<kCfg>, fused_grid, 2);
-    hipLaunchKernelGGL(bf16_fused_kernel<kCfg>, dim3((unsigned)gf), dim3(kBlock), 0, s, problems,
-                       G, w);
+    constexpr int kThreads = FusedNt<kCfg>::threads;
+    const int gf = resident_grid(bf16_fused_kernel<kCfg>, fused_grid, 1, kThreads);
+    hipLaunchKernelGGL(bf16_fused_kernel<kCfg>, dim3((unsigned)gf), dim3(kThreads), 0, s,
+                       problems, G, w);
   }
   // planes: every problem in configurations 0-2, those with strides past the
   // split source's limit in the fused ones (the kernels exit at once if none)

@@ -113,8 +113,16 @@ def _problems(op: str, dev):
                               torch.empty(M, N, device=dev)))
                 flops += 2 * M * N * K
             d = desc.grouped_descriptors(probs, dev)
-            need = (desc.desc_gemm_grouped_workspace(G) if mode == "f32"
-                    else desc.desc_gemm_grouped_workspace_for(mode, d.cpu()))
+            if mode == "f32":
+                need = desc.desc_gemm_grouped_workspace(G)
+            else:
+                # the workspace depends on the configuration: size it for the largest
+                cls = desc.desc_size_class(op, G)
+                need = 0
+                for cfg in range(desc.desc_config_count(op)):
+                    desc.desc_config_set(op, cls, cfg)
+                    need = max(need, desc.desc_gemm_grouped_workspace_for(mode, d.cpu()))
+                desc.desc_config_set(op, cls, -1)
             ws = torch.empty(need, dtype=torch.uint8, device=dev)
             fn = (lambda d=d, ws=ws, probs=probs, mode=mode:
                   desc.desc_gemm_grouped(d, mode=mode, ws=ws))
