@@ -527,11 +527,15 @@ def desc_gemm_grouped(descriptors: torch.Tensor, mode="f32", ws: torch.Tensor | 
     G = descriptors.shape[0]
     if _mode(mode) == _mode("f32"):
         need = desc_gemm_grouped_workspace(G)
-    elif ws is None:
+    elif ws is None or descriptors_host is not None:
         host = descriptors_host if descriptors_host is not None else descriptors.cpu()
         need = desc_gemm_grouped_workspace_for(mode, host)
         if need == 0 and G > 0:
             raise ValueError("a grouped problem has a shape the bf16x3 mode refuses")
+        if ws is not None and ws.numel() < need:
+            # the device would refuse the call and only set the error word
+            raise ValueError(f"workspace of {ws.numel()} bytes, the current configuration "
+                             f"needs {need}")
     else:
         need = ws.numel()
     w = ws if ws is not None else torch.empty(max(need, 256), dtype=torch.uint8,
