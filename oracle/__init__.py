@@ -52,6 +52,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_scan_exclusive_i32.argtypes = [P, P, I64]
         L.oracle_transpose_u32.argtypes = [P, P, I64, I64]
         L.oracle_transpose_bytes.argtypes = [P, P, I64, I64, I64]
+        L.oracle_reverse_u32.argtypes = [P, P, I64]
         L.oracle_gemm_ref_sampled.argtypes = [P, I64, P, I64, I64, P, P, I64, P, P]
         L.oracle_bf16_rne.argtypes = [F]
         L.oracle_bf16_rne.restype = ctypes.c_uint16
@@ -123,6 +124,15 @@ def transpose_bytes(m) -> np.ndarray:
     rows, cols = m.shape
     out = np.empty((cols, rows), dtype=m.dtype)
     lib().oracle_transpose_bytes(_p(m), _p(out), rows, cols, m.dtype.itemsize)
+    return out
+
+
+def reverse_u32(x) -> np.ndarray:
+    """out[i] = x[n - 1 - i] for a 1-D array of 32-bit elements (bits kept)."""
+    x = np.ascontiguousarray(x)
+    assert x.ndim == 1 and x.dtype.itemsize == 4
+    out = np.empty_like(x)
+    lib().oracle_reverse_u32(_p(x), _p(out), x.size)
     return out
 
 

@@ -104,6 +104,15 @@ void oracle_transpose_bytes(const uint8_t *in, uint8_t *out, int64_t rows, int64
 }
 
 /* ------------------------------------------------------------------ */
+/* Reversal of n 32-bit words: out[i] = in[n - 1 - i] (a byte move).    */
+/* ------------------------------------------------------------------ */
+void oracle_reverse_u32(const uint32_t *in, uint32_t *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        memcpy(&out[i], &in[n - 1 - i], 4);
+}
+
+/* ------------------------------------------------------------------ */
 /* GEMM reference on sampled entries.                                   */
 /* A is M x K (row stride lda), B is K x N (row stride ldb), row-major. */
 /* For each sample s: R[s] = sum_k a[i][k]*b[k][j] in FP64 (every FP32  */

@@ -79,3 +79,19 @@ def test_bytes_f64_bits_preserved():
 def test_bytes_matches_32_bit_form():
     m = workloads.matrix_f32(65, 33, seed=51)
     assert np.array_equal(oracle.transpose_bytes(m), oracle.transpose_u32(m))
+
+
+# ----------------------------------------------------------------- reversal (the reverse view)
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 5, 1000, 4097])
+def test_reverse_self_describing_and_involution(n):
+    x = np.arange(n, dtype=np.uint32)
+    y = oracle.reverse_u32(x)
+    assert np.array_equal(y, np.arange(n - 1, -1, -1, dtype=np.uint32) if n else y)
+    assert np.array_equal(oracle.reverse_u32(y), x)
+
+
+def test_reverse_matches_numpy_and_keeps_bits():
+    x = workloads.matrix_f32(1, 12345, seed=52).ravel()
+    x[:4] = np.array([0x7FC00001, 0x80000000, 0x00000001, 0xFF800000], np.uint32).view(np.float32)
+    y = oracle.reverse_u32(x)
+    assert np.array_equal(y.view(np.uint32), x[::-1].view(np.uint32))
