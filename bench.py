@@ -274,6 +274,19 @@ def op_transpose_elems(desc, torch):
     return out
 
 
+def op_reverse(desc, torch):
+    """Reversal of 2^28 words (the copy through the reverse view) beside the copy."""
+    n = 1 << 28
+    x = torch.zeros(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    ms_r = graph_time_ms(torch, lambda: desc.desc_reverse_u32(x, y), reps=10)
+    ms_c = graph_time_ms(torch, lambda: desc.desc_copy_32(x, y), reps=10)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"reverse_us": round(ms_r * 1e3, 1), "reverse_GBs": round(8 * n / ms_r / 1e6, 1),
+            "copy_us": round(ms_c * 1e3, 1), "copy_GBs": round(8 * n / ms_c / 1e6, 1)}
+
+
 def op_copy(desc, torch):
     n = 1 << 28
     x = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -421,7 +434,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views,variants,"
-                                     "transpose_elems",
+                                     "transpose_elems,reverse",
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -525,6 +538,9 @@ def main(argv=None):
     if "views" in extra:
         log("view kernels against hand-indexed twins")
         result["ops"]["views_vs_hand"] = op_views(desc, torch, workloads)
+    if "reverse" in extra:
+        log("reversal through the reverse view")
+        result["ops"]["reverse_2^28"] = op_reverse(desc, torch)
     if "transpose_elems" in extra:
         log("transposes of 1-, 2- and 8-byte elements")
         result["ops"]["transpose_elems_512MB"] = op_transpose_elems(desc, torch)

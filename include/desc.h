@@ -268,6 +268,11 @@ desc_status desc_scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n,
  * ---------------------------------------------------------------------- */
 desc_status desc_copy_32(const void* in, void* out, int64_t n, void* stream);
 
+/* Reversal of n 32-bit words, out[i] = in[n - 1 - i] (bit patterns moved):
+ * the copy read through the `reverse` view (Sec. 3.2).  `in` and `out` must
+ * not overlap; 4-byte aligned; n = 0 launches nothing. */
+desc_status desc_reverse_u32(const void* in, void* out, int64_t n, void* stream);
+
 /* ------------------------------------------------------------------------
  * Configurations.  Tile shapes are compile-time parameters of the kernels
  * (the paper keeps sizes as nats in the types); each operation is compiled

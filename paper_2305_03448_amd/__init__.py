@@ -27,7 +27,7 @@ __all__ = [
     "desc_reduce_i32_workspace", "desc_reduce_i32",
     "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
-    "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32",
+    "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32", "desc_reverse_u32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
     "desc_config_set", "desc_config_get", "desc_config_load", "OPS",
     "desc_gemm_workspace", "desc_gemm", "GEMM_MODES",
@@ -62,6 +62,7 @@ SIGNATURES = {
     "desc_transpose_batched_f32": (_ST, [_P, _P, _I64, _I64, _I64, _P]),
     "desc_transpose_batched": (_ST, [_P, _P, _I64, _I64, _I64, _I64, _P]),
     "desc_copy_32": (_ST, [_P, _P, _I64, _P]),
+    "desc_reverse_u32": (_ST, [_P, _P, _I64, _P]),
     "desc_config_count": (ctypes.c_int, [ctypes.c_int]),
     "desc_config_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
     "desc_op_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -301,6 +302,19 @@ def desc_transpose_batched(x: torch.Tensor, out: torch.Tensor, stream=None) -> t
         raise ValueError("x must be (rows, cols) or (batch, rows, cols), out the transposes")
     _check(lib().desc_transpose_batched(_ptr(x), _ptr(out), x.element_size(), xs[0], xs[1], xs[2],
                                         _stream(x, stream)), "desc_transpose_batched")
+    return out
+
+
+def desc_reverse_u32(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out[i] = x[n - 1 - i] for contiguous tensors of n 32-bit elements."""
+    if x.device.type != "cuda" or out.device.type != "cuda":
+        raise ValueError("x and out must be in GPU memory")
+    if x.element_size() != 4 or out.element_size() != 4 or x.numel() != out.numel():
+        raise ValueError("x and out must hold the same number of 32-bit elements")
+    if not (x.is_contiguous() and out.is_contiguous()):
+        raise ValueError("x and out must be contiguous")
+    _check(lib().desc_reverse_u32(_ptr(x), _ptr(out), x.numel(), _stream(x, stream)),
+           "desc_reverse_u32")
     return out
 
 

@@ -491,6 +491,18 @@ desc_status desc_copy_32(const void* in, void* out, int64_t n, void* stream) {
       desc::launch::copy_32((const uint32_t*)in, (uint32_t*)out, n, (hipStream_t)stream));
 }
 
+desc_status desc_reverse_u32(const void* in, void* out, int64_t n, void* stream) {
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (nb > 0 && (in == nullptr || out == nullptr)) return DESC_ERR_NULL;
+  if (nb == 0) return DESC_OK;
+  DESC_TRY(check_device({in, out}));
+  if (misaligned(in, 4) || misaligned(out, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb})) return DESC_ERR_ALIAS;
+  return hip_status(
+      desc::launch::reverse_32((const uint32_t*)in, (uint32_t*)out, n, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- configurations
 int desc_config_count(desc_op op) { return desc::tune::config_count((int)op); }
 

@@ -69,6 +69,50 @@ hipError_t launch_copy(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
+// Reversal, out[i] = in[n - 1 - i]: the copy read through the reverse view.
+// With n a multiple of 4 and both arrays 16-byte aligned, the input is seen
+// as 16-byte vectors in reverse order and each vector's four words are
+// swapped end for end; otherwise word by word.
+template <bool kVec>
+__global__ __launch_bounds__(kBlock) void reverse32_kernel(const uint32_t* __restrict__ in,
+                                                           uint32_t* __restrict__ out, int64_t n) {
+  auto block = block_x();
+  auto thread = thread_x<kBlock>();
+  if constexpr (kVec) {
+    constexpr int kUnroll = 4, kChunk = kBlock * kUnroll;
+    const int64_t nvec = n / 4, nchunks = nvec / kChunk;
+    auto src = array((const u32x4*)in, nvec).reverse();
+    auto dst = array((u32x4*)out, nvec);
+    auto sc = src.fst(nchunks * kChunk).group<kBlock>().group<kUnroll>();
+    auto dc = dst.fst(nchunks * kChunk).group<kBlock>().group<kUnroll>();
+    for (idx_t c = block.index(); c < nchunks; c += block.count()) {
+      auto s = sc.idx(c).transpose().select(thread);
+      auto d = dc.idx(c).transpose().select(thread);
+      u32x4 v[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) v[u] = __builtin_nontemporal_load(&s[u]);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const u32x4 w = {v[u].w, v[u].z, v[u].y, v[u].x};
+        __builtin_nontemporal_store(w, &d[u]);
+      }
+    }
+    if (block.index() == block.count() - 1) {   // the vectors after the last full chunk
+      auto rs = src.snd(nchunks * kChunk);
+      auto rd = dst.snd(nchunks * kChunk);
+      for (idx_t i = thread.index(); i < rs.extent(); i += kBlock) {
+        const u32x4 v = rs[i];
+        rd[i] = u32x4{v.w, v.z, v.y, v.x};
+      }
+    }
+  } else {
+    auto src = array(in, n).reverse();
+    auto dst = array(out, n);
+    for (idx_t i = block.index() * kBlock + thread.index(); i < n; i += block.count() * kBlock)
+      dst[i] = src[i];
+  }
+}
+
 constexpr const char* kNames[] = {"u4_nt", "u4", "u8_nt", "u8"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered = (tune::register_op(tune::kCopy32, "copy_32", 4, kNames, kDefaults), true);
@@ -86,6 +130,21 @@ hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) 
     case 3: return launch_copy<8, false>(in, out, n, s);
     default: return launch_copy<4, true>(in, out, n, s);
   }
+}
+
+hipError_t reverse_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const bool vec = n % 4 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  const int64_t per_block = vec ? 4 * kBlock * 4 : kBlock;
+  int64_t grid = (n + per_block - 1) / per_block;
+  if (grid > 16384) grid = 16384;
+  if (vec)
+    hipLaunchKernelGGL(reverse32_kernel<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, out,
+                       n);
+  else
+    hipLaunchKernelGGL(reverse32_kernel<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, in, out,
+                       n);
+  return hipGetLastError();
 }
 
 }  // namespace launch

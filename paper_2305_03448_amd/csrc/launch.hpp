@@ -70,6 +70,7 @@ hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* 
 
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t reverse_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 
 // variants.hip
 hipError_t reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,

@@ -154,6 +154,19 @@ def test_transpose_checks(fake_pointers):
     assert L.desc_transpose_f32(D(0), HOSTP, 3, 3, None) == HOST
 
 
+def test_reverse_checks(fake_pointers):
+    L = fake_pointers
+    st = lambda *a: L.desc_reverse_u32(*a, None)
+    assert st(D(0), D(1 << 20), 0) == OK                               # nothing to move
+    assert st(None, D(1 << 20), 5) == NULL
+    assert st(D(0), None, 5) == NULL
+    assert st(D(0), D(1 << 20), -1) == SIZE
+    assert st(D(0), D(1 << 20), 1 << 62) == SIZE
+    assert st(HOSTP, D(1 << 20), 5) == HOST
+    assert st(D(2), D(1 << 20), 5) == ALIGN
+    assert st(D(0), D(16), 5) == ALIAS                                 # out starts inside in
+
+
 def test_transpose_any_element_size_checks(fake_pointers):
     L = fake_pointers
     st = lambda *a: L.desc_transpose_batched(*a, None)

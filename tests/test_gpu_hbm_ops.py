@@ -340,3 +340,35 @@ def test_transpose_f64_bit_patterns():
     case("transpose f64 bit patterns")
     desc.desc_transpose_batched(x, y)
     assert np.array_equal(y.cpu().view(torch.uint8).numpy().view(np.uint64), m.T)
+
+
+# ------------------------------------------------------------------ reversal (reverse view)
+@pytest.mark.parametrize("n", [0] + EDGE_SIZES)
+def test_reverse_edge_sizes(n):
+    case(f"reverse n={n}")
+    x = workloads.int_uniform(n, seed=800 + n % 71)
+    y = torch.full((n,), -7, dtype=torch.int32, device=dev())
+    desc.desc_reverse_u32(to_dev(x), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.reverse_u32(x))
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+@pytest.mark.parametrize("n", [7, 65536, 300_004])
+def test_reverse_unaligned(n, offset):
+    case(f"reverse unaligned n={n} offset={offset}")
+    x = workloads.int_uniform(n, seed=810)
+    y = torch.empty(n, dtype=torch.int32, device=dev())
+    desc.desc_reverse_u32(to_dev(x, offset), y)
+    assert np.array_equal(y.cpu().numpy(), oracle.reverse_u32(x))
+
+
+def test_reverse_2_28_involution():
+    case("reverse 2^28 twice")
+    x = workloads.int_uniform(1 << 28, seed=2)
+    xt = to_dev(x)
+    y = torch.empty_like(xt)
+    desc.desc_reverse_u32(xt, y)
+    assert np.array_equal(y.cpu().numpy(), oracle.reverse_u32(x))
+    z = torch.empty_like(xt)
+    desc.desc_reverse_u32(y, z)
+    assert torch.equal(z, xt)
