@@ -70,6 +70,9 @@ def lib() -> ctypes.CDLL:
         L.oracle_gemm_fp8_sampled.argtypes = [P, I64, P, I64, P, P, I64, P, P, I64, P, P]
         L.oracle_reduce_segmented_i32.argtypes = [P, P, I64, P]
         L.oracle_scan_segmented_i32.argtypes = [P, P, P, I64]
+        L.oracle_minmax_i32.argtypes = [P, I64, P]
+        L.oracle_sum_f32.argtypes = [P, I64]
+        L.oracle_sum_f32.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -86,6 +89,21 @@ def _c(a, dtype):
 def reduce_i32(x) -> int:
     x = _c(x, np.int32)
     return int(lib().oracle_reduce_i32(_p(x), x.size))
+
+
+def minmax_i32(x):
+    """(min, max) of int32 values; (INT32_MAX, INT32_MIN) for an empty array."""
+    x = _c(x, np.int32)
+    out = np.empty(2, np.int32)
+    lib().oracle_minmax_i32(_p(x), x.size, _p(out))
+    return int(out[0]), int(out[1])
+
+
+def sum_f32(x) -> float:
+    """The exact sum of FP32 values rounded once to the nearest double (IEEE
+    rules for non-finite inputs; a zero total is +0)."""
+    x = _c(x, np.float32)
+    return float(lib().oracle_sum_f32(_p(x), x.size))
 
 
 def scan_i32(x, return_info: bool = False):

@@ -27,6 +27,8 @@
  *                   with round-to-nearest-even and saturation to +-448
  *   - segmented   : the reduce / scan definitions restarted at every segment
  *                   offset
+ *   - min/max     : smallest and largest int32 value (identities when empty)
+ *   - float sum   : the exact sum of FP32 values, rounded once to a double
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
  * (contraction off so that every FP32 multiply rounds on its own).
@@ -34,6 +36,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
+#include <limits.h>
 
 /* ------------------------------------------------------------------ */
 /* Reduce: s = sum_i x_i, exact in int64 (|x_i| < 2^31, n < 2^32).     */
@@ -331,4 +334,103 @@ void oracle_scan_segmented_i32(const int32_t *x, int32_t *y, const int64_t *off,
             y[i] = (int32_t)acc;
         }
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* Min and max of int32 values: out[0] = min, out[1] = max.  An empty  */
+/* array gives the identities out = {INT32_MAX, INT32_MIN}.  (A further */
+/* reduction operator over the same block-wide structure, Sec. 5.)     */
+/* ------------------------------------------------------------------ */
+void oracle_minmax_i32(const int32_t *x, int64_t n, int32_t *out)
+{
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int64_t i = 0; i < n; ++i) {
+        if (x[i] < lo) lo = x[i];
+        if (x[i] > hi) hi = x[i];
+    }
+    out[0] = lo;
+    out[1] = hi;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sum of FP32 values, exactly, returned rounded once to the nearest    */
+/* double (ties to even).  Every finite float is an integer multiple of */
+/* 2^-149 below 2^128, so x * 2^149 is an integer of at most 277 bits;   */
+/* the sum of n < 2^40 of them fits 317 bits.  The integers are added   */
+/* into eleven 32-bit limbs (bits 32k .. 32k+31 of sum * 2^149), held   */
+/* in int64 so that carries can wait, and the total is rounded at the  */
+/* end.  Non-finite inputs follow IEEE addition, which for a sum is     */
+/* order-free: any NaN, or +inf together with -inf, gives NaN; else an  */
+/* infinity gives that infinity.  A zero total is returned as +0.      */
+/* (The float reduction is the                                          */
+/* block-wide reduction of Sec. 5 over another element type; the paper  */
+/* fixes no order, so the exact sum is the reference.)                  */
+/* ------------------------------------------------------------------ */
+#define ORACLE_LIMBS 11
+
+static void limbs_carry(int64_t *L)
+{
+    for (int k = 0; k < ORACLE_LIMBS - 1; ++k) {
+        int64_t c = L[k] >> 32;               /* floor division by 2^32 */
+        L[k] -= c * ((int64_t)1 << 32);
+        L[k + 1] += c;
+    }
+}
+
+double oracle_sum_f32(const float *x, int64_t n)
+{
+    int64_t L[ORACLE_LIMBS] = {0};
+    int nan = 0, pinf = 0, ninf = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t u;
+        memcpy(&u, &x[i], 4);
+        const uint32_t ef = (u >> 23) & 0xFF, frac = u & 0x7FFFFF;
+        if (ef == 0xFF) {
+            if (frac) nan = 1;
+            else if (u >> 31) ninf = 1;
+            else pinf = 1;
+            continue;
+        }
+        /* value = m * 2^(s - 149) with m < 2^24, s in [0, 253] */
+        const int64_t m = ef ? (int64_t)(frac | 0x800000u) : (int64_t)frac;
+        const int s = ef ? (int)ef - 1 : 0;
+        const int64_t v = (u >> 31) ? -(m << (s % 32)) : (m << (s % 32));   /* |v| < 2^55 */
+        const int k = s / 32;
+        L[k] += v & 0xFFFFFFFF;     /* low 32 bits, as a non-negative number */
+        L[k + 1] += v >> 32;        /* the rest, floor-shifted */
+        if ((i & 0xFFFFF) == 0xFFFFF) limbs_carry(L);
+    }
+    if (nan || (pinf && ninf)) return NAN;
+    if (pinf) return INFINITY;
+    if (ninf) return -INFINITY;
+    limbs_carry(L);
+    /* limbs 0..9 now lie in [0, 2^32); the top limb carries the sign */
+    int neg = L[ORACLE_LIMBS - 1] < 0;
+    uint32_t mag[ORACLE_LIMBS];
+    if (neg) {                      /* two's-complement negation over the limbs */
+        uint64_t borrow = 1;
+        for (int k = 0; k < ORACLE_LIMBS; ++k) {
+            uint64_t w = (uint64_t)(~(uint32_t)L[k]) + borrow;
+            mag[k] = (uint32_t)w;
+            borrow = w >> 32;
+        }
+    } else {
+        for (int k = 0; k < ORACLE_LIMBS; ++k) mag[k] = (uint32_t)L[k];
+    }
+    int top = -1;                   /* highest set bit of the magnitude */
+    for (int b = 32 * ORACLE_LIMBS - 1; b >= 0; --b)
+        if ((mag[b / 32] >> (b % 32)) & 1u) { top = b; break; }
+    if (top < 0) return 0.0;
+#define BIT(b) ((b) >= 0 && ((mag[(b) / 32] >> ((b) % 32)) & 1u))
+    int lo = top - 52 > 0 ? top - 52 : 0;   /* keep bits lo..top: at most 53 */
+    uint64_t mant = 0;
+    for (int b = top; b >= lo; --b) mant = (mant << 1) | (uint64_t)BIT(b);
+    if (lo > 0) {                   /* round to nearest, ties to even */
+        int round = BIT(lo - 1), sticky = 0;
+        for (int b = lo - 2; b >= 0 && !sticky; --b) sticky = BIT(b);
+        if (round && (sticky || (mant & 1))) mant += 1;
+    }
+#undef BIT
+    double r = ldexp((double)mant, lo - 149);
+    return neg ? -r : r;
 }

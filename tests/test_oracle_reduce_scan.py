@@ -154,3 +154,101 @@ def test_scan_exclusive_wraps_modulo_2_32():
     x = np.full(5, 2**31 - 1, np.int32)
     y = oracle.scan_exclusive_i32(x)
     assert y.tolist() == [_wrap32(k * (2**31 - 1)) for k in range(5)]
+
+
+# ------------------------------------------------------------------ min / max
+def test_minmax_bruteforce_tiny():
+    vals = (-3, -1, 0, 2, 5)
+    for length in range(1, 5):
+        for xs in itertools.product(vals, repeat=length):
+            assert oracle.minmax_i32(np.array(xs, dtype=np.int32)) == (min(xs), max(xs))
+
+
+def test_minmax_matches_numpy_and_extremes():
+    x = workloads.int_uniform(100003, 21, -(1 << 31), (1 << 31) - 1)
+    assert oracle.minmax_i32(x) == (int(x.min()), int(x.max()))
+    y = np.zeros(4099, np.int32)
+    y[4098] = -(1 << 31)
+    y[0] = (1 << 31) - 1
+    assert oracle.minmax_i32(y) == (-(1 << 31), (1 << 31) - 1)
+    # a sorted run: the ends are the answer
+    z = np.arange(-777, 5000, dtype=np.int32)
+    assert oracle.minmax_i32(z) == (-777, 4999)
+    assert oracle.minmax_i32(z[::-1]) == (-777, 4999)
+
+
+def test_minmax_empty_gives_identities():
+    assert oracle.minmax_i32(np.zeros(0, np.int32)) == ((1 << 31) - 1, -(1 << 31))
+
+
+# ------------------------------------------------------------------ float sum
+def _fraction_sum(x):
+    from fractions import Fraction
+    return float(sum((Fraction(float(v)) for v in x), Fraction(0)))   # rounds once
+
+
+def test_sum_f32_matches_exact_rationals():
+    # Python's float(Fraction) rounds the exact rational correctly; the
+    # inputs span the whole float32 range, denormals and zeros included.
+    g = np.random.default_rng(31)
+    for trial in range(40):
+        n = int(g.integers(1, 200))
+        exp = g.integers(-149, 127, size=n)
+        sig = 1.0 + g.random(n)
+        x = (np.where(g.random(n) < 0.5, -1.0, 1.0) * np.ldexp(sig, exp))
+        x = np.clip(x, -3.4e38, 3.4e38).astype(np.float32)
+        x[g.random(n) < 0.1] = 0.0
+        assert oracle.sum_f32(x) == _fraction_sum(x), trial
+
+
+def test_sum_f32_matches_fsum():
+    import math
+    for seed, (lo, hi) in [(32, (-40, 40)), (33, (-126, 100)), (34, (-2, 2))]:
+        x = workloads.wide_f32(200001, seed, lo, hi)
+        assert oracle.sum_f32(x) == math.fsum(x.astype(np.float64))
+
+
+def test_sum_f32_closed_forms():
+    # integers 1..n are exact in float32 up to 2^24; their sum is n(n+1)/2
+    n = 1 << 20
+    assert oracle.sum_f32(np.arange(1, n + 1, dtype=np.float32)) == n * (n + 1) / 2
+    # catastrophic cancellation keeps the small term exactly
+    assert oracle.sum_f32(np.array([2.0 ** 100, 1.0, -(2.0 ** 100)], np.float32)) == 1.0
+    assert oracle.sum_f32(np.array([2.0 ** 100, 2.0 ** -100, -(2.0 ** 100)], np.float32)) \
+        == 2.0 ** -100
+    # 2^k copies of the smallest denormal, and of the largest float
+    tiny = np.full(1 << 12, np.float32(2.0 ** -149))
+    assert oracle.sum_f32(tiny) == 2.0 ** -137
+    big = np.full(1 << 20, np.finfo(np.float32).max)
+    assert oracle.sum_f32(big) == float(np.finfo(np.float32).max) * 2.0 ** 20
+    assert oracle.sum_f32(-big) == -float(np.finfo(np.float32).max) * 2.0 ** 20
+
+
+def test_sum_f32_rounds_once_to_nearest_even():
+    t = 2.0 ** 53
+    cases = [([t, 1.0], t),                    # halfway, even below
+             ([t, 1.0, 2.0], t + 4.0),         # 2^53 + 3: halfway, even above
+             ([t, 1.0, 2.0 ** -20], t + 2.0),  # just above halfway
+             ([t, 1.0, -(2.0 ** -20)], t),     # just below halfway
+             ([t, t, 1.0], 2 * t)]             # 2^54 + 1: below halfway of step 4
+    for xs, want in cases:
+        x = np.array(xs, np.float32)
+        assert oracle.sum_f32(x) == want, xs
+        assert oracle.sum_f32(-x) == -want, xs
+
+
+def test_sum_f32_is_order_free_and_empty_is_zero():
+    x = workloads.wide_f32(50000, 35)
+    p = np.random.default_rng(36).permutation(x.size)
+    assert oracle.sum_f32(x[p]) == oracle.sum_f32(x)
+    assert oracle.sum_f32(x[::-1]) == oracle.sum_f32(x)
+    assert oracle.sum_f32(np.zeros(0, np.float32)) == 0.0
+    assert oracle.sum_f32(np.array([-0.0, -0.0], np.float32)) == 0.0
+
+
+def test_sum_f32_non_finite_follow_ieee():
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    assert oracle.sum_f32(np.array([1.0, inf, -5.0], np.float32)) == np.inf
+    assert oracle.sum_f32(np.array([1.0, -inf], np.float32)) == -np.inf
+    assert np.isnan(oracle.sum_f32(np.array([inf, 2.0, -inf], np.float32)))
+    assert np.isnan(oracle.sum_f32(np.array([1.0, nan, inf], np.float32)))

@@ -15,6 +15,8 @@ Generator: numpy ``Generator(PCG64(seed))``.
   [0, 1), which is log-uniform over [1, 2**20]; the offsets array is the
   exclusive running total of the lengths (``offsets[0] = 0``,
   ``offsets[S] = T``);
+* wide-range FP32: sign from ``random() < 0.5``, significand ``1 + random()``,
+  exponent ``integers(emin, emax + 1)`` (default [-40, 40]), cast to float32;
 * grouped GEMM shapes: ``64 * integers(1, 17, size=(G, 3))`` -> (M, N, K)
   each uniform over {64, 128, ..., 1024}.
 
@@ -34,6 +36,7 @@ SEEDS = {
     "gemm8192_a": 7, "gemm8192_b": 8, "gemm8192_samples": 9,
     "seg_lengths": 10, "seg_values": 11,
     "grouped_shapes": 12, "grouped_values": 13, "grouped_samples": 14,
+    "reduce_f32": 15,       # 2**28 float32, wide exponent range
 }
 
 SIZES = {
@@ -59,6 +62,17 @@ def int_uniform(n: int, seed: int, lo: int = -1024, hi: int = 1024) -> np.ndarra
 def normal_f32(shape, seed: int) -> np.ndarray:
     """N(0, 1) drawn in float64 and rounded to float32."""
     return rng(seed).standard_normal(size=shape, dtype=np.float64).astype(np.float32)
+
+
+def wide_f32(n: int, seed: int, emin: int = -40, emax: int = 40) -> np.ndarray:
+    """``n`` float32 values with a random sign, a significand uniform in
+    [1, 2) and an exponent uniform over [emin, emax] (a wide dynamic range,
+    so that the order of a floating-point sum shows in its rounding)."""
+    g = rng(seed)
+    sig = 1.0 + g.random(n)
+    exp = g.integers(emin, emax + 1, size=n)
+    sign = np.where(g.random(n) < 0.5, -1.0, 1.0)
+    return (sign * np.ldexp(sig, exp)).astype(np.float32)
 
 
 def matrix_f32(rows: int, cols: int, seed: int) -> np.ndarray:
