@@ -317,6 +317,44 @@ def op_reduce(desc, torch, workloads):
             "cold_us": round(cold * 1e3, 2), "cold_GBs": round(nbytes / cold / 1e6, 1)}
 
 
+def op_reduce_ops(desc, torch, workloads, oracle):
+    """Min/max of 2^28 int32 and the fixed-order FP64 sum of 2^28 float32
+    (wide exponent range, seed 15), beside the int32 sum of the same size,
+    as graph replays; each result checked against the oracle."""
+    import numpy as np
+    n = 1 << 28
+    xi_np = workloads.int_uniform(n, seed=2, lo=-(1 << 31), hi=(1 << 31) - 1)
+    xi = torch.from_numpy(xi_np).cuda()
+    mm = torch.empty(2, dtype=torch.int32, device="cuda")
+    si = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = torch.zeros(desc.desc_reduce_op_workspace(n), dtype=torch.uint8, device="cuda")
+    wsi = torch.zeros(desc.desc_reduce_i32_workspace(n), dtype=torch.uint8, device="cuda")
+    ms_mm = graph_time_ms(torch, lambda: desc.desc_reduce_minmax_i32(xi, mm, ws=ws), reps=10)
+    ms_si = graph_time_ms(torch, lambda: desc.desc_reduce_i32(xi, si, ws=wsi), reps=10)
+    ok_mm = tuple(mm.cpu().tolist()) == oracle.minmax_i32(xi_np)
+    ok_si = int(si.item()) == oracle.reduce_i32(xi_np)
+    del xi, xi_np
+    xf_np = workloads.wide_f32(n, seed=15)
+    xf = torch.from_numpy(xf_np).cuda()
+    sf = torch.empty(1, dtype=torch.float64, device="cuda")
+    ms_sf = graph_time_ms(torch, lambda: desc.desc_reduce_sum_f32(xf, sf, ws=ws), reps=10)
+    got = float(sf.item())
+    chunks = n // 4096
+    G = min(chunks, 2048)
+    d = 16 * (-(-chunks // G)) + (-(-G // 256)) + 16
+    bound = d * 2.0 ** -53 * float(np.abs(xf_np.astype(np.float64)).sum())
+    exact = oracle.sum_f32(xf_np)
+    del xf, xf_np, ws, wsi
+    torch.cuda.empty_cache()
+    gbs = lambda ms: round(4 * n / ms / 1e6, 1)
+    return {"n": n,
+            "minmax_us": round(ms_mm * 1e3, 1), "minmax_GBs": gbs(ms_mm), "minmax_check": ok_mm,
+            "sum_f32_us": round(ms_sf * 1e3, 1), "sum_f32_GBs": gbs(ms_sf),
+            "sum_f32_err": abs(got - exact), "sum_f32_bound": bound,
+            "sum_f32_check": abs(got - exact) <= bound,
+            "sum_i32_us": round(ms_si * 1e3, 1), "sum_i32_GBs": gbs(ms_si), "sum_i32_check": ok_si}
+
+
 def op_gemm(desc, torch, workloads, oracle, n, seeds, modes):
     import numpy as np
     A_np = workloads.matrix_f32(n, n, seed=seeds[0])
@@ -434,7 +472,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ops", default="copy,reduce,gemm,gemm8192,segmented,grouped,views,variants,"
-                                     "transpose_elems,reverse",
+                                     "transpose_elems,reverse,reduce_ops",
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -550,6 +588,9 @@ def main(argv=None):
     if "reduce" in extra:
         log("reduce 2^22")
         result["ops"]["reduce_2^22"] = op_reduce(desc, torch, workloads)
+    if "reduce_ops" in extra:
+        log("min/max and fixed-order float sum 2^28")
+        result["ops"]["reduce_ops_2^28"] = op_reduce_ops(desc, torch, workloads, oracle)
     if "gemm" in extra:
         log("gemm 4096^3")
         result["ops"]["gemm_4096"] = op_gemm(desc, torch, workloads, oracle, 4096, (4, 5, 6),

@@ -82,6 +82,38 @@ desc_status desc_reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws
                             size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Two more reductions over the block-wide structure of the sum (Sec. 5,
+ * "block-wide parallel reduction", with other operators and element types).
+ *
+ * desc_reduce_minmax_i32: out[0] = min, out[1] = max of in[0..n); n = 0
+ * writes the identities {INT32_MAX, INT32_MIN}.  `out` int32[2].
+ *
+ * desc_reduce_sum_f32: out[0] = the sum of the float32 values in[0..n),
+ * accumulated in FP64 in an order fixed by the element indices and n alone
+ * (not by the input address, the run or the hardware's scheduling), so
+ * equal inputs give bit-equal results.  The order: elements are taken in
+ * chunks of 4096; lane j (0..255) of block b adds, from 0.0, elements
+ * 1024u + 4j + e (u, e = 0..3) of chunks b, b + G, b + 2G, ... in that order;
+ * the 256 lane values of a block meet in a tree (inside each 64-lane wave
+ * lane i adds lane i^32, then i^16, 8, 4, 2, 1; then the four waves as
+ * (w0 + w1) + (w2 + w3)); lane t of the last block adds the values of blocks
+ * t, t + 256, ... from 0.0 and the same tree combines those.  G = min(max(
+ * ceil(n / 4096), 1), 2048).  The error against the exact sum is at most
+ * d * 2^-53 * sum|in[i]|, d = 16 ceil(ceil(n / 4096) / G) + ceil(G / 256)
+ * + 16.  Non-finite inputs follow IEEE addition (NaN, or +inf with -inf,
+ * gives NaN).  n = 0 writes +0.0.  `out` double[1], 8-byte aligned.
+ *
+ * Both: `in` 4-byte aligned (may be NULL when n = 0); one workspace of
+ * desc_reduce_op_workspace(n) bytes, zeroed before first use, may serve both
+ * calls but no other entry point.
+ * ---------------------------------------------------------------------- */
+size_t desc_reduce_op_workspace(int64_t n);
+desc_status desc_reduce_minmax_i32(const int32_t* in, int64_t n, int32_t* out, void* ws,
+                                   size_t ws_bytes, void* stream);
+desc_status desc_reduce_sum_f32(const float* in, int64_t n, double* out, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Inclusive scan (Sec. 5, "scan"): out[i] = in[0] + ... + in[i] modulo 2^32
  * (two's-complement wrap), int32 in and out, out-of-place.  n = 0 launches
  * nothing.

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libdesc.so")
 __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
+    "desc_reduce_op_workspace", "desc_reduce_minmax_i32", "desc_reduce_sum_f32",
     "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32", "desc_reverse_u32",
@@ -52,6 +53,9 @@ SIGNATURES = {
     "desc_set_pointer_classifier": (None, [_P]),
     "desc_reduce_i32_workspace": (_SZ, [_I64]),
     "desc_reduce_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
+    "desc_reduce_op_workspace": (_SZ, [_I64]),
+    "desc_reduce_minmax_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
+    "desc_reduce_sum_f32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
     "desc_scan_i32_workspace": (_SZ, [_I64]),
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_scan_exclusive_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
@@ -198,6 +202,37 @@ def desc_reduce_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None 
     w = _ws("reduce_i32", desc_reduce_i32_workspace(n), x, ws)
     _check(lib().desc_reduce_i32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(), _stream(x, stream)),
            "desc_reduce_i32")
+    return out
+
+
+# ------------------------------------------------------------------ min/max, float sum
+def desc_reduce_op_workspace(n: int) -> int:
+    return lib().desc_reduce_op_workspace(n)
+
+
+def desc_reduce_minmax_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    """out = [min, max] of int32 ``x`` ([INT32_MAX, INT32_MIN] when empty)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if out.numel() != 2:
+        raise ValueError("out must hold two int32")
+    n = x.numel()
+    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws)
+    _check(lib().desc_reduce_minmax_i32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(),
+                                        _stream(x, stream)), "desc_reduce_minmax_i32")
+    return out
+
+
+def desc_reduce_sum_f32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+    """out[0] = FP64 sum of float32 ``x`` in the order fixed by the indices and n."""
+    _dev(x, torch.float32, "x"); _dev(out, torch.float64, "out")
+    if out.numel() != 1:
+        raise ValueError("out must hold one float64")
+    n = x.numel()
+    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws)
+    _check(lib().desc_reduce_sum_f32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(),
+                                     _stream(x, stream)), "desc_reduce_sum_f32")
     return out
 
 

@@ -127,6 +127,40 @@ desc_status desc_reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws
   return hip_status(desc::launch::reduce_i32(in, n, out, ws, (hipStream_t)stream));
 }
 
+// ----------------------------------------------------------------- min/max, float sum
+size_t desc_reduce_op_workspace(int64_t n) { return desc::launch::reduce_op_workspace(n); }
+
+namespace {
+// The checks shared by the two reductions: `in` holds n 4-byte elements,
+// `out` out_bytes bytes aligned to out_align.
+desc_status reduce_op_checked(const void* in, int64_t n, void* out, int64_t out_bytes,
+                              int64_t out_align, void* ws, size_t ws_bytes) {
+  if (out == nullptr || ws == nullptr || (in == nullptr && n > 0)) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({n > 0 ? in : nullptr, out, ws}));
+  if (misaligned(in, 4) || misaligned(out, out_align) || misaligned(ws, 8))
+    return DESC_ERR_ALIGNMENT;
+  if (overlap({out, out_bytes}, {in, nb}) || overlap({ws, (int64_t)ws_bytes}, {in, nb}) ||
+      overlap({ws, (int64_t)ws_bytes}, {out, out_bytes}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < desc_reduce_op_workspace(n)) return DESC_ERR_WORKSPACE;
+  return DESC_OK;
+}
+}  // namespace
+
+desc_status desc_reduce_minmax_i32(const int32_t* in, int64_t n, int32_t* out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  DESC_TRY(reduce_op_checked(in, n, out, 8, 4, ws, ws_bytes));
+  return hip_status(desc::launch::minmax_i32(in, n, out, ws, (hipStream_t)stream));
+}
+
+desc_status desc_reduce_sum_f32(const float* in, int64_t n, double* out, void* ws,
+                                size_t ws_bytes, void* stream) {
+  DESC_TRY(reduce_op_checked(in, n, out, 8, 8, ws, ws_bytes));
+  return hip_status(desc::launch::sum_f32(in, n, out, ws, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- scan
 size_t desc_scan_i32_workspace(int64_t n) {
   return desc::launch::scan_i32_workspace(n < 0 ? 0 : n);

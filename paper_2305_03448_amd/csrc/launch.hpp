@@ -16,6 +16,12 @@ constexpr int kReduceMaxBlocks = 2048;
 size_t reduce_i32_workspace(int64_t n);
 hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipStream_t s);
 
+// reduce_ops.hip
+int64_t reduce_op_grid(int64_t n);
+size_t reduce_op_workspace(int64_t n);
+hipError_t minmax_i32(const int32_t* in, int64_t n, int32_t* out, void* ws, hipStream_t s);
+hipError_t sum_f32(const float* in, int64_t n, double* out, void* ws, hipStream_t s);
+
 // scan.hip
 size_t scan_i32_workspace(int64_t n);
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,

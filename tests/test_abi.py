@@ -85,6 +85,31 @@ def test_reduce_checks(fake_pointers):
     assert st(D(0), 100, D(4096), D(1 << 20), wsb - 1) == WS
 
 
+@pytest.mark.parametrize("entry,out_align", [("desc_reduce_minmax_i32", 4),
+                                              ("desc_reduce_sum_f32", 8)])
+def test_reduce_op_checks(fake_pointers, entry, out_align):
+    L = fake_pointers
+    wsb = L.desc_reduce_op_workspace(100)
+    assert wsb == 64 + 16 and L.desc_reduce_op_workspace(1 << 28) == 64 + 16 * 2048
+    assert L.desc_reduce_op_workspace(0) == L.desc_reduce_op_workspace(-5) == 64 + 16
+    st = lambda *a: getattr(L, entry)(*a, None)
+    assert st(D(0), 100, None, D(1 << 20), wsb) == NULL
+    assert st(None, 100, D(4096), D(1 << 20), wsb) == NULL
+    assert st(D(0), 100, D(4096), None, wsb) == NULL
+    assert st(D(0), -1, D(4096), D(1 << 20), wsb) == SIZE
+    assert st(D(0), 1 << 62, D(4096), D(1 << 20), wsb) == SIZE
+    assert st(HOSTP, 100, D(4096), D(1 << 20), wsb) == HOST
+    assert st(D(0), 100, HOSTP, D(1 << 20), wsb) == HOST
+    assert st(D(0), 100, D(4096), HOSTP, wsb) == HOST
+    assert st(D(2), 100, D(4096), D(1 << 20), wsb) == ALIGN
+    assert st(D(0), 100, D(4096 + out_align // 2), D(1 << 20), wsb) == ALIGN
+    assert st(D(0), 100, D(4096), D((1 << 20) + 4), wsb) == ALIGN
+    assert st(D(0), 100, D(392), D(1 << 20), wsb) == ALIAS          # out overlaps in's end
+    assert st(D(0), 100, D(4096), D(96), wsb) == ALIAS              # ws overlaps in
+    assert st(D(0), 100, D(4096), D(4096 - 16), wsb) == ALIAS       # ws overlaps out
+    assert st(D(0), 100, D(4096), D(1 << 20), wsb - 1) == WS
+
+
 @pytest.mark.parametrize("entry", ["desc_scan_i32", "desc_scan_exclusive_i32"])
 def test_scan_checks(fake_pointers, entry):
     L = fake_pointers
