@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         L.oracle_minmax_i32.argtypes = [P, I64, P]
         L.oracle_sum_f32.argtypes = [P, I64]
         L.oracle_sum_f32.restype = ctypes.c_double
+        L.oracle_scan_f32_at.argtypes = [P, I64, P, I64, P]
+        L.oracle_scan_f32_at.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -104,6 +106,17 @@ def sum_f32(x) -> float:
     rules for non-finite inputs; a zero total is +0)."""
     x = _c(x, np.float32)
     return float(lib().oracle_sum_f32(_p(x), x.size))
+
+
+def scan_f32(x, idx=None) -> np.ndarray:
+    """Exact inclusive prefix sums of FP32 values, each rounded once to the
+    nearest double, at the ascending positions ``idx`` (all when None)."""
+    x = _c(x, np.float32)
+    idx = np.arange(x.size, dtype=np.int64) if idx is None else _c(idx, np.int64)
+    out = np.empty(idx.size, np.float64)
+    if lib().oracle_scan_f32_at(_p(x), x.size, _p(idx), idx.size, _p(out)) != 0:
+        raise ValueError("positions must be ascending and below n")
+    return out
 
 
 def scan_i32(x, return_info: bool = False):

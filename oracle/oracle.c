@@ -29,6 +29,7 @@
  *                   offset
  *   - min/max     : smallest and largest int32 value (identities when empty)
  *   - float sum   : the exact sum of FP32 values, rounded once to a double
+ *   - float scan  : the exact inclusive prefixes, each rounded once
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC
  * (contraction off so that every FP32 multiply rounds on its own).
@@ -368,6 +369,12 @@ void oracle_minmax_i32(const int32_t *x, int64_t n, int32_t *out)
 /* ------------------------------------------------------------------ */
 #define ORACLE_LIMBS 11
 
+typedef struct {
+    int64_t L[ORACLE_LIMBS];   /* sum * 2^149 in 32-bit limbs, carries pending */
+    int64_t pending;           /* additions since the last carry pass */
+    int nan, pinf, ninf;
+} exact_acc;
+
 static void limbs_carry(int64_t *L)
 {
     for (int k = 0; k < ORACLE_LIMBS - 1; ++k) {
@@ -377,52 +384,58 @@ static void limbs_carry(int64_t *L)
     }
 }
 
-double oracle_sum_f32(const float *x, int64_t n)
+static void exact_add(exact_acc *a, float xf)
 {
-    int64_t L[ORACLE_LIMBS] = {0};
-    int nan = 0, pinf = 0, ninf = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        uint32_t u;
-        memcpy(&u, &x[i], 4);
-        const uint32_t ef = (u >> 23) & 0xFF, frac = u & 0x7FFFFF;
-        if (ef == 0xFF) {
-            if (frac) nan = 1;
-            else if (u >> 31) ninf = 1;
-            else pinf = 1;
-            continue;
-        }
-        /* value = m * 2^(s - 149) with m < 2^24, s in [0, 253] */
-        const int64_t m = ef ? (int64_t)(frac | 0x800000u) : (int64_t)frac;
-        const int s = ef ? (int)ef - 1 : 0;
-        const int64_t v = (u >> 31) ? -(m << (s % 32)) : (m << (s % 32));   /* |v| < 2^55 */
-        const int k = s / 32;
-        L[k] += v & 0xFFFFFFFF;     /* low 32 bits, as a non-negative number */
-        L[k + 1] += v >> 32;        /* the rest, floor-shifted */
-        if ((i & 0xFFFFF) == 0xFFFFF) limbs_carry(L);
+    uint32_t u;
+    memcpy(&u, &xf, 4);
+    const uint32_t ef = (u >> 23) & 0xFF, frac = u & 0x7FFFFF;
+    if (ef == 0xFF) {
+        if (frac) a->nan = 1;
+        else if (u >> 31) a->ninf = 1;
+        else a->pinf = 1;
+        return;
     }
-    if (nan || (pinf && ninf)) return NAN;
-    if (pinf) return INFINITY;
-    if (ninf) return -INFINITY;
-    limbs_carry(L);
+    /* value = m * 2^(s - 149) with m < 2^24, s in [0, 253] */
+    const int64_t m = ef ? (int64_t)(frac | 0x800000u) : (int64_t)frac;
+    const int s = ef ? (int)ef - 1 : 0;
+    const int64_t v = (u >> 31) ? -(m << (s % 32)) : (m << (s % 32));   /* |v| < 2^55 */
+    const int k = s / 32;
+    a->L[k] += v & 0xFFFFFFFF;     /* low 32 bits, as a non-negative number */
+    a->L[k + 1] += v >> 32;        /* the rest, floor-shifted */
+    if (++a->pending == (1 << 20)) {
+        limbs_carry(a->L);
+        a->pending = 0;
+    }
+}
+
+/* The accumulated value rounded once to the nearest double, ties to even. */
+static double exact_round(exact_acc *a)
+{
+    if (a->nan || (a->pinf && a->ninf)) return NAN;
+    if (a->pinf) return INFINITY;
+    if (a->ninf) return -INFINITY;
+    limbs_carry(a->L);             /* value-preserving */
+    a->pending = 0;
     /* limbs 0..9 now lie in [0, 2^32); the top limb carries the sign */
-    int neg = L[ORACLE_LIMBS - 1] < 0;
+    const int neg = a->L[ORACLE_LIMBS - 1] < 0;
     uint32_t mag[ORACLE_LIMBS];
     if (neg) {                      /* two's-complement negation over the limbs */
         uint64_t borrow = 1;
         for (int k = 0; k < ORACLE_LIMBS; ++k) {
-            uint64_t w = (uint64_t)(~(uint32_t)L[k]) + borrow;
+            uint64_t w = (uint64_t)(~(uint32_t)a->L[k]) + borrow;
             mag[k] = (uint32_t)w;
             borrow = w >> 32;
         }
     } else {
-        for (int k = 0; k < ORACLE_LIMBS; ++k) mag[k] = (uint32_t)L[k];
+        for (int k = 0; k < ORACLE_LIMBS; ++k) mag[k] = (uint32_t)a->L[k];
     }
     int top = -1;                   /* highest set bit of the magnitude */
-    for (int b = 32 * ORACLE_LIMBS - 1; b >= 0; --b)
-        if ((mag[b / 32] >> (b % 32)) & 1u) { top = b; break; }
+    for (int k = ORACLE_LIMBS - 1; k >= 0 && top < 0; --k)
+        for (int b = 31; b >= 0; --b)
+            if ((mag[k] >> b) & 1u) { top = 32 * k + b; break; }
     if (top < 0) return 0.0;
 #define BIT(b) ((b) >= 0 && ((mag[(b) / 32] >> ((b) % 32)) & 1u))
-    int lo = top - 52 > 0 ? top - 52 : 0;   /* keep bits lo..top: at most 53 */
+    const int lo = top - 52 > 0 ? top - 52 : 0;   /* keep bits lo..top: at most 53 */
     uint64_t mant = 0;
     for (int b = top; b >= lo; --b) mant = (mant << 1) | (uint64_t)BIT(b);
     if (lo > 0) {                   /* round to nearest, ties to even */
@@ -431,6 +444,35 @@ double oracle_sum_f32(const float *x, int64_t n)
         if (round && (sticky || (mant & 1))) mant += 1;
     }
 #undef BIT
-    double r = ldexp((double)mant, lo - 149);
+    const double r = ldexp((double)mant, lo - 149);
     return neg ? -r : r;
+}
+
+double oracle_sum_f32(const float *x, int64_t n)
+{
+    exact_acc a;
+    memset(&a, 0, sizeof a);
+    for (int64_t i = 0; i < n; ++i) exact_add(&a, x[i]);
+    return exact_round(&a);
+}
+
+/* ------------------------------------------------------------------ */
+/* Inclusive scan of FP32 values, exactly: out[k] = x[0] + ... + x[i]  */
+/* for i = idx[k], rounded once to the nearest double (idx ascending,   */
+/* each below n).  The same exact accumulator as the sum, read at the   */
+/* requested positions; idx = 0, 1, ..., n-1 gives the whole scan.      */
+/* (The scan of Sec. 5 over float values; the paper fixes no order, so  */
+/* the exact prefix is the reference.)                                  */
+/* ------------------------------------------------------------------ */
+int oracle_scan_f32_at(const float *x, int64_t n, const int64_t *idx, int64_t m, double *out)
+{
+    exact_acc a;
+    memset(&a, 0, sizeof a);
+    int64_t i = 0;
+    for (int64_t k = 0; k < m; ++k) {
+        if (idx[k] < i - 1 || idx[k] >= n) return -1;   /* not ascending or out of range */
+        for (; i <= idx[k]; ++i) exact_add(&a, x[i]);
+        out[k] = exact_round(&a);
+    }
+    return 0;
 }

@@ -252,3 +252,46 @@ def test_sum_f32_non_finite_follow_ieee():
     assert oracle.sum_f32(np.array([1.0, -inf], np.float32)) == -np.inf
     assert np.isnan(oracle.sum_f32(np.array([inf, 2.0, -inf], np.float32)))
     assert np.isnan(oracle.sum_f32(np.array([1.0, nan, inf], np.float32)))
+
+
+# ------------------------------------------------------------------ float scan
+def test_scan_f32_matches_exact_rationals():
+    from fractions import Fraction
+    g = np.random.default_rng(37)
+    for trial in range(25):
+        n = int(g.integers(1, 120))
+        x = (np.where(g.random(n) < 0.5, -1.0, 1.0) *
+             np.ldexp(1.0 + g.random(n), g.integers(-149, 127, size=n)))
+        x = np.clip(x, -3.4e38, 3.4e38).astype(np.float32)
+        acc, want = Fraction(0), []
+        for v in x:
+            acc += Fraction(float(v))
+            want.append(float(acc))        # rounds once
+        assert oracle.scan_f32(x).tolist() == want, trial
+
+
+def test_scan_f32_closed_forms_and_cancellation():
+    n = 1 << 16
+    k = np.arange(1, n + 1, dtype=np.float64)
+    assert np.array_equal(oracle.scan_f32(k.astype(np.float32)), k * (k + 1) / 2)
+    x = np.array([2.0 ** 100, 1.0, -(2.0 ** 100), 1.0, 2.0 ** -149], np.float32)
+    # 2^100 + 1 is not a double: it rounds to 2^100; the exact sum keeps the 1
+    # 2 + 2^-149 needs 150 significant bits: it rounds to 2
+    assert oracle.scan_f32(x).tolist() == [2.0 ** 100, 2.0 ** 100, 1.0, 2.0, 2.0]
+
+
+def test_scan_f32_positions_last_and_fsum():
+    import math
+    x = workloads.wide_f32(100_003, 38)
+    full = oracle.scan_f32(x)
+    idx = np.sort(np.random.default_rng(39).choice(x.size, 500, replace=False))
+    idx = np.concatenate([[0, 0], idx, [x.size - 1]]).astype(np.int64)
+    assert np.array_equal(oracle.scan_f32(x, idx), full[idx])
+    assert full[-1] == oracle.sum_f32(x)
+    for i in idx[::25]:
+        assert full[i] == math.fsum(x[: i + 1].astype(np.float64))
+    with pytest.raises(ValueError):
+        oracle.scan_f32(x, np.array([5, 4], np.int64))
+    with pytest.raises(ValueError):
+        oracle.scan_f32(x, np.array([x.size], np.int64))
+    assert oracle.scan_f32(np.zeros(0, np.float32)).size == 0
