@@ -318,9 +318,10 @@ def op_reduce(desc, torch, workloads):
 
 
 def op_reduce_ops(desc, torch, workloads, oracle):
-    """Min/max of 2^28 int32 and the fixed-order FP64 sum of 2^28 float32
-    (wide exponent range, seed 15), beside the int32 sum of the same size,
-    as graph replays; each result checked against the oracle."""
+    """Min/max of 2^28 int32, the fixed-order FP64 sum and the fixed-order
+    scan of 2^28 float32 (wide exponent range, seed 15), beside the int32 sum
+    of the same size, as graph replays; each result checked against the
+    oracle (the scan at 2048 sampled positions)."""
     import numpy as np
     n = 1 << 28
     xi_np = workloads.int_uniform(n, seed=2, lo=-(1 << 31), hi=(1 << 31) - 1)
@@ -344,7 +345,18 @@ def op_reduce_ops(desc, torch, workloads, oracle):
     d = 16 * (-(-chunks // G)) + (-(-G // 256)) + 16
     bound = d * 2.0 ** -53 * float(np.abs(xf_np.astype(np.float64)).sum())
     exact = oracle.sum_f32(xf_np)
-    del xf, xf_np, ws, wsi
+    # the fixed-order float scan of the same input, beside the int32 scan
+    yf = torch.empty_like(xf)
+    wss = torch.zeros(desc.desc_scan_f32_workspace(n), dtype=torch.uint8, device="cuda")
+    ms_scf = graph_time_ms(torch, lambda: desc.desc_scan_f32(xf, yf, ws=wss), reps=10)
+    idx = np.unique(np.random.default_rng(44).integers(0, n, 2048)).astype(np.int64)
+    ys = yf[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.float64)
+    ex = oracle.scan_f32(xf_np, idx)
+    cum = np.cumsum(np.abs(xf_np.astype(np.float64)))[idx]
+    d_scan = -(-(n // 65536) // 64) + 160
+    ok_scf = bool(np.all(np.abs(ys - ex) <= 2.0 ** -24 * np.abs(ex) + 2.0 ** -149
+                         + d_scan * 2.0 ** -53 * cum * (1 + 1e-6)))
+    del xf, xf_np, ws, wsi, yf, wss
     torch.cuda.empty_cache()
     gbs = lambda ms: round(4 * n / ms / 1e6, 1)
     return {"n": n,
@@ -352,7 +364,9 @@ def op_reduce_ops(desc, torch, workloads, oracle):
             "sum_f32_us": round(ms_sf * 1e3, 1), "sum_f32_GBs": gbs(ms_sf),
             "sum_f32_err": abs(got - exact), "sum_f32_bound": bound,
             "sum_f32_check": abs(got - exact) <= bound,
-            "sum_i32_us": round(ms_si * 1e3, 1), "sum_i32_GBs": gbs(ms_si), "sum_i32_check": ok_si}
+            "sum_i32_us": round(ms_si * 1e3, 1), "sum_i32_GBs": gbs(ms_si), "sum_i32_check": ok_si,
+            "scan_f32_us": round(ms_scf * 1e3, 1), "scan_f32_GBs": round(8 * n / ms_scf / 1e6, 1),
+            "scan_f32_check": ok_scf}
 
 
 def op_gemm(desc, torch, workloads, oracle, n, seeds, modes):

@@ -129,6 +129,27 @@ desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, 
                                     size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Inclusive scan of float32 values (the scan of Sec. 5 over floats):
+ * out[i] = the prefix in[0] + ... + in[i], accumulated in FP64 in an order
+ * fixed by the element indices and n alone, and rounded once to float32, so
+ * equal inputs give bit-equal outputs on every run and at every address.
+ * The order: tiles of 65536 elements, each [16 waves][16 rounds][64 lanes]
+ * [4]; within a tile, lane sums of four, a wave scan in DPP order and
+ * sequential carries over rounds and waves; across tiles, the aggregates of
+ * each group of 64 tiles meet in a butterfly and the groups' sums are
+ * chained in order (the full statement is in the kernel's source).  Error
+ * against the exact prefix S_i: at most 2^-24 |S_i| + 2^-149 +
+ * d 2^-53 sum_{k<=i} |in[k]|, d = ceil(ceil(n / 65536) / 64) + 160.
+ * Non-finite inputs follow IEEE addition; zero prefixes come out as +0.
+ * Out-of-place; `in`, `out` 4-byte aligned; n = 0 launches nothing.  The
+ * workspace (desc_scan_f32_workspace(n) bytes, zeroed before first use)
+ * serves no other entry point.
+ * ---------------------------------------------------------------------- */
+size_t desc_scan_f32_workspace(int64_t n);
+desc_status desc_scan_f32(const float* in, float* out, int64_t n, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
  * The paper's own forms of the two operations above (Sec. 5), for
  * comparison with the single-pass forms.
  *

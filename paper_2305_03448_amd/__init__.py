@@ -26,6 +26,7 @@ __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
     "desc_reduce_op_workspace", "desc_reduce_minmax_i32", "desc_reduce_sum_f32",
+    "desc_scan_f32_workspace", "desc_scan_f32",
     "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32", "desc_reverse_u32",
@@ -56,6 +57,8 @@ SIGNATURES = {
     "desc_reduce_op_workspace": (_SZ, [_I64]),
     "desc_reduce_minmax_i32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
     "desc_reduce_sum_f32": (_ST, [_P, _I64, _P, _P, _SZ, _P]),
+    "desc_scan_f32_workspace": (_SZ, [_I64]),
+    "desc_scan_f32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_scan_i32_workspace": (_SZ, [_I64]),
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_scan_exclusive_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
@@ -233,6 +236,25 @@ def desc_reduce_sum_f32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | N
     w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws)
     _check(lib().desc_reduce_sum_f32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(),
                                      _stream(x, stream)), "desc_reduce_sum_f32")
+    return out
+
+
+# ------------------------------------------------------------------ fixed-order float scan
+def desc_scan_f32_workspace(n: int) -> int:
+    return lib().desc_scan_f32_workspace(n)
+
+
+def desc_scan_f32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """Inclusive scan of float32 ``x`` into ``out``, FP64 accumulation in the
+    order fixed by the indices and n, rounded once to float32."""
+    _dev(x, torch.float32, "x"); _dev(out, torch.float32, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many elements as x")
+    n = x.numel()
+    w = _ws("scan_f32", desc_scan_f32_workspace(n), x, ws)
+    _check(lib().desc_scan_f32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
+           "desc_scan_f32")
     return out
 
 

@@ -193,6 +193,24 @@ desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, 
   return scan_checked(in, out, n, ws, ws_bytes, stream, true);
 }
 
+// ----------------------------------------------------------------- fixed-order float scan
+size_t desc_scan_f32_workspace(int64_t n) { return desc::launch::scan_f32_workspace(n); }
+
+desc_status desc_scan_f32(const float* in, float* out, int64_t n, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (ws == nullptr || ((in == nullptr || out == nullptr) && n > 0)) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (n == 0) return DESC_OK;
+  DESC_TRY(check_device({in, out, ws}));
+  if (misaligned(in, 4) || misaligned(out, 4) || misaligned(ws, 8)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb}) || overlap({ws, (int64_t)ws_bytes}, {in, nb}) ||
+      overlap({ws, (int64_t)ws_bytes}, {out, nb}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < desc_scan_f32_workspace(n)) return DESC_ERR_WORKSPACE;
+  return hip_status(desc::launch::scan_f32(in, out, n, ws, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- the paper's forms
 desc_status desc_reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,
                                    void* stream) {

@@ -27,6 +27,10 @@ size_t scan_i32_workspace(int64_t n);
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws, hipStream_t s,
                     bool exclusive = false);
 
+// scan_f32.hip
+size_t scan_f32_workspace(int64_t n);
+hipError_t scan_f32(const float* in, float* out, int64_t n, void* ws, hipStream_t s);
+
 // transpose.hip
 int64_t transpose_max_rows();
 hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_t rows,

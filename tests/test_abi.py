@@ -110,6 +110,28 @@ def test_reduce_op_checks(fake_pointers, entry, out_align):
     assert st(D(0), 100, D(4096), D(1 << 20), wsb - 1) == WS
 
 
+def test_scan_f32_checks(fake_pointers):
+    L = fake_pointers
+    wsb = L.desc_scan_f32_workspace(100)
+    assert wsb == 64 + 16 + 16
+    assert L.desc_scan_f32_workspace((1 << 28) + 1) == 64 + 16 * 4097 + 16 * 65
+    st = lambda *a: L.desc_scan_f32(*a, None)
+    assert st(D(0), D(4096), 100, None, wsb) == NULL
+    assert st(None, D(4096), 100, D(1 << 20), wsb) == NULL
+    assert st(D(0), None, 100, D(1 << 20), wsb) == NULL
+    assert st(D(0), D(4096), -1, D(1 << 20), wsb) == SIZE
+    assert st(D(0), D(4096), 1 << 62, D(1 << 20), wsb) == SIZE
+    assert st(HOSTP, D(4096), 100, D(1 << 20), wsb) == HOST
+    assert st(D(0), HOSTP, 100, D(1 << 20), wsb) == HOST
+    assert st(D(2), D(4096), 100, D(1 << 20), wsb) == ALIGN
+    assert st(D(0), D(4098), 100, D(1 << 20), wsb) == ALIGN
+    assert st(D(0), D(4096), 100, D((1 << 20) + 4), wsb) == ALIGN
+    assert st(D(0), D(200), 100, D(1 << 20), wsb) == ALIAS
+    assert st(D(0), D(4096), 100, D(4096 + 200), wsb) == ALIAS
+    assert st(D(0), D(4096), 100, D(1 << 20), wsb - 1) == WS
+    assert st(None, None, 0, D(1 << 20), 0) == 0         # n = 0: nothing to check or launch
+
+
 @pytest.mark.parametrize("entry", ["desc_scan_i32", "desc_scan_exclusive_i32"])
 def test_scan_checks(fake_pointers, entry):
     L = fake_pointers
