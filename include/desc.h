@@ -293,6 +293,45 @@ desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_pr
                               void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Strided batched GEMM: C_g = A_g B_g for g < G, one shape M x N x K, with
+ * A_g = A + g * stride_a, B_g = B + g * stride_b, C_g = C + g * stride_c
+ * (strides in elements, >= 0; row-major, lda >= K, ldb >= N, ldc >= N as
+ * for desc_gemm).  Modes DESC_GEMM_F32 and DESC_GEMM_BF16X3, with the
+ * arithmetic of desc_gemm_grouped: a kernel writes the G problem
+ * descriptors into the front of the workspace and the grouped kernels run
+ * on them.  The workspace (256-byte aligned, no initialisation) must hold
+ * desc_gemm_strided_batched_workspace(mode, G, M, N, K, lda, ldb) bytes (0
+ * for an unsupported mode or a refused shape).  Checks as for desc_gemm on
+ * the spans of all batches; outputs of two batches that would overlap
+ * (stride_c < (M - 1) ldc + N with G > 1) are DESC_ERR_ALIAS.  G = 0, M = 0
+ * or N = 0 launches nothing; K = 0 writes zeros.
+ * ---------------------------------------------------------------------- */
+size_t desc_gemm_strided_batched_workspace(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
+                                           int64_t K, int64_t lda, int64_t ldb);
+desc_status desc_gemm_strided_batched(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
+                                      int64_t K, const float* A, int64_t lda, int64_t stride_a,
+                                      const float* B, int64_t ldb, int64_t stride_b, float* C,
+                                      int64_t ldc, int64_t stride_c, void* ws, size_t ws_bytes,
+                                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Uniform batched reduce and scan: `in` is a row-major batch x len int32
+ * matrix, each row one segment of the segmented forms below (offsets
+ * s * len, written by a kernel into the front of the workspace).
+ *   reduce : out[b] = exact int64 sum of row b (0 when len = 0).
+ *   scan   : out[b][i] = in[b][0] + ... + in[b][i] modulo 2^32.
+ * Workspaces (8-byte aligned, no initialisation): the matching
+ * *_batched_i32_workspace(batch, len) bytes.  batch = 0 (and, for the scan,
+ * len = 0) launches nothing.
+ * ---------------------------------------------------------------------- */
+size_t desc_reduce_batched_i32_workspace(int64_t batch, int64_t len);
+desc_status desc_reduce_batched_i32(const int32_t* in, int64_t batch, int64_t len, int64_t* out,
+                                    void* ws, size_t ws_bytes, void* stream);
+size_t desc_scan_batched_i32_workspace(int64_t batch, int64_t len);
+desc_status desc_scan_batched_i32(const int32_t* in, int32_t* out, int64_t batch, int64_t len,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Segmented forms (batched Sec. 5 reduction and scan): `in` holds n int32
  * values; segment s covers positions [offsets[s], offsets[s+1]) for
  * s < num_segments, with offsets int64[num_segments + 1] in GPU memory,

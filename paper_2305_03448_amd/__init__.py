@@ -39,6 +39,9 @@ __all__ = [
     "desc_scan_segmented_i32_workspace", "desc_scan_segmented_i32",
     "desc_gemm_grouped_workspace", "desc_gemm_grouped_workspace_for", "desc_gemm_grouped",
     "grouped_descriptors",
+    "desc_gemm_strided_batched_workspace", "desc_gemm_strided_batched",
+    "desc_reduce_batched_i32_workspace", "desc_reduce_batched_i32",
+    "desc_scan_batched_i32_workspace", "desc_scan_batched_i32",
 ]
 
 _P = ctypes.c_void_p
@@ -92,6 +95,13 @@ SIGNATURES = {
     "desc_gemm_grouped_workspace": (_SZ, [_I64]),
     "desc_gemm_grouped_workspace_for": (_SZ, [ctypes.c_int, _I64, _P]),
     "desc_gemm_grouped": (_ST, [ctypes.c_int, _I64, _P, _P, _SZ, _P]),
+    "desc_gemm_strided_batched_workspace": (_SZ, [ctypes.c_int, _I64, _I64, _I64, _I64, _I64, _I64]),
+    "desc_gemm_strided_batched": (_ST, [ctypes.c_int, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P,
+                                        _I64, _I64, _P, _I64, _I64, _P, _SZ, _P]),
+    "desc_reduce_batched_i32_workspace": (_SZ, [_I64, _I64]),
+    "desc_reduce_batched_i32": (_ST, [_P, _I64, _I64, _P, _P, _SZ, _P]),
+    "desc_scan_batched_i32_workspace": (_SZ, [_I64, _I64]),
+    "desc_scan_batched_i32": (_ST, [_P, _P, _I64, _I64, _P, _SZ, _P]),
 }
 
 # desc_gemm_mode values
@@ -613,3 +623,72 @@ def desc_gemm_grouped(descriptors: torch.Tensor, mode="f32", ws: torch.Tensor | 
                                               device=descriptors.device)
     _check(lib().desc_gemm_grouped(_mode(mode), G, _ptr(descriptors), _ptr(w), w.numel(),
                                    _stream(descriptors, stream)), "desc_gemm_grouped")
+
+
+# ------------------------------------------------------------------ uniform batched forms
+def desc_reduce_batched_i32_workspace(batch: int, length: int) -> int:
+    return lib().desc_reduce_batched_i32_workspace(batch, length)
+
+
+def desc_scan_batched_i32_workspace(batch: int, length: int) -> int:
+    return lib().desc_scan_batched_i32_workspace(batch, length)
+
+
+def desc_reduce_batched_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                            stream=None) -> torch.Tensor:
+    """out[b] = exact int64 sum of row b of the 2-D int32 ``x``."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int64, "out")
+    if x.dim() != 2 or out.numel() != x.shape[0]:
+        raise ValueError("x must be 2-D and out hold one int64 per row")
+    B, L = x.shape
+    w = _ws("batched_reduce", desc_reduce_batched_i32_workspace(B, L), x, ws)
+    _check(lib().desc_reduce_batched_i32(_ptr(x), B, L, _ptr(out), _ptr(w), w.numel(),
+                                         _stream(x, stream)), "desc_reduce_batched_i32")
+    return out
+
+
+def desc_scan_batched_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = None,
+                          stream=None) -> torch.Tensor:
+    """Inclusive scan of every row of the 2-D int32 ``x`` (wrapping modulo 2^32)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if x.dim() != 2 or out.shape != x.shape:
+        raise ValueError("x must be 2-D and out of the same shape")
+    B, L = x.shape
+    w = _ws("batched_scan", desc_scan_batched_i32_workspace(B, L), x, ws)
+    _check(lib().desc_scan_batched_i32(_ptr(x), _ptr(out), B, L, _ptr(w), w.numel(),
+                                       _stream(x, stream)), "desc_scan_batched_i32")
+    return out
+
+
+def _strided3(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 tensor in GPU memory")
+    if t.dim() != 3 or (t.numel() > 0 and t.stride(2) != 1):
+        raise ValueError(f"{name} must be 3-D with unit stride in its last dimension")
+    return t
+
+
+def desc_gemm_strided_batched_workspace(mode, G: int, M: int, N: int, K: int, lda: int,
+                                        ldb: int) -> int:
+    return lib().desc_gemm_strided_batched_workspace(_mode(mode), G, M, N, K, lda, ldb)
+
+
+def desc_gemm_strided_batched(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, mode="f32",
+                              ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """C[g] = A[g] @ B[g] for 3-D float32 tensors with unit stride in the last
+    dimension (any batch and row strides, e.g. padded views)."""
+    _strided3(A, "A"); _strided3(B, "B"); _strided3(C, "C")
+    G, M, K = A.shape
+    N = B.shape[2]
+    if B.shape[:2] != (G, K) or tuple(C.shape) != (G, M, N):
+        raise ValueError("shapes must be A (G, M, K), B (G, K, N), C (G, M, N)")
+    lda, ldb, ldc = A.stride(1), B.stride(1), C.stride(1)
+    need = desc_gemm_strided_batched_workspace(mode, G, M, N, K, lda, ldb)
+    if need == 0 and G > 0 and M > 0 and N > 0:
+        raise ValueError("shape refused by this mode")
+    w = _ws("strided_batched_" + str(mode), need, C, ws)
+    _check(lib().desc_gemm_strided_batched(_mode(mode), G, M, N, K, _ptr(A), lda, A.stride(0),
+                                           _ptr(B), ldb, B.stride(0), _ptr(C), ldc, C.stride(0),
+                                           _ptr(w), w.numel(), _stream(C, stream)),
+           "desc_gemm_strided_batched")
+    return C

@@ -470,6 +470,121 @@ desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_pr
       desc::launch::gemm_grouped_bf16x3(problems, G, ws, ws_bytes, (hipStream_t)stream));
 }
 
+// ----------------------------------------------------------------- strided batched GEMM
+namespace {
+// Bytes from the first element of batch 0 to the end of the last row of
+// batch G - 1 (rows x cols at leading dimension ld, batches `stride` apart).
+int64_t batch_span_bytes(int64_t G, int64_t stride, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t one = matrix_bytes(rows, cols, ld, 4);
+  if (one <= 0 || G <= 1) return one;
+  const int64_t step = bytes_of(G - 1, stride);
+  if (step < 0 || step > INT64_MAX / 4) return -1;
+  if (step * 4 > INT64_MAX - one) return -1;
+  return step * 4 + one;
+}
+}  // namespace
+
+size_t desc_gemm_strided_batched_workspace(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
+                                           int64_t K, int64_t lda, int64_t ldb) {
+  if (G < 0 || G > INT32_MAX || M < 0 || N < 0 || K < 0) return 0;
+  const size_t head = desc::launch::strided_problems_bytes(G);
+  if (mode == DESC_GEMM_F32) return head + desc::launch::gemm_grouped_workspace(G);
+  if (mode != DESC_GEMM_BF16X3) return 0;
+  const desc_gemm_problem p{M, N, K, lda, ldb, N, nullptr, nullptr, nullptr};
+  const size_t rest = desc::launch::gemm_grouped_bf16x3_workspace_uniform(p, G);
+  if (rest == SIZE_MAX || rest > SIZE_MAX - head) return 0;
+  return head + rest;
+}
+
+desc_status desc_gemm_strided_batched(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
+                                      int64_t K, const float* A, int64_t lda, int64_t stride_a,
+                                      const float* B, int64_t ldb, int64_t stride_b, float* C,
+                                      int64_t ldc, int64_t stride_c, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (G < 0 || M < 0 || N < 0 || K < 0 || stride_a < 0 || stride_b < 0 || stride_c < 0)
+    return DESC_ERR_SIZE;
+  if (mode != DESC_GEMM_F32 && mode != DESC_GEMM_BF16X3) return DESC_ERR_UNSUPPORTED;
+  if (G == 0 || M == 0 || N == 0) return DESC_OK;
+  if (C == nullptr || ws == nullptr || (K > 0 && (A == nullptr || B == nullptr)))
+    return DESC_ERR_NULL;
+  if (G > INT32_MAX || ldc < N || (K > 0 && (lda < K || ldb < N))) return DESC_ERR_SIZE;
+  const int64_t a_b = K > 0 ? batch_span_bytes(G, stride_a, M, K, lda) : 0;
+  const int64_t b_b = K > 0 ? batch_span_bytes(G, stride_b, K, N, ldb) : 0;
+  const int64_t c_b = batch_span_bytes(G, stride_c, M, N, ldc);
+  if (a_b < 0 || b_b < 0 || c_b < 0) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({K > 0 ? (const void*)A : nullptr, K > 0 ? (const void*)B : nullptr, C,
+                         ws}));
+  if (misaligned(A, 4) || misaligned(B, 4) || misaligned(C, 4) || misaligned(ws, 256))
+    return DESC_ERR_ALIGNMENT;
+  // outputs must not overlap the operands, one another, or the workspace
+  if (overlap({C, c_b}, {A, a_b}) || overlap({C, c_b}, {B, b_b}) ||
+      (G > 1 && stride_c < (M - 1) * ldc + N))
+    return DESC_ERR_ALIAS;
+  const int64_t wsb = (int64_t)ws_bytes;
+  if (overlap({ws, wsb}, {A, a_b}) || overlap({ws, wsb}, {B, b_b}) || overlap({ws, wsb}, {C, c_b}))
+    return DESC_ERR_ALIAS;
+  const size_t need = desc_gemm_strided_batched_workspace(mode, G, M, N, K, lda, ldb);
+  if (need == 0) return DESC_ERR_SIZE;
+  if (ws_bytes < need) return DESC_ERR_WORKSPACE;
+  return hip_status(desc::launch::gemm_strided_batched(mode, G, M, N, K, A, lda, stride_a, B,
+                                                       ldb, stride_b, C, ldc, stride_c, ws,
+                                                       ws_bytes, (hipStream_t)stream));
+}
+
+// ----------------------------------------------------------------- uniform batched reduce/scan
+size_t desc_reduce_batched_i32_workspace(int64_t batch, int64_t len) {
+  if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return 0;
+  return desc::launch::batched_offsets_bytes(batch) +
+         desc::launch::segmented_workspace(batch * len, batch, false);
+}
+
+size_t desc_scan_batched_i32_workspace(int64_t batch, int64_t len) {
+  if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return 0;
+  return desc::launch::batched_offsets_bytes(batch) +
+         desc::launch::segmented_workspace(batch * len, batch, true);
+}
+
+namespace {
+desc_status check_batched(const int32_t* in, const void* out, int64_t out_bytes, int64_t n,
+                          int64_t batch, void* ws, size_t ws_bytes, size_t need) {
+  if (ws == nullptr || out == nullptr || (n > 0 && in == nullptr)) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0 || out_bytes < 0 || batch > INT32_MAX ||
+      desc::launch::segmented_max_grid(n, batch) > INT32_MAX)
+    return DESC_ERR_SIZE;
+  DESC_TRY(check_device({n > 0 ? (const void*)in : nullptr, out, ws}));
+  if (misaligned(in, 4) || misaligned(out, 4) || misaligned(ws, 8)) return DESC_ERR_ALIGNMENT;
+  const int64_t wsb = (int64_t)ws_bytes;
+  if (overlap({out, out_bytes}, {in, nb}) || overlap({ws, wsb}, {in, nb}) ||
+      overlap({ws, wsb}, {out, out_bytes}))
+    return DESC_ERR_ALIAS;
+  if (ws_bytes < need) return DESC_ERR_WORKSPACE;
+  return DESC_OK;
+}
+}  // namespace
+
+desc_status desc_reduce_batched_i32(const int32_t* in, int64_t batch, int64_t len, int64_t* out,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return DESC_ERR_SIZE;
+  if (batch == 0) return DESC_OK;
+  const int64_t ob = bytes_of(batch, 8);
+  DESC_TRY(check_batched(in, out, ob, batch * len, batch, ws, ws_bytes,
+                         desc_reduce_batched_i32_workspace(batch, len)));
+  if (misaligned(out, 8)) return DESC_ERR_ALIGNMENT;
+  return hip_status(
+      desc::launch::reduce_batched_i32(in, batch, len, out, ws, (hipStream_t)stream));
+}
+
+desc_status desc_scan_batched_i32(const int32_t* in, int32_t* out, int64_t batch, int64_t len,
+                                  void* ws, size_t ws_bytes, void* stream) {
+  if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return DESC_ERR_SIZE;
+  if (batch == 0 || len == 0) return DESC_OK;
+  DESC_TRY(check_batched(in, out, bytes_of(batch * len, 4), batch * len, batch, ws, ws_bytes,
+                         desc_scan_batched_i32_workspace(batch, len)));
+  return hip_status(
+      desc::launch::scan_batched_i32(in, out, batch, len, ws, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- segmented
 size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments) {
   if (n < 0 || num_segments < 0) return 0;

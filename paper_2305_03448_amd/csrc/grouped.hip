@@ -667,6 +667,18 @@ size_t gemm_grouped_bf16x3_workspace(const desc_gemm_problem* host, int64_t G) {
   return total;
 }
 
+size_t gemm_grouped_bf16x3_workspace_uniform(const desc_gemm_problem& p, int64_t G) {
+  const int cfg =
+      tune::get(tune::kGemmGroupedBf16x3, tune::size_class(tune::kGemmGroupedBf16x3, G));
+  const size_t head = bf16_head_bytes(G);
+  const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
+  if (d.huge) return SIZE_MAX;
+  if (G == 0 || fused_route(cfg, p.lda, p.ldb)) return head;
+  const size_t b = (size_t)bf16_plane_bytes(d);
+  if (b != 0 && (size_t)G > (SIZE_MAX - head) / b) return SIZE_MAX;
+  return head + (size_t)G * b;
+}
+
 hipError_t gemm_grouped_bf16x3(const desc_gemm_problem* problems, int64_t G, void* ws,
                                size_t ws_bytes, hipStream_t s) {
   (void)kRegisteredBf16;

@@ -78,6 +78,20 @@ hipError_t gemm_grouped_bf16x3(const desc_gemm_problem* problems, int64_t G, voi
 hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* ws,
                             hipStream_t s);
 
+// batched.hip
+size_t batched_offsets_bytes(int64_t B);
+size_t strided_problems_bytes(int64_t G);
+hipError_t reduce_batched_i32(const int32_t* in, int64_t B, int64_t L, int64_t* out, void* ws,
+                              hipStream_t s);
+hipError_t scan_batched_i32(const int32_t* in, int32_t* out, int64_t B, int64_t L, void* ws,
+                            hipStream_t s);
+hipError_t gemm_strided_batched(int mode, int64_t G, int64_t M, int64_t N, int64_t K,
+                                const float* A, int64_t lda, int64_t sa, const float* Bm,
+                                int64_t ldb, int64_t sb, float* C, int64_t ldc, int64_t sc,
+                                void* ws, size_t ws_bytes, hipStream_t s);
+// grouped.hip: the BF16X3 workspace for G problems of one shape
+size_t gemm_grouped_bf16x3_workspace_uniform(const desc_gemm_problem& p, int64_t G);
+
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t reverse_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);

@@ -132,6 +132,57 @@ def test_scan_f32_checks(fake_pointers):
     assert st(None, None, 0, D(1 << 20), 0) == 0         # n = 0: nothing to check or launch
 
 
+def test_batched_reduce_scan_checks(fake_pointers):
+    L = fake_pointers
+    for entry, wsf in (("desc_reduce_batched_i32", L.desc_reduce_batched_i32_workspace),
+                       ("desc_scan_batched_i32", L.desc_scan_batched_i32_workspace)):
+        wsb = wsf(10, 10)
+        assert wsb > 0 and wsf(-1, 5) == 0 and wsf(1 << 40, 1 << 40) == 0
+        if entry == "desc_reduce_batched_i32":
+            st = lambda i, b, l, o, w, n: L.desc_reduce_batched_i32(i, b, l, o, w, n, None)
+        else:
+            st = lambda i, b, l, o, w, n: L.desc_scan_batched_i32(i, o, b, l, w, n, None)
+        assert st(D(0), 10, 10, None, D(1 << 20), wsb) == NULL
+        assert st(None, 10, 10, D(4096), D(1 << 20), wsb) == NULL
+        assert st(D(0), 10, 10, D(4096), None, wsb) == NULL
+        assert st(D(0), -1, 10, D(4096), D(1 << 20), wsb) == SIZE
+        assert st(D(0), 10, -1, D(4096), D(1 << 20), wsb) == SIZE
+        assert st(D(0), 1 << 40, 1 << 40, D(4096), D(1 << 20), wsb) == SIZE
+        assert st(HOSTP, 10, 10, D(4096), D(1 << 20), wsb) == HOST
+        assert st(D(0), 10, 10, HOSTP, D(1 << 20), wsb) == HOST
+        assert st(D(2), 10, 10, D(4096), D(1 << 20), wsb) == ALIGN
+        assert st(D(0), 10, 10, D(4096), D((1 << 20) + 4), wsb) == ALIGN
+        assert st(D(0), 10, 10, D(200), D(1 << 20), wsb) == ALIAS
+        assert st(D(0), 10, 10, D(4096), D(0), wsb) == ALIAS
+        assert st(D(0), 10, 10, D(4096), D(1 << 20), wsb - 1) == WS
+        assert st(None, 0, 10, None, None, 0) == 0              # batch = 0: nothing to do
+    assert L.desc_reduce_batched_i32(D(0), 10, 10, D(4100), D(1 << 20), 1 << 16, None) == ALIGN
+
+
+def test_strided_batched_gemm_checks(fake_pointers):
+    L = fake_pointers
+    F32, BF = 0, 1
+    wsb = L.desc_gemm_strided_batched_workspace(F32, 4, 8, 8, 8, 8, 8)
+    assert wsb > 0 and L.desc_gemm_strided_batched_workspace(2, 4, 8, 8, 8, 8, 8) == 0
+    assert L.desc_gemm_strided_batched_workspace(BF, 4, 8, 8, 8, 8, 8) > 0
+    A, B, C, W = D(0), D(1 << 16), D(1 << 17), D(1 << 20)
+    st = lambda mode=F32, G=4, M=8, N=8, K=8, a=A, lda=8, sa=64, b=B, ldb=8, sb=64, c=C, ldc=8, \
+        sc=64, w=W, n=wsb: L.desc_gemm_strided_batched(mode, G, M, N, K, a, lda, sa, b, ldb, sb,
+                                                       c, ldc, sc, w, n, None)
+    assert st(mode=2) == -6                                      # FP8 is not offered here
+    assert st(G=-1) == SIZE and st(sa=-1) == SIZE
+    assert st(G=0, a=None) == 0 and st(M=0, a=None) == 0         # nothing to do
+    assert st(c=None) == NULL and st(a=None) == NULL and st(w=None) == NULL
+    assert st(K=0, a=None, b=None, n=0) == WS                    # K = 0 needs no operands
+    assert st(lda=7) == SIZE and st(ldc=7) == SIZE
+    assert st(a=HOSTP) == HOST and st(w=HOSTP) == HOST
+    assert st(a=D(2)) == ALIGN and st(w=D((1 << 20) + 64)) == ALIGN
+    assert st(c=D(100)) == ALIAS                                 # C overlaps A's batches
+    assert st(sc=63) == ALIAS                                    # two batches of C overlap
+    assert st(w=D((1 << 17) + 256)) == ALIAS                     # workspace overlaps C
+    assert st(n=wsb - 1) == WS
+
+
 @pytest.mark.parametrize("entry", ["desc_scan_i32", "desc_scan_exclusive_i32"])
 def test_scan_checks(fake_pointers, entry):
     L = fake_pointers

@@ -1,0 +1,102 @@
+"""Parity of the uniform batched forms with the oracle through the C ABI:
+row-by-row reduce and scan of a batch x len int32 matrix (the segmented
+oracle with offsets s * len, bit for bit), and the strided batched GEMM in
+the FP32 and split-BF16 modes (every entry of every batch within the
+componentwise bound, padded strides included)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2305_03448_amd as desc
+import workloads
+from gpu_util import bf16x3_bound, case, dev, needs_gpu, to_dev
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+SHAPES = [(1, 1), (3, 5), (1, 70000), (1000, 4097), (4096, 1000), (64, 65536 + 3), (7, 0)]
+
+
+def _offsets(B, L):
+    return np.arange(B + 1, dtype=np.int64) * L
+
+
+@pytest.mark.parametrize("B,L", SHAPES)
+def test_reduce_batched(B, L):
+    case(f"reduce_batched B={B} L={L}")
+    x = workloads.int_uniform(B * L, seed=500 + B % 31).reshape(B, L)
+    out = torch.full((B,), -7, dtype=torch.int64, device=dev())
+    desc.desc_reduce_batched_i32(to_dev(x), out)
+    want = oracle.reduce_segmented_i32(x.ravel(), _offsets(B, L))
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("B,L", SHAPES)
+def test_scan_batched(B, L):
+    case(f"scan_batched B={B} L={L}")
+    x = workloads.int_uniform(B * L, seed=600 + B % 37).reshape(B, L)
+    out = torch.full((B, L), -7, dtype=torch.int32, device=dev())
+    desc.desc_scan_batched_i32(to_dev(x), out)
+    want = oracle.scan_segmented_i32(x.ravel(), _offsets(B, L)).reshape(B, L)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_batched_unaligned_and_workspace_reuse():
+    ws = torch.zeros(desc.desc_scan_batched_i32_workspace(300, 4099), dtype=torch.uint8,
+                     device=dev())
+    for rep, (B, L, off) in enumerate([(300, 4099, 1), (5, 3, 3), (299, 4097, 2), (300, 4099, 0)]):
+        case(f"batched reuse rep {rep} B={B} L={L} offset={off}")
+        x = workloads.int_uniform(B * L, seed=700 + rep).reshape(B, L)
+        xt = to_dev(x, off)
+        y = torch.empty((B, L), dtype=torch.int32, device=dev())
+        desc.desc_scan_batched_i32(xt, y, ws=ws)
+        assert np.array_equal(y.cpu().numpy(),
+                              oracle.scan_segmented_i32(x.ravel(), _offsets(B, L)).reshape(B, L))
+        r = torch.empty(B, dtype=torch.int64, device=dev())
+        desc.desc_reduce_batched_i32(xt, r, ws=ws)
+        assert np.array_equal(r.cpu().numpy(), oracle.reduce_segmented_i32(x.ravel(),
+                                                                           _offsets(B, L)))
+
+
+def _gemm_case(G, M, N, K, pad, seed, mode):
+    g = workloads.rng(seed)
+    A = g.standard_normal((G, M, K)).astype(np.float32)
+    B = g.standard_normal((G, K, N)).astype(np.float32)
+    # padded rows and batches: lda = K + pad, batch stride = M * lda + 5 * pad
+    def padded(X):
+        Gx, R, Cc = X.shape
+        buf = torch.zeros(Gx * (R * (Cc + pad) + 5 * pad) + 8, dtype=torch.float32, device=dev())
+        v = buf.as_strided((Gx, R, Cc), (R * (Cc + pad) + 5 * pad, Cc + pad, 1))
+        v.copy_(torch.from_numpy(X))
+        return v
+    At, Bt = padded(A), padded(B)
+    Ct = padded(np.full((G, M, N), np.nan, np.float32))
+    desc.desc_gemm_strided_batched(At, Bt, Ct, mode=mode)
+    C = Ct.cpu().numpy()
+    worst = 0.0
+    for b in range(G):
+        ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+        R, D = oracle.gemm_ref_sampled(A[b], B[b], ii.ravel(), jj.ravel())
+        worst = max(worst, float((np.abs(C[b].ravel() - R) / np.maximum(D, 1e-300)).max()))
+    return worst
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+@pytest.mark.parametrize("G,M,N,K,pad", [(1, 64, 64, 64, 0), (8, 200, 136, 260, 3),
+                                         (33, 96, 64, 128, 0), (4, 130, 257, 1, 1),
+                                         (3, 17, 9, 700, 5)])
+def test_gemm_strided_batched(mode, G, M, N, K, pad):
+    case(f"gemm_strided_batched {mode} G={G} {M}x{N}x{K} pad={pad}")
+    worst = _gemm_case(G, M, N, K, pad, seed=800 + G, mode=mode)
+    tol = 1e-5 if (mode == "f32" or K >= 64) else bf16x3_bound(K)
+    print(f"[result] strided batched {mode} worst {worst:.3e}")
+    assert worst <= tol
+
+
+def test_gemm_strided_batched_k0_writes_zeros():
+    case("gemm_strided_batched K=0")
+    A = torch.empty((3, 5, 0), dtype=torch.float32, device=dev())
+    B = torch.empty((3, 0, 7), dtype=torch.float32, device=dev())
+    C = torch.full((3, 5, 7), float("nan"), dtype=torch.float32, device=dev())
+    desc.desc_gemm_strided_batched(A, B, C)
+    assert torch.count_nonzero(C).item() == 0
