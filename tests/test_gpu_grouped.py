@@ -273,8 +273,10 @@ def test_grouped_bf16x3_fused_routes_long_strides_through_planes(bf16_config):
     A2, B2 = _problems([(130, 90, 70)], 31)[0]
     C1 = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
     C2 = torch.full((130, 90), float("nan"), dtype=torch.float32, device=dev())
-    d = desc.grouped_descriptors([(to_dev(A1), Bbig[:, :N], C1), (to_dev(A2), to_dev(B2), C2)],
-                                 dev())
+    # the operands stay referenced until the call has finished: the
+    # descriptors hold raw addresses, and freed blocks can become the workspace
+    ops = [(to_dev(A1), Bbig[:, :N], C1), (to_dev(A2), to_dev(B2), C2)]
+    d = desc.grouped_descriptors(ops, dev())
     desc.desc_gemm_grouped(d, mode="bf16x3")
     torch.cuda.synchronize()
     frac, _ = _check_all([(A1, B1), (A2, B2)], [C1.cpu().numpy(), C2.cpu().numpy()])
