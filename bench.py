@@ -87,6 +87,15 @@ class Timer:
         self.torch.cuda.synchronize()
         return sum(s.elapsed_time(e) for s, e in self.pairs) / max(1, len(self.pairs))
 
+    def spread_us(self):
+        """p10, median and p90 of the launch durations, in microseconds."""
+        self.torch.cuda.synchronize()
+        d = sorted(s.elapsed_time(e) * 1e3 for s, e in self.pairs)
+        if not d:
+            return {}
+        pick = lambda q: round(d[min(len(d) - 1, int(q * (len(d) - 1) + 0.5))], 2)
+        return {"p10_us": pick(0.1), "median_us": pick(0.5), "p90_us": pick(0.9)}
+
 
 def graph_time_ms(torch, fn, reps: int = 50, warm: int = 3) -> float:
     """Mean time of fn() from a HIP graph holding `reps` back-to-back calls."""
@@ -575,9 +584,11 @@ def main(argv=None):
                      "bytes_per_launch": SCAN_BYTES, "launch_us": round(scan_ms * 1e3, 2),
                      "traffic": traffic},
         "ops": {"scan_2^28": {"us": round(scan_ms * 1e3, 2), "GBs": round(scan_gbs, 1),
-                              "frac": round(scan_gbs / HBM_PEAK_GBS, 4), "check": ok_scan},
+                              "frac": round(scan_gbs / HBM_PEAK_GBS, 4), "check": ok_scan,
+                              **t_scan.spread_us()},
                 "transpose_8192": {"us": round(tr_ms * 1e3, 2), "GBs": round(tr_gbs, 1),
-                                   "frac": round(tr_gbs / HBM_PEAK_GBS, 4), "check": ok_tr}},
+                                   "frac": round(tr_gbs / HBM_PEAK_GBS, 4), "check": ok_tr,
+                                   **t_tr.spread_us()}},
     }
     extra = [o for o in args.ops.split(",") if o]
     if extra:
