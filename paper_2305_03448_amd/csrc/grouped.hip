@@ -7,10 +7,10 @@
 //
 //   plan kernel (one block): gives each problem a tile shape (128 x 128 when
 //     both M and N are at least 256, else 64 x 64; or 64 x 64 throughout, by
-//     the tuning table), orders the problems with
-//     the large tiles first (so the long tiles start early and the short ones
-//     fill in at the end), and writes the exclusive prefix of tile counts in
-//     that order with the total to the workspace.
+//     the tuning table), orders the problems longest tiles first -- the
+//     large tiles, then by K in buckets of 64 -- so that the long tiles start
+//     early and the short ones fill in at the end, and writes the exclusive
+//     prefix of tile counts in that order with the total to the workspace.
 //   main kernel: a grid of as many blocks as fit on the device at once walks
 //     the global tile sequence, runs of 64 consecutive tiles per XCD so that
 //     a problem's tiles share one L2; a binary search over the prefix finds
@@ -96,6 +96,15 @@ __device__ __forceinline__ idx_t wave_owner(const int64_t* start, int64_t G, int
   return lo;
 }
 
+// Sort key of the planned order: 0 .. kKBuckets-1 for large-tile problems,
+// kKBuckets .. 2 kKBuckets-1 for the others, K descending in buckets of 64.
+constexpr int kKBuckets = 16;
+__device__ __forceinline__ int plan_key(const desc_gemm_problem& p, bool big) {
+  const int64_t kb = p.K <= 64 ? 0 : ((p.K - 1) / 64 < kKBuckets - 1 ? (p.K - 1) / 64
+                                                                       : kKBuckets - 1);
+  return (big ? 0 : kKBuckets) + (kKBuckets - 1 - (int)kb);
+}
+
 __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_problem* probs,
                                                               int64_t G, int64_t big_min,
                                                               int64_t* total,
@@ -107,25 +116,35 @@ __global__ __launch_bounds__(kBlock) void grouped_plan_kernel(const desc_gemm_pr
   auto ord = array(order, G);
   auto bg = array(big, G);
   auto ts = array(tile_start, G + 1);
-  // pass 1: stable partition, large-tile problems first
-  int64_t nbig = 0;
+  // pass 1: order the problems longest tiles first (a tile's time grows with
+  // its area and its K): large-tile problems, then small ones, each by K in
+  // buckets of 64, largest first.  A counting sort with LDS counters; the
+  // order within a bucket varies from run to run, which changes only which
+  // block computes a tile, never its arithmetic.
+  __shared__ int32_t s_pos[2 * kKBuckets];
+  if (thread.index() < 2 * kKBuckets) s_pos[thread.index()] = 0;
+  sync(thread);
   for (idx_t base = 0; base < G; base += kBlock) {
     const idx_t g = base + thread.index();
-    const bool b = g < G && is_big(pr[g], big_min);
-    if (g < G) bg[g] = b;
-    int64_t ex;
-    const int64_t tot = block_excl(b ? 1 : 0, &ex, lds);
-    if (b) ord[nbig + ex] = (int32_t)g;
-    nbig += tot;
+    if (g < G) {
+      const bool b = is_big(pr[g], big_min);
+      bg[g] = b;
+      atomicAdd(&s_pos[plan_key(pr[g], b)], 1);
+    }
   }
-  int64_t nsmall = 0;
+  sync(thread);
+  if (thread.index() == 0) {
+    int32_t at = 0;
+    for (int k = 0; k < 2 * kKBuckets; ++k) {
+      const int32_t c = s_pos[k];
+      s_pos[k] = at;
+      at += c;
+    }
+  }
+  sync(thread);
   for (idx_t base = 0; base < G; base += kBlock) {
     const idx_t g = base + thread.index();
-    const bool s = g < G && !is_big(pr[g], big_min);
-    int64_t ex;
-    const int64_t tot = block_excl(s ? 1 : 0, &ex, lds);
-    if (s) ord[nbig + nsmall + ex] = (int32_t)g;
-    nsmall += tot;
+    if (g < G) ord[atomicAdd(&s_pos[plan_key(pr[g], is_big(pr[g], big_min))], 1)] = (int32_t)g;
   }
   sync(thread);
   // pass 2: tile prefix in planned order

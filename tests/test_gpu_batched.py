@@ -93,10 +93,11 @@ def test_gemm_strided_batched(mode, G, M, N, K, pad):
     assert worst <= tol
 
 
-def test_gemm_strided_batched_k0_writes_zeros():
-    case("gemm_strided_batched K=0")
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_gemm_strided_batched_k0_writes_zeros(mode):
+    case(f"gemm_strided_batched K=0 {mode}")
     A = torch.empty((3, 5, 0), dtype=torch.float32, device=dev())
     B = torch.empty((3, 0, 7), dtype=torch.float32, device=dev())
     C = torch.full((3, 5, 7), float("nan"), dtype=torch.float32, device=dev())
-    desc.desc_gemm_strided_batched(A, B, C)
+    desc.desc_gemm_strided_batched(A, B, C, mode=mode)
     assert torch.count_nonzero(C).item() == 0
