@@ -332,12 +332,13 @@ struct Bf16Ws {
   int64_t* nt_start;     // [G + 1]
   int64_t* split_start;  // [G + 1]
   int64_t* plane_off;    // [G]
-  int64_t* fused_start;  // [G + 1]
+  int64_t* fused_start;  // [G + 1], over the fused order's slots
+  int32_t* fused_order;  // [G] problem of each slot, longest tiles first
   uint8_t* planes;
   int64_t planes_bytes;  // room for the planes
 };
-size_t bf16_head_bytes(int64_t G) {
-  return 256 + 4 * (((G + 1) * 8 + 255) & ~(size_t)255);   // planes start 256-byte aligned
+size_t bf16_head_bytes(int64_t G) {   // planes start 256-byte aligned
+  return 256 + 4 * (((G + 1) * 8 + 255) & ~(size_t)255) + ((G * 4 + 255) & ~(size_t)255);
 }
 Bf16Ws bf16_carve(void* ws, size_t ws_bytes, int64_t G) {
   uint8_t* w = (uint8_t*)ws;
@@ -349,6 +350,7 @@ Bf16Ws bf16_carve(void* ws, size_t ws_bytes, int64_t G) {
   r.split_start = (int64_t*)(w + 256 + arr);
   r.plane_off = (int64_t*)(w + 256 + 2 * arr);
   r.fused_start = (int64_t*)(w + 256 + 3 * arr);
+  r.fused_order = (int32_t*)(w + 256 + 4 * arr);
   r.planes = w + bf16_head_bytes(G);
   r.planes_bytes = (int64_t)ws_bytes - (int64_t)bf16_head_bytes(G);
   return r;
@@ -405,13 +407,63 @@ __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_probl
       nts[g] = c_nt + e_nt;
       sps[g] = c_sp + e_sp;
       pof[g] = c_pl + e_pl;
-      fts[g] = c_ft + e_ft;
     }
     c_nt += t_nt;
     c_sp += t_sp;
     c_ft += t_ft;
     // at most 256 * 2^44 bytes per round: held below 2^60, no overflow
     c_pl = c_pl + t_pl < (int64_t(1) << 60) ? c_pl + t_pl : (int64_t(1) << 60);
+  }
+  // The fused tiles in the order of the FP32 plan (longest tiles first: the
+  // large edge, then K descending), by a counting sort on LDS counters; the
+  // order within a bucket varies from run to run, which changes only which
+  // block computes a tile.  Problems that take no fused tiles keep a slot
+  // with an empty range.
+  __shared__ int32_t s_pos[2 * kKBuckets];
+  auto ford = array(w.fused_order, G);
+  if (thread.index() < 2 * kKBuckets) s_pos[thread.index()] = 0;
+  sync(thread);
+  for (idx_t base = 0; base < G; base += kBlock) {
+    const idx_t g = base + thread.index();
+    if (g < G) {
+      const desc_gemm_problem p = pr[g];
+      atomicAdd(&s_pos[plan_key(p, tile_edge<kCfg>(p.M, p.N) == kPadBig)], 1);
+    }
+  }
+  sync(thread);
+  if (thread.index() == 0) {
+    int32_t at = 0;
+    for (int k = 0; k < 2 * kKBuckets; ++k) {
+      const int32_t c = s_pos[k];
+      s_pos[k] = at;
+      at += c;
+    }
+  }
+  sync(thread);
+  for (idx_t base = 0; base < G; base += kBlock) {
+    const idx_t g = base + thread.index();
+    if (g < G) {
+      const desc_gemm_problem p = pr[g];
+      ford[atomicAdd(&s_pos[plan_key(p, tile_edge<kCfg>(p.M, p.N) == kPadBig)], 1)] = (int32_t)g;
+    }
+  }
+  sync(thread);
+  int64_t c_slot = 0;
+  for (idx_t base = 0; base < G; base += kBlock) {
+    const idx_t i = base + thread.index();
+    int64_t ft = 0;
+    if (i < G) {
+      const desc_gemm_problem p = pr[ford[i]];
+      const Bf16Dims d = bf16_dims(p.M, p.N, p.K);
+      if (!d.empty && !d.huge && fused_for<kCfg>(p)) {
+        const int64_t e = tile_edge<kCfg>(p.M, p.N);
+        ft = (round_up(p.M, e) / e) * (round_up(p.N, e) / e);
+      }
+    }
+    int64_t e_ft;
+    const int64_t t_ft = block_excl(ft, &e_ft, lds);
+    if (i < G) fts[i] = c_slot + e_ft;
+    c_slot += t_ft;
   }
   if (thread.index() == 0) {
     const bool fits = c_huge == 0 && c_pl <= w.planes_bytes;
@@ -581,14 +633,15 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
   for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
     const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
     if (t >= T) break;
-    if (thread.index() < kWave) {
-      const idx_t g = wave_owner(w.fused_start, G, t);
-      if (thread.index() == 0) s_g = g;
+    if (thread.index() < kWave) {   // the slot of tile t in the fused order
+      const idx_t slot = wave_owner(w.fused_start, G, t);
+      if (thread.index() == 0) s_g = slot;
     }
     sync(thread);
-    const idx_t g = wave::uniform_i64(s_g);
+    const idx_t slot = wave::uniform_i64(s_g);
+    const idx_t g = array(w.fused_order, G)[slot];
     const desc_gemm_problem p = array(probs, G)[g];
-    const idx_t local = t - array(w.fused_start, G + 1)[g];
+    const idx_t local = t - array(w.fused_start, G + 1)[slot];
     constexpr int64_t e = kSmallOnly<kCfg> ? kPad : kPadBig;
     const idx_t tn = round_up(p.N, e) / e;
     const idx_t tm = wave::uniform_i64(local / tn), tc = wave::uniform_i64(local % tn);

@@ -305,13 +305,14 @@ def _problems_host_ld(rows):
 def test_grouped_workspace_for():
     L = desc.lib()
     F32, BF16X3, FP8 = 0, 1, 2
-    # bf16x3: a head of 256 bytes + four 256-aligned arrays of G + 1 int64,
+    # bf16x3: a head of 256 bytes + four 256-aligned arrays of G + 1 int64 +
+    # one 256-aligned array of G int32 (the fused order),
     # then, for each problem staged through planes, four bf16 planes
     # (Ma + Na) x Kp with M, N rounded up to multiples of 128 (either tile
     # size fits) and K to a multiple of 64 (at least 64); empty problems
     # take nothing
     shapes = [(100, 90, 80), (0, 5, 5), (5, 7, 0), (64, 64, 64), (1, 1, 1000)]
-    head = 256 + 4 * 256
+    head = 256 + 4 * 256 + 256
     planes = [4 * (128 + 128) * 128, 0, 4 * (128 + 128) * 64, 4 * (128 + 128) * 64,
               4 * (128 + 128) * 1024]
     op = desc.OPS["gemm_grouped_bf16x3"]
@@ -330,10 +331,10 @@ def test_grouped_workspace_for():
                 head + 2 * planes[0]
     finally:
         L.desc_config_set(op, 0, -1)
-    assert L.desc_gemm_grouped_workspace_for(BF16X3, 0, None) == head
-    big_G = 100                                   # (101 * 8) rounded to 256 = 1024
+    assert L.desc_gemm_grouped_workspace_for(BF16X3, 0, None) == 256 + 4 * 256
+    big_G = 100                      # (101 * 8) rounded to 256 = 1024; 400 rounded = 512
     assert L.desc_gemm_grouped_workspace_for(BF16X3, big_G, _problems_host(
-        [(0, 0, 0)] * big_G)) == 256 + 4 * 1024
+        [(0, 0, 0)] * big_G)) == 256 + 4 * 1024 + 512
     assert L.desc_gemm_grouped_workspace_for(F32, 7, None) == L.desc_gemm_grouped_workspace(7)
     assert L.desc_gemm_grouped_workspace_for(FP8, 1, _problems_host(shapes[:1])) == 0
     assert L.desc_gemm_grouped_workspace_for(BF16X3, -1, None) == 0
