@@ -267,7 +267,9 @@ __global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restri
                                                         uint32_t* __restrict__ out, int64_t rows,
                                                         int64_t cols) {
   __shared__ uint32_t lds[kT * kPitch];
-  const int64_t bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z, tid = threadIdx.x;
+  // column tiles in diagonal order, as in the library's kernel
+  const int64_t bx = ((int64_t)blockIdx.x + blockIdx.y) % gridDim.x, by = blockIdx.y,
+                bz = blockIdx.z, tid = threadIdx.x;
   const bool full = kVec && (by + 1) * kT <= rows && (bx + 1) * kT <= cols;
   if (full) {
     const int64_t y = tid / kTX, x = tid % kTX, c4 = cols / 4, r4 = rows / 4;
