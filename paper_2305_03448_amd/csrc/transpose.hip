@@ -37,16 +37,23 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <int kT, bool kNt>
-struct TransposeCfg {
+template <int kT, bool kNt, int kThreads>
+struct TransposeShape {
+  static constexpr int block = kThreads;     // threads per block
   static constexpr int t = kT;               // tile edge (words)
   static constexpr int pitch = kT + 1;       // LDS row pitch (words)
   static constexpr int tx = kT / 4;          // threads along a row (16 bytes each)
-  static constexpr int ty = kBlock / tx;     // threads along a column
+  static constexpr int ty = kThreads / tx;   // threads along a column
   static constexpr int items = kT / ty;      // rows per thread
   static constexpr bool nt = kNt;
   static_assert(ty * items == kT, "tile rows must divide among the thread rows");
 };
+// 256 threads per block, and 512 (twice the waves per tile, half the rows
+// per thread).
+template <int kT, bool kNt>
+struct TransposeCfg : TransposeShape<kT, kNt, kBlock> {};
+template <int kT, bool kNt>
+struct TransposeCfg512 : TransposeShape<kT, kNt, 512> {};
 
 template <bool kNt, class T>
 __device__ __forceinline__ T load16(const T* p) {
@@ -60,7 +67,7 @@ __device__ __forceinline__ void store16(T v, T* p) {
 }
 
 template <class C, bool kVec>
-__global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __restrict__ in,
+__global__ __launch_bounds__(C::block) void transpose32_kernel(const uint32_t* __restrict__ in,
                                                              uint32_t* __restrict__ out,
                                                              int64_t rows, int64_t cols) {
   constexpr int T = C::t, TY = C::ty, TX = C::tx, IT = C::items;
@@ -70,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __r
   // over the matrix rather than rows a power-of-two stride apart.
   const Block bx{((idx_t)blockIdx.x + (idx_t)blockIdx.y) % (idx_t)gridDim.x, (idx_t)gridDim.x};
   auto by = block_y();   // row tile of the input
-  auto thread = thread_x<kBlock>();
+  auto thread = thread_x<C::block>();
   const Block bz{(idx_t)blockIdx.z, (idx_t)gridDim.z};   // matrix of the batch
 
   // The LDS tile as [T][T+1] words with the padding column split off.
@@ -109,12 +116,12 @@ __global__ __launch_bounds__(kBlock) void transpose32_kernel(const uint32_t* __r
     auto a = matrices(in, bz.count(), rows, cols).select(bz);
     auto b = matrices(out, bz.count(), cols, rows).select(bz);
     const idx_t r0 = by.index() * T, c0 = bx.index() * T;
-    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+    for (idx_t e = thread.index(); e < T * T; e += C::block) {
       const idx_t r = e / T, c = e % T;
       if (r0 + r < rows && c0 + c < cols) tile.at(r, c) = a.at(r0 + r, c0 + c);
     }
     sync(thread);
-    for (idx_t e = thread.index(); e < T * T; e += kBlock) {
+    for (idx_t e = thread.index(); e < T * T; e += C::block) {
       const idx_t c = e / T, r = e % T;
       if (r0 + r < rows && c0 + c < cols) b.at(c0 + c, r0 + r) = tile.at(r, c);
     }
@@ -129,10 +136,10 @@ hipError_t launch_transpose(const uint32_t* in, uint32_t* out, int64_t batch, in
                   (unsigned)batch);
   const bool vec = rows % 4 == 0 && cols % 4 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
   if (vec)
-    hipLaunchKernelGGL((transpose32_kernel<C, true>), grid, dim3(kBlock), 0, s, in, out, rows,
+    hipLaunchKernelGGL((transpose32_kernel<C, true>), grid, dim3(C::block), 0, s, in, out, rows,
                        cols);
   else
-    hipLaunchKernelGGL((transpose32_kernel<C, false>), grid, dim3(kBlock), 0, s, in, out, rows,
+    hipLaunchKernelGGL((transpose32_kernel<C, false>), grid, dim3(C::block), 0, s, in, out, rows,
                        cols);
   return hipGetLastError();
 }
@@ -243,10 +250,11 @@ hipError_t launch_transpose_elem(const void* in, void* out, int64_t batch, int64
   return hipGetLastError();
 }
 
-constexpr const char* kNames[] = {"t64_nt", "t64", "t32_nt", "t32", "t128_nt", "t128"};
+constexpr const char* kNames[] = {"t64_nt", "t64", "t32_nt", "t32", "t128_nt", "t128",
+                                   "t128_nt_b512", "t128_b512"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kTranspose32, "transpose_32", 6, kNames, kDefaults), true);
+    (tune::register_op(tune::kTranspose32, "transpose_32", 8, kNames, kDefaults), true);
 
 }  // namespace
 
@@ -267,6 +275,8 @@ hipError_t transpose_32(const uint32_t* in, uint32_t* out, int64_t batch, int64_
     case 3: return launch_transpose<TransposeCfg<32, false>>(in, out, batch, rows, cols, s);
     case 4: return launch_transpose<TransposeCfg<128, true>>(in, out, batch, rows, cols, s);
     case 5: return launch_transpose<TransposeCfg<128, false>>(in, out, batch, rows, cols, s);
+    case 6: return launch_transpose<TransposeCfg512<128, true>>(in, out, batch, rows, cols, s);
+    case 7: return launch_transpose<TransposeCfg512<128, false>>(in, out, batch, rows, cols, s);
     default: return launch_transpose<TransposeCfg<64, true>>(in, out, batch, rows, cols, s);
   }
 }
