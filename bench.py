@@ -49,7 +49,7 @@ STEP_BYTES = SCAN_BYTES + TRANSPOSE_BYTES
 # each scaled by what the counter reads for the copy kernel of known size
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), taken for ScanCfg<1024, 16, true>;
 # None when the kernel has changed since the counters were taken.
-SCAN_TRAFFIC_BYTES = 2152132865
+SCAN_TRAFFIC_BYTES = 2152064430
 SCAN_TRAFFIC_CONFIG = "b1024_r16_nt"
 
 
