@@ -36,6 +36,7 @@
 // generation; the last block waits until both words of every slot carry the
 // current tag, and advances the generation when it is done.
 #include "common.hpp"
+#include "handover.hpp"
 #include "launch.hpp"
 #include "view.hpp"
 
@@ -49,8 +50,6 @@ constexpr int64_t kMaxBlocks = 2048;
 constexpr int kWaves = kBlock / kWave;
 
 typedef uint32_t u32x4u __attribute__((ext_vector_type(4))) __attribute__((aligned(4)));
-
-__device__ __forceinline__ uint32_t tag_of(uint32_t gen) { return 1u + gen % 0xFFFFFFFFu; }
 
 // FP64 sum of FP32 values, in the order stated above.
 struct SumF32 {
@@ -157,14 +156,13 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
   }
   const Acc mine = block_tree<Op>(acc, lds);   // (its barrier also publishes s_gen)
   const uint32_t gen = s_gen;
-  const uint64_t tag = (uint64_t)tag_of(gen) << 32;
+  const uint64_t tag = handover::tag_of(gen);
   auto slot = array(slots, 2 * block.count()).template group<2>();   // [G][2]
   const bool last = block.index() == block.count() - 1;
   if (!last) {
-    if (thread.index() == 0) {
-      store_status(&slot.idx(block.index())[0], tag | Op::half(mine, 0));
-      store_status(&slot.idx(block.index())[1], tag | Op::half(mine, 1));
-    }
+    if (thread.index() == 0)
+      handover::publish(&slot.idx(block.index())[0], tag,
+                        ((uint64_t)Op::half(mine, 1) << 32) | Op::half(mine, 0));
     return;
   }
 
@@ -174,21 +172,9 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
   for (idx_t b = thread.index(); b < block.count(); b += kBlock) {
     Acc v = mine;
     if (b != block.index()) {
-      uint32_t h[2];
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        uint64_t w = load_status(&slot.idx(b)[k]);
-        for (uint32_t polls = 0; (w & ~0xFFFFFFFFull) != tag; ++polls) {
-          if (polls == kSpinLimit) {     // inconsistent workspace
-            store_u32(&hdr->error, 1u);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-          w = load_status(&slot.idx(b)[k]);
-        }
-        h[k] = (uint32_t)w;
-      }
-      v = Op::from_halves(h[0], h[1]);
+      uint64_t w = 0;
+      if (!handover::poll(&slot.idx(b)[0], tag, w)) store_u32(&hdr->error, 1u);
+      v = Op::from_halves((uint32_t)w, (uint32_t)(w >> 32));
     }
     g = Op::join(g, v);
   }

@@ -39,6 +39,7 @@
 // order); the last tile advances the generation once everything before it
 // has published.
 #include "common.hpp"
+#include "handover.hpp"
 #include "launch.hpp"
 #include "layouts.hpp"
 #include "view.hpp"
@@ -52,8 +53,6 @@ constexpr int kWaves = kBlock / kWave;      // 16
 constexpr int kRounds = 16;
 constexpr int kTile = kWaves * kRounds * kWave * 4;   // 65536
 constexpr int kGroup = 64;                  // tiles per look-back group
-
-__device__ __forceinline__ uint32_t tag_of(uint32_t gen) { return 1u + gen % 0xFFFFFFFFu; }
 
 // A DPP move of an FP64 value (both halves with the same control); lanes
 // that receive nothing get +0.0.
@@ -93,25 +92,8 @@ __device__ __forceinline__ double lane_read_f64(double v, int lane) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ void publish(uint64_t* w, uint64_t tag, double v) {
-  const uint64_t u = (uint64_t)__double_as_longlong(v);
-  store_status(&w[0], tag | (u & 0xFFFFFFFFull));
-  store_status(&w[1], tag | (u >> 32));
-}
-
-// Waits until both words carry `tag`; false when the poll limit is reached.
-__device__ __forceinline__ bool poll(const uint64_t* w, uint64_t tag, double& v) {
-  uint64_t lo = load_status(&w[0]), hi = load_status(&w[1]);
-  for (uint32_t polls = 0; (lo & ~0xFFFFFFFFull) != tag || (hi & ~0xFFFFFFFFull) != tag;
-       ++polls) {
-    if (polls == kSpinLimit) return false;
-    __builtin_amdgcn_s_sleep(2);
-    lo = load_status(&w[0]);
-    hi = load_status(&w[1]);
-  }
-  v = __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-  return true;
-}
+__device__ __forceinline__ uint64_t bits(double v) { return (uint64_t)__double_as_longlong(v); }
+__device__ __forceinline__ double from_bits(uint64_t u) { return __longlong_as_double((long long)u); }
 
 // Marks the loaded values as changed, so that the compiler converts them to
 // FP64 again where they are used next instead of keeping 64 converted
@@ -187,24 +169,25 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
 
   // Wave 0: publish A_t, gather the group's earlier aggregates and Q_g.
   if (wv.index() == 0) {
-    const uint64_t tag = (uint64_t)tag_of(gen) << 32;
+    const uint64_t tag = handover::tag_of(gen);
     const idx_t g = tile / kGroup;
     const int p = (int)(tile % kGroup);
     auto ag = array(aggs, 2 * ntiles).group<2>();                         // [T][2]
     auto gq = array(groups, 2 * ((ntiles + kGroup - 1) / kGroup)).group<2>();
-    if (lane.index() == 0) publish(&ag.idx(tile)[0], tag, agg);
+    if (lane.index() == 0) handover::publish(&ag.idx(tile)[0], tag, bits(agg));
     bool ok = true;
-    double v = lane.index() == p ? agg : 0.0;
-    if (lane.index() < p) ok = poll(&ag.idx(g * kGroup + lane.index())[0], tag, v);
-    double q = 0.0;
-    if (g > 0 && lane.index() == 0) ok = poll(&gq.idx(g - 1)[0], tag, q) && ok;
+    uint64_t vb = bits(lane.index() == p ? agg : 0.0), qb = bits(0.0);
+    if (lane.index() < p) ok = handover::poll(&ag.idx(g * kGroup + lane.index())[0], tag, vb);
+    if (g > 0 && lane.index() == 0) ok = handover::poll(&gq.idx(g - 1)[0], tag, qb) && ok;
+    const double v = from_bits(vb);
+    double q = from_bits(qb);
     if (__ballot(!ok) != 0 && lane.index() == 0) store_u32(&hdr->error, 1u);
     q = lane_read_f64(q, 0);
     const double e = wave_sum_f64(lane.index() < p ? v : 0.0);
     const double carry = q + e;
     if (p == kGroup - 1) {
       const double s = wave_sum_f64(v);
-      if (lane.index() == 0) publish(&gq.idx(g)[0], tag, q + s);
+      if (lane.index() == 0) handover::publish(&gq.idx(g)[0], tag, bits(q + s));
     }
     if (lane.index() == 0) {
       sl.carry = carry;
