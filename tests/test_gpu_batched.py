@@ -101,3 +101,46 @@ def test_gemm_strided_batched_k0_writes_zeros(mode):
     C = torch.full((3, 5, 7), float("nan"), dtype=torch.float32, device=dev())
     desc.desc_gemm_strided_batched(A, B, C, mode=mode)
     assert torch.count_nonzero(C).item() == 0
+
+
+def test_batched_graph_replay():
+    # the three batched forms (each a description kernel plus the segmented
+    # or grouped kernels) captured into one HIP graph and replayed
+    B, L = 300, 4099
+    x = workloads.int_uniform(B * L, seed=95).reshape(B, L)
+    xt = to_dev(x)
+    r = torch.empty(B, dtype=torch.int64, device=dev())
+    y = torch.empty((B, L), dtype=torch.int32, device=dev())
+    wr = torch.zeros(desc.desc_reduce_batched_i32_workspace(B, L), dtype=torch.uint8, device=dev())
+    wy = torch.zeros(desc.desc_scan_batched_i32_workspace(B, L), dtype=torch.uint8, device=dev())
+    G, M, N, K = 6, 96, 80, 70
+    g_ = workloads.rng(96)
+    A = g_.standard_normal((G, M, K)).astype(np.float32)
+    Bm = g_.standard_normal((G, K, N)).astype(np.float32)
+    At, Bt = to_dev(A), to_dev(Bm)
+    C = torch.empty((G, M, N), dtype=torch.float32, device=dev())
+    wg = torch.zeros(desc.desc_gemm_strided_batched_workspace("f32", G, M, N, K, K, N),
+                     dtype=torch.uint8, device=dev())
+    case("batched eager before capture")
+    desc.desc_reduce_batched_i32(xt, r, ws=wr)
+    desc.desc_scan_batched_i32(xt, y, ws=wy)
+    desc.desc_gemm_strided_batched(At, Bt, C, ws=wg)
+    torch.cuda.synchronize()
+    want_r, want_y, want_c = r.cpu().numpy(), y.cpu().numpy(), C.cpu().numpy().view(np.uint32)
+    assert np.array_equal(want_r, oracle.reduce_segmented_i32(x.ravel(), _offsets(B, L)))
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        desc.desc_reduce_batched_i32(xt, r, ws=wr)
+        desc.desc_scan_batched_i32(xt, y, ws=wy)
+        desc.desc_gemm_strided_batched(At, Bt, C, ws=wg)
+    for rep in range(3):
+        case(f"batched graph replay {rep}")
+        r.fill_(-1); y.fill_(-1); C.fill_(float("nan"))
+        desc.desc_reduce_batched_i32(xt[:5], torch.empty(5, dtype=torch.int64, device=dev()))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(r.cpu().numpy(), want_r)
+        assert np.array_equal(y.cpu().numpy(), want_y)
+        assert np.array_equal(C.cpu().numpy().view(np.uint32), want_c)

@@ -164,3 +164,37 @@ def test_reduce_ops_workload_2_28():
     assert _bits(_sum(xt)) == _bits(got)
     assert abs(got - oracle.sum_f32(xf)) <= _bound(xf)
     assert _bits(got) == _bits(fixed_order_sum(xf))
+
+
+def test_reduce_ops_graph_replay():
+    # min/max and the float sum captured into one HIP graph; each replay,
+    # with eager calls on other workspaces in between, gives the eager bits
+    n = (1 << 22) + 5
+    xf = workloads.wide_f32(n, seed=90)
+    xi = workloads.int_uniform(n, seed=91, lo=-(1 << 31), hi=(1 << 31) - 1)
+    xft, xit = to_dev(xf), to_dev(xi)
+    ws = torch.zeros(desc.desc_reduce_op_workspace(n), dtype=torch.uint8, device=dev())
+    s = torch.empty(1, dtype=torch.float64, device=dev())
+    m = torch.empty(2, dtype=torch.int32, device=dev())
+    case("reduce ops eager before capture")
+    desc.desc_reduce_sum_f32(xft, s, ws=ws)
+    desc.desc_reduce_minmax_i32(xit, m, ws=ws)
+    want_s, want_m = _bits(float(s.item())), tuple(m.cpu().tolist())
+    assert want_s == _bits(fixed_order_sum(xf)) and want_m == oracle.minmax_i32(xi)
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        desc.desc_reduce_sum_f32(xft, s, ws=ws)
+        desc.desc_reduce_minmax_i32(xit, m, ws=ws)
+    other = torch.zeros(desc.desc_reduce_op_workspace(4097), dtype=torch.uint8, device=dev())
+    y = to_dev(workloads.wide_f32(4097, seed=92))
+    for rep in range(3):
+        case(f"reduce ops graph replay {rep}")
+        s.fill_(-1.0); m.fill_(7)
+        desc.desc_reduce_sum_f32(y, torch.empty(1, dtype=torch.float64, device=dev()), ws=other)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert _bits(float(s.item())) == want_s
+        assert tuple(m.cpu().tolist()) == want_m

@@ -138,3 +138,32 @@ def test_scan_f32_workload_2_28_sampled():
     out2 = torch.empty_like(xt)
     desc.desc_scan_f32(xt, out2)
     assert torch.equal(out.view(torch.int32), out2.view(torch.int32))
+
+
+def test_scan_f32_graph_replay():
+    # the float scan captured into a HIP graph: every replay, with eager
+    # scans on another workspace in between, gives the eager bits
+    n = 3 * 65536 + 11
+    x = workloads.wide_f32(n, seed=93)
+    xt = to_dev(x)
+    ws = torch.zeros(desc.desc_scan_f32_workspace(n), dtype=torch.uint8, device=dev())
+    y = torch.empty_like(xt)
+    case("scan_f32 eager before capture")
+    desc.desc_scan_f32(xt, y, ws=ws)
+    want = y.cpu().numpy().view(np.uint32).copy()
+    _check(x, y.cpu().numpy())
+    stream = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        desc.desc_scan_f32(xt, y, ws=ws)
+    other = torch.zeros(desc.desc_scan_f32_workspace(70000), dtype=torch.uint8, device=dev())
+    z = to_dev(workloads.wide_f32(70000, seed=94))
+    for rep in range(3):
+        case(f"scan_f32 graph replay {rep}")
+        y.fill_(float("nan"))
+        desc.desc_scan_f32(z, torch.empty_like(z), ws=other)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), want)
