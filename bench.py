@@ -307,7 +307,8 @@ def op_copy(desc, torch):
 
 def op_reduce(desc, torch, workloads):
     """Reduction of 2^22 int32 (seed 1): L2/MALL-resident (warm) and after a
-    512 MiB write that evicts it (cold), both as graph replays."""
+    512 MiB write that evicts it (cold), both as graph replays; then a cold
+    sweep over 2^22 .. 2^28 elements."""
     x_np = workloads.int_uniform(1 << 22, seed=1)
     x = torch.from_numpy(x_np).cuda()
     out = torch.empty(1, dtype=torch.int64, device="cuda")
@@ -321,9 +322,25 @@ def op_reduce(desc, torch, workloads):
     torch.cuda.synchronize()
     ok = int(out.item()) == int(x_np.sum(dtype="int64"))
     nbytes = 4 * (1 << 22) + 8
+    # sweep: where the latency of one launch stops dominating (cold, after the flush)
+    sweep = []
+    for lg in (22, 24, 26, 28):
+        n = 1 << lg
+        xs_np = workloads.int_uniform(n, seed=1)
+        xs = torch.from_numpy(xs_np).cuda()
+        wss = torch.zeros(desc.desc_reduce_i32_workspace(n), dtype=torch.uint8, device="cuda")
+        t_both = graph_time_ms(torch, lambda: (flush.fill_(1),
+                                               desc.desc_reduce_i32(xs, out, ws=wss)), reps=10)
+        t = max(t_both - fl, 1e-6)
+        torch.cuda.synchronize()
+        sweep.append({"n": n, "cold_us": round(t * 1e3, 2),
+                      "cold_GBs": round((4 * n + 8) / t / 1e6, 1),
+                      "check": int(out.item()) == int(xs_np.sum(dtype="int64"))})
+        del xs, wss
     return {"n": 1 << 22, "bytes": nbytes, "check": ok,
             "warm_us": round(warm * 1e3, 2), "warm_GBs": round(nbytes / warm / 1e6, 1),
-            "cold_us": round(cold * 1e3, 2), "cold_GBs": round(nbytes / cold / 1e6, 1)}
+            "cold_us": round(cold * 1e3, 2), "cold_GBs": round(nbytes / cold / 1e6, 1),
+            "sweep_cold": sweep}
 
 
 def op_reduce_ops(desc, torch, workloads, oracle):
