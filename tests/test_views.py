@@ -30,6 +30,8 @@ EXPECTED = [
     "access_check_transpose_kernel_clean", "access_check_transpose_without_barrier_races",
     "access_check_reduce_tree_clean", "access_check_reduce_tree_without_barriers_races",
     "access_check_scan_stores_clean",
+    # layouts of the min/max and float-sum kernel and the transposes' tile order
+    "reduce_ops_chunk_groups_bijection", "transpose_diagonal_tile_order_bijection",
 ]
 
 

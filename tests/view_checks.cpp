@@ -493,5 +493,39 @@ int main(int argc, char** argv) {
     check(c.conflicts().empty() && c.accesses() == out.size(), "access_check_scan_stores_clean");
   }
 
+  // --- min/max and float-sum chunk layout: [chunks][4][256] groups of four --------
+  // Lane j of a block takes groups 256 u + j of a chunk (elements 1024 u + 4 j ..),
+  // u = 0..3; over the grid-strided chunks of G blocks every group is read once.
+  {
+    const int G = 3, chunks = 7, lanes = 256;
+    std::vector<int> a(chunks * 1024);    // groups
+    Access acc(chunks * 1024);
+    bool order = true;
+    for (int b = 0; b < G; ++b)
+      for (int c = b; c < chunks; c += G)
+        for (int j = 0; j < lanes; ++j) {
+          auto v = array(a.data(), chunks * 1024).group<256>().group<4>().idx(c).transpose().select(
+              R<Level::Thread>(j, lanes));
+          for (int u = 0; u < 4; ++u) {
+            const long g = &v[u] - a.data();
+            order &= g == c * 1024L + 256 * u + j;
+            acc.add(g, b * lanes + j);
+          }
+        }
+    check(order && acc.bijection(), "reduce_ops_chunk_groups_bijection");
+  }
+
+  // --- transpose tiles in diagonal order: block (x, y) -> tile ((x + y) mod X, y) ---
+  {
+    bool ok = true;
+    for (const auto& gxy : std::vector<std::pair<int, int>>{{64, 128}, {64, 64}, {5, 3}, {1, 9}}) {
+      Access acc(gxy.first * gxy.second);
+      for (int y = 0; y < gxy.second; ++y)
+        for (int x = 0; x < gxy.first; ++x) acc.add(((x + y) % gxy.first) + gxy.first * y, x + gxy.first * y);
+      ok &= acc.bijection();
+    }
+    check(ok, "transpose_diagonal_tile_order_bijection");
+  }
+
   return g_fail;
 }
