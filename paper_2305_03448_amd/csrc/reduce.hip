@@ -30,9 +30,12 @@ namespace desc {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kUnroll = 4;                        // int32x4 per lane per tile
-constexpr int kTileVec = kBlock * kUnroll;        // int32x4 per tile
-constexpr int kTile = kTileVec * 4;               // int32 per tile
+// A tile is [kU][kBlock] int32x4: kU 16-byte loads per lane, all in flight at
+// once.  kU = 4 (4096 elements) is the streaming shape; kU = 16 (16384) gives
+// a quarter of the blocks, for sizes where dispatch and the final gather, not
+// the stream, set the time.
+constexpr int kMinU = 4;
+constexpr int kTile = kBlock * kMinU * 4;         // int32 per tile of the smallest shape
 
 constexpr int kValueBits = 51;
 constexpr uint64_t kValueMask = (1ull << kValueBits) - 1;
@@ -61,6 +64,7 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
 
 // body: the 16-byte-aligned middle of the input as ntiles full tiles;
 // edge: the remaining scalars (head and tail), summed by the last block.
+template <int kU>
 __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
     const i32x4* __restrict__ body, int64_t ntiles, const int32_t* __restrict__ head,
     int64_t nhead, const int32_t* __restrict__ tail, int64_t ntail, int64_t* __restrict__ out,
@@ -71,16 +75,16 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
   auto thread = thread_x<kBlock>();
   if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
 
-  auto vecs = array(body, ntiles * kTileVec);   // [tiles][kUnroll][kBlock] int32x4
+  auto vecs = array(body, ntiles * (kBlock * kU));   // [tiles][kU][kBlock] int32x4
 
   int64_t acc = 0;
   for (idx_t t = block.index(); t < ntiles; t += block.count()) {
-    auto mine = layout::block_striped<kBlock, kUnroll>(vecs, t, thread);   // [kUnroll]
-    i32x4 q[kUnroll];
+    auto mine = layout::block_striped<kBlock, kU>(vecs, t, thread);   // [kU]
+    i32x4 q[kU];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) q[u] = __builtin_nontemporal_load(&mine[u]);
+    for (int u = 0; u < kU; ++u) q[u] = __builtin_nontemporal_load(&mine[u]);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < kU; ++u)
       acc += (int64_t)q[u].x + (int64_t)q[u].y + (int64_t)q[u].z + (int64_t)q[u].w;
   }
   const bool last = block.index() == block.count() - 1;
@@ -121,19 +125,20 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
   }
 }
 
-constexpr const char* kNames[] = {"b256_u4_nt"};
+constexpr const char* kNames[] = {"b256_u4_nt", "b256_u16_nt"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kReduceI32, "reduce_i32", 1, kNames, kDefaults), true);
+    (tune::register_op(tune::kReduceI32, "reduce_i32", 2, kNames, kDefaults), true);
 
 }  // namespace
 
 namespace launch {
 
-// Grid: one block per tile up to kReduceMaxBlocks, more when needed to keep
-// a block's share at most 2^19 elements.
-static int64_t reduce_grid(int64_t n) {
-  const int64_t ntiles = n / kTile;
+// Grid: one block per tile (of `tile` elements) up to kReduceMaxBlocks, more
+// when needed to keep a block's share at most 2^19 elements.  The smallest
+// tile gives the largest grid, which sizes the workspace.
+static int64_t reduce_grid(int64_t n, int64_t tile = kTile) {
+  const int64_t ntiles = n / tile;
   int64_t grid = ntiles < kReduceMaxBlocks ? ntiles : kReduceMaxBlocks;
   const int64_t need = (n + (1 << 19) - 1) >> 19;
   if (grid < need) grid = need;
@@ -144,22 +149,31 @@ size_t reduce_i32_workspace(int64_t n) {
   return sizeof(WsHeader) + sizeof(uint64_t) * (size_t)reduce_grid(n < 0 ? 0 : n);
 }
 
-hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipStream_t s) {
+template <int kU>
+static hipError_t launch_reduce(const int32_t* in, int64_t n, int64_t* out, void* ws,
+                                hipStream_t s) {
+  constexpr int64_t tile = (int64_t)kBlock * kU * 4;
   // Split the input at the first 16-byte boundary and after the last full tile.
   const uintptr_t addr = (uintptr_t)in;
   int64_t nhead = (int64_t)(((16 - (addr & 15)) & 15) / 4);
   if (nhead > n) nhead = n;
   const int64_t rest = n - nhead;
-  const int64_t ntiles = rest / kTile;
-  const int64_t ntail = rest - ntiles * kTile;
-  const int64_t grid = reduce_grid(n);
-  (void)kRegistered;
+  const int64_t ntiles = rest / tile;
+  const int64_t ntail = rest - ntiles * tile;
+  const int64_t grid = reduce_grid(n, tile);
   WsHeader* hdr = (WsHeader*)ws;
   uint64_t* partials = (uint64_t*)((char*)ws + sizeof(WsHeader));
-  hipLaunchKernelGGL(reduce_i32_kernel, dim3((unsigned)grid), dim3(kBlock), 0, s,
-                     (const i32x4*)(in + nhead), ntiles, in, nhead, in + nhead + ntiles * kTile,
+  hipLaunchKernelGGL(reduce_i32_kernel<kU>, dim3((unsigned)grid), dim3(kBlock), 0, s,
+                     (const i32x4*)(in + nhead), ntiles, in, nhead, in + nhead + ntiles * tile,
                      ntail, out, hdr, partials);
   return hipGetLastError();
+}
+
+hipError_t reduce_i32(const int32_t* in, int64_t n, int64_t* out, void* ws, hipStream_t s) {
+  (void)kRegistered;
+  if (tune::get(tune::kReduceI32, tune::size_class(tune::kReduceI32, n)) == 1)
+    return launch_reduce<16>(in, n, out, ws, s);
+  return launch_reduce<kMinU>(in, n, out, ws, s);
 }
 
 }  // namespace launch

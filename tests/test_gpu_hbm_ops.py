@@ -211,6 +211,22 @@ def test_scan_every_config(n, restore_configs):
         assert np.array_equal(y.cpu().numpy(), want), name
 
 
+@pytest.mark.parametrize("offset", [0, 3])
+@pytest.mark.parametrize("n", [1, 4097, 16383, 16384, 16385, 300_001, (1 << 22) + 5,
+                               (1 << 24) + 16383])
+def test_reduce_every_config(n, offset, restore_configs):
+    x = workloads.int_uniform(n, seed=410 + n % 11, lo=-(1 << 31), hi=(1 << 31) - 1)
+    want = oracle.reduce_i32(x)
+    xt = to_dev(x, offset)
+    cls = desc.desc_size_class("reduce_i32", n)
+    for cfg, name in _each_config("reduce_i32"):
+        case(f"reduce config {name} n={n} offset={offset}")
+        desc.desc_config_set("reduce_i32", cls, cfg)
+        out = torch.full((1,), -1, dtype=torch.int64, device=dev())
+        desc.desc_reduce_i32(xt, out)
+        assert int(out.item()) == want, name
+
+
 @pytest.mark.parametrize("rows,cols", [(37, 1), (64, 64), (200, 136), (130, 260), (1024, 516)])
 def test_transpose_every_config(rows, cols, restore_configs):
     m = workloads.self_describing_u32(rows, cols)

@@ -40,7 +40,7 @@ MEMORY_OPS = ("global_", "buffer_", "flat_", "ds_", "s_barrier", "s_load", "s_bu
 
 # (view source, demangled view kernel, demangled twin, max instruction ratio view / twin)
 PAIRS = [
-    ("reduce.hip", "reduce_i32_kernel(", "hand::reduce_i32_hand(", 1.0),
+    ("reduce.hip", "reduce_i32_kernel<4>(", "hand::reduce_i32_hand(", 1.0),
     ("scan.hip", "scan_i32_kernel<desc::(anonymous namespace)::ScanCfg<512, 32, true>, true, false>",
      "hand::scan_i32_hand<true>", 1.15),
     ("scan.hip", "scan_i32_kernel<desc::(anonymous namespace)::ScanCfg<512, 32, true>, false, false>",
