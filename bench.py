@@ -516,7 +516,7 @@ def main(argv=None):
                     help="extra per-op measurements ('' for none)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the kernels have no multi-GPU path)", file=sys.stderr)
         return 2
 
