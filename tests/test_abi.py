@@ -363,3 +363,23 @@ def test_grouped_checks(fake_pointers):
     assert st(F32, G, D(0), D(192), wsb) == ALIAS  # ws starts inside the descriptors
     assert st(F32, G, D(0), D(1 << 20), wsb - 1) == WS
     assert st(BF16X3, G, D(0), D(1 << 20), head3 - 1) == WS
+
+
+def test_tuning_table_names_known_configurations():
+    # every line of the shipped table names a registered operation and one of
+    # its configurations, and loading it selects exactly that configuration
+    L = desc.lib()
+    assert L.desc_config_load(desc.TUNE_FILE.encode()) == 0
+    seen = 0
+    with open(desc.TUNE_FILE) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            op, cls, name = line.split()
+            assert op in desc.OPS, op
+            names = [desc.desc_config_name(op, c) for c in range(desc.desc_config_count(op))]
+            assert name in names, (op, name, names)
+            assert desc.desc_config_get(op, int(cls)) == names.index(name), line
+            seen += 1
+    assert seen == 4 * len(desc.OPS)          # four size classes for every operation
