@@ -100,9 +100,12 @@ def test_grouped_strided_and_empty():
             assert err.max() <= TOL
 
 
-@pytest.mark.parametrize("M,N,K", [(100, 90, 80), (512, 384, 256)])
-def test_grouped_single_equals_plain(M, N, K):
+@pytest.mark.parametrize("grouped_config", [1], indirect=True)   # tile64: the plain GEMM's
+@pytest.mark.parametrize("M,N,K", [(100, 90, 80), (512, 384, 256)])  # m64n64k16 tile form
+def test_grouped_single_equals_plain(M, N, K, grouped_config):
     case(f"grouped single vs plain {M}x{N}x{K}")
+    for cls in range(4):
+        desc.desc_config_set("gemm_f32", cls, 3)                        # m64n64k16
     pairs = _problems([(M, N, K)], 5)
     outs, dp, _ = _run(pairs)
     C2 = torch.empty((M, N), dtype=torch.float32, device=dev())
