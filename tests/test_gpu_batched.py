@@ -144,3 +144,27 @@ def test_batched_graph_replay():
         assert np.array_equal(r.cpu().numpy(), want_r)
         assert np.array_equal(y.cpu().numpy(), want_y)
         assert np.array_equal(C.cpu().numpy().view(np.uint32), want_c)
+
+
+def test_gemm_strided_batched_bf16x3_long_rows_use_planes():
+    # lda past the fused split source's limit (2^24 elements): the split-BF16
+    # mode stages these problems through planes sized into the workspace
+    G, M, N, K, lda = 2, 3, 50, 5, (1 << 24) + 7
+    g = workloads.rng(97)
+    A = g.standard_normal((G, M, K)).astype(np.float32)
+    B = g.standard_normal((G, K, N)).astype(np.float32)
+    buf = torch.zeros(G * M * lda, dtype=torch.float32, device=dev())
+    At = buf.as_strided((G, M, K), (M * lda, lda, 1))
+    At.copy_(torch.from_numpy(A))
+    Bt = to_dev(B)
+    C = torch.full((G, M, N), float("nan"), dtype=torch.float32, device=dev())
+    need = desc.desc_gemm_strided_batched_workspace("bf16x3", G, M, N, K, lda, N)
+    assert need > desc.desc_gemm_strided_batched_workspace("bf16x3", G, M, N, K, K, N)
+    case("gemm_strided_batched bf16x3 lda = 2^24 + 7")
+    desc.desc_gemm_strided_batched(At, Bt, C, mode="bf16x3")
+    out = C.cpu().numpy()
+    for b in range(G):
+        ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+        R, D = oracle.gemm_ref_sampled(A[b], B[b], ii.ravel(), jj.ravel())
+        err = np.abs(out[b].ravel() - R) / np.maximum(D, 1e-300)
+        assert err.max() <= bf16x3_bound(K), b
