@@ -226,3 +226,144 @@ def test_fp8_reference_exact_when_codes_are_exact():
     for s, (i, j) in enumerate(zip(ii.ravel(), jj.ravel())):
         exact = math.fsum(float(A[i, k]) * float(B[k, j]) for k in range(K))
         assert Rq[s] == exact
+
+
+# ------------------------------------------------------------------ FP8 pins at general scales
+def _e4m3_codes_by_library(t):
+    """OCP e4m3 codes of float32 values |t| < 464 (torch's round-to-nearest-even)."""
+    return torch.from_numpy(np.ascontiguousarray(t, np.float32)).to(
+        torch.float8_e4m3fn).view(torch.uint8).numpy()
+
+
+def _quant_rows_float32_steps(A, inv_step="f32", mul_step="f32"):
+    """Row quantisation written with numpy float32 arithmetic, one operation
+    per rounding: alpha = max|a|, inv = 448 / alpha (float32 division),
+    t = a * inv (float32 product), codes by the library encoder, scale =
+    alpha / 448.  inv_step / mul_step select deliberately wrong variants."""
+    alpha = np.abs(A).max(axis=1).astype(np.float32)
+    nz = alpha > 0
+    if inv_step == "f32":
+        inv = np.where(nz, np.float32(448.0) / np.where(nz, alpha, 1), np.float32(1.0))
+        inv = inv.astype(np.float32)
+    else:  # inverse kept in FP64
+        inv = np.where(nz, 448.0 / np.where(nz, alpha, 1).astype(np.float64), 1.0)
+    if mul_step == "f32":
+        t = (A * inv[:, None]).astype(np.float32)
+    elif mul_step == "div":   # a / (alpha / 448) instead of a * (448 / alpha)
+        s = (alpha / np.float32(448.0)).astype(np.float32)
+        t = np.where(nz[:, None], A / np.where(nz, s, 1)[:, None], A).astype(np.float32)
+    else:                     # product in FP64 encoded without the float32 rounding
+        t = A.astype(np.float64) * inv[:, None].astype(np.float64)
+        return _e4m3_encode_f64(t), alpha, (alpha / np.float32(448.0)).astype(np.float32)
+    return _e4m3_codes_by_library(t), alpha, (alpha / np.float32(448.0)).astype(np.float32)
+
+
+def _e4m3_encode_f64(t):
+    """Nearest e4m3 value of doubles |t| <= 448, ties to the even code."""
+    codes = np.arange(0, 0x7F, dtype=np.int64)
+    vals = np.array([_e4m3_value_from_definition(int(c)) for c in codes])
+    a = np.abs(t).ravel()
+    hi = np.clip(np.searchsorted(vals, a), 1, vals.size - 1)
+    lo = hi - 1
+    dlo, dhi = a - vals[lo], vals[hi] - a
+    pick = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(codes[lo] % 2 == 0, lo, hi)))
+    q = codes[pick] | np.where(np.signbit(t.ravel()), 0x80, 0)
+    return q.astype(np.uint8).reshape(t.shape)
+
+
+def test_quant_rows_equal_float32_steps_and_separate_wrong_steps():
+    # Rows of very different magnitudes; the codes, absmax and scales must be
+    # those of the float32 steps bit for bit, and the same data must separate
+    # the plausible wrong steps (inverse in FP64, product in FP64, division
+    # by the scale), so that each of them fails this pin.
+    # Besides random values, each row holds values whose scaled image lies
+    # within a few float32 steps of an e4m3 rounding point (the midpoint of two
+    # neighbouring codes), where one rounding more or less changes the code.
+    g = workloads.rng(41)
+    M, K = 512, 1024
+    A = (g.standard_normal((M, K)) * 2.0 ** g.integers(-20, 20, (M, 1))).astype(np.float32)
+    grid = np.unique(oracle.e4m3_decode(np.arange(0, 0x7F, dtype=np.uint8)))
+    mids = (grid[:-1] + grid[1:]) / 2.0
+    for i in range(M):
+        alpha = np.float32(np.abs(A[i]).max())
+        m = g.choice(mids, 128)
+        a = (m * (float(alpha) / 448.0)).astype(np.float32)
+        near = np.concatenate([a, np.nextafter(a, np.float32(np.inf)),
+                               np.nextafter(a, np.float32(0))])
+        near = np.minimum(near, alpha)                    # alpha stays the absmax
+        A[i, 1:1 + near.size] = near * g.choice([-1, 1], near.size).astype(np.float32)
+    A[7] = 0.0
+    q, al, sc = oracle.quant_rows_e4m3(A)
+    want_q, want_al, want_sc = _quant_rows_float32_steps(A)
+    assert np.array_equal(q, want_q)
+    assert np.array_equal(al, want_al) and np.array_equal(sc, want_sc)
+    for inv_step, mul_step in (("f64", "f32"), ("f32", "f64"), ("f32", "div")):
+        wrong_q = _quant_rows_float32_steps(A, inv_step, mul_step)[0]
+        assert not np.array_equal(q, wrong_q), (inv_step, mul_step)
+    # columns: the same steps on B^T
+    B = np.ascontiguousarray(A[:300, :200].T)
+    qc, be, scc = oracle.quant_cols_e4m3(B)
+    wq, wal, wsc = _quant_rows_float32_steps(np.ascontiguousarray(B.T))
+    assert np.array_equal(qc, wq.T) and np.array_equal(be, wal) and np.array_equal(scc, wsc)
+
+
+def test_quant_rows_within_half_spacing():
+    # deq(q) * 448 / alpha approximates a to within half an e4m3 spacing at the
+    # scaled value, plus the two float32 roundings of the scaling (2^-23
+    # relative); spacing 2^(floor(log2|u|) - 3) for |u| >= 2^-6, else 2^-9.
+    g = workloads.rng(42)
+    A = (g.standard_normal((64, 700)) * 2.0 ** g.integers(-30, 30, (64, 1))).astype(np.float32)
+    q, al, _ = oracle.quant_rows_e4m3(A)
+    u = A.astype(np.float64) * (448.0 / al.astype(np.float64))[:, None]
+    dq = np.array([_e4m3_value_from_definition(int(c)) for c in q.ravel()]).reshape(q.shape)
+    au = np.abs(u)
+    spacing = np.where(au >= 2.0**-6, 2.0 ** (np.floor(np.log2(np.maximum(au, 2.0**-6))) - 3),
+                       2.0**-9)
+    assert np.all(np.abs(dq - u) <= 0.5 * spacing + 2.0**-23 * au * 1.0000001)
+    assert np.all(np.abs(dq) <= 448.0)
+
+
+def test_fp8_reference_power_of_two_scales():
+    # Scaling A by 2^a and B by 2^b leaves every code unchanged and multiplies
+    # the scales by exactly 2^a and 2^b (448/alpha and alpha/448 move by exact
+    # powers of two), so Rq and Dq move by exactly 2^(a+b): a reference that
+    # drops a scale, or uses one twice, fails for a != b.
+    A = workloads.matrix_f32(40, 192, seed=43)
+    B = workloads.matrix_f32(192, 30, seed=44)
+    ii, jj = workloads.sample_pairs(40, 30, 300, seed=45)
+    qa, ala, sa = oracle.quant_rows_e4m3(A)
+    qb, alb, sb = oracle.quant_cols_e4m3(B)
+    Rq, Dq = oracle.gemm_fp8_sampled(qa, qb, sa, sb, ii, jj)
+    for a, b in ((5, -3), (-11, 7), (0, 9)):
+        qa2, ala2, sa2 = oracle.quant_rows_e4m3((A * np.float32(2.0**a)).astype(np.float32))
+        qb2, alb2, sb2 = oracle.quant_cols_e4m3((B * np.float32(2.0**b)).astype(np.float32))
+        assert np.array_equal(qa2, qa) and np.array_equal(qb2, qb)
+        assert np.array_equal(sa2, sa * np.float32(2.0**a)) and np.array_equal(sb2, sb * np.float32(2.0**b))
+        Rq2, Dq2 = oracle.gemm_fp8_sampled(qa2, qb2, sa2, sb2, ii, jj)
+        assert np.array_equal(Rq2, Rq * 2.0 ** (a + b)) and np.array_equal(Dq2, Dq * 2.0 ** (a + b))
+
+
+def test_fp8_reference_is_the_exact_scaled_sum_rounded_once():
+    # With general (non power-of-two) scales the reference equals the exact
+    # rational s_a s_b sum_k deq(qa) deq(qb), rounded once to a double: every
+    # product of two e4m3 values is a multiple of 2^-18 below 2^18, so the FP64
+    # sum of up to 2^12 of them is exact, s_a s_b (two floats) is exact in FP64,
+    # and only the final product rounds.  Decoding here follows the format
+    # definition, not the oracle's decoder.
+    from fractions import Fraction
+    g = workloads.rng(46)
+    M, N, K = 12, 9, 320
+    A = (g.standard_normal((M, K)) * g.uniform(0.01, 30.0, (M, 1))).astype(np.float32)
+    B = (g.standard_normal((K, N)) * g.uniform(0.01, 30.0, (1, N))).astype(np.float32)
+    qa, _, sa = oracle.quant_rows_e4m3(A)
+    qb, _, sb = oracle.quant_cols_e4m3(B)
+    assert len(set(sa.tolist())) == M and not np.any(np.log2(sa) == np.round(np.log2(sa)))
+    ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    Rq, Dq = oracle.gemm_fp8_sampled(qa, qb, sa, sb, ii, jj)
+    val = {c: Fraction(_e4m3_value_from_definition(c)) for c in range(256) if (c & 0x7F) != 0x7F}
+    for s, (i, j) in enumerate(zip(ii, jj)):
+        terms = [val[int(qa[i, k])] * val[int(qb[k, j])] for k in range(K)]
+        sc = Fraction(float(sa[i])) * Fraction(float(sb[j]))
+        assert Rq[s] == float(sc * sum(terms))
+        assert Dq[s] == float(abs(sc) * sum(abs(t) for t in terms))
