@@ -73,6 +73,52 @@ typedef int (*desc_pointer_classifier)(const void* p);
 void desc_set_pointer_classifier(desc_pointer_classifier fn);
 
 /* ------------------------------------------------------------------------
+ * Device status of a workspace.  A few failures can only be seen on the GPU,
+ * after the call has returned DESC_OK; the kernels record them in the
+ * 32-bit status word at byte 4 of the workspace:
+ *   DESC_DEV_WAIT_LIMIT  a block's bounded wait for another block ran out.
+ *                        The output of that call is wrong.  Causes: a
+ *                        workspace that was not zeroed before its first use,
+ *                        two calls overlapping on one workspace, or a wait
+ *                        limit set below (debugging).  Sticky: it stays set
+ *                        until read.  Reported by the workspaces of
+ *                        desc_reduce_i32, desc_reduce_op (min/max, float
+ *                        sum), desc_scan_i32 / desc_scan_exclusive_i32,
+ *                        desc_scan_f32, the segmented scan and the batched
+ *                        scan.
+ *   DESC_DEV_PLANES      desc_gemm_grouped or desc_gemm_strided_batched in
+ *                        DESC_GEMM_BF16X3 mode found that the bf16 planes do
+ *                        not fit the workspace (or a dimension above 2^40)
+ *                        and computed nothing.  Written by every such call
+ *                        (0 when it computed), so it describes the last call.
+ *
+ * desc_workspace_status: a kernel on `stream` copies the word into
+ * status[0] (int32, GPU memory) and resets it to 0; stream-ordered after the
+ * calls before it, no host read, capture-safe.  `ws` is the workspace of one
+ * of the calls above (8-byte aligned, ws_bytes >= 64).  On another
+ * workspace of the library the value has no meaning, and resetting it does
+ * not disturb later calls (those workspaces are scratch, rewritten by every
+ * call, or leave the word alone).
+ *
+ * desc_workspace_set_wait_limit (debugging): every bounded wait of a call on
+ * this workspace gives up after at most max_polls polls (0: at once, without
+ * polling); max_polls < 0 restores the built-in limit (2^20 polls).  Kept in
+ * the workspace header until changed (zeroing the workspace restores the
+ * default).  For the workspaces that report DESC_DEV_WAIT_LIMIT.  A wait
+ * that gives up leaves its block to finish with a partial value, so every
+ * kernel still ends normally; the affected outputs are unspecified.
+ * max_polls above 2^32 - 2 is DESC_ERR_SIZE.
+ * ---------------------------------------------------------------------- */
+enum {
+  DESC_DEV_OK = 0,
+  DESC_DEV_WAIT_LIMIT = 1,
+  DESC_DEV_PLANES = 2
+};
+desc_status desc_workspace_status(void* ws, size_t ws_bytes, int32_t* status, void* stream);
+desc_status desc_workspace_set_wait_limit(void* ws, size_t ws_bytes, int64_t max_polls,
+                                          void* stream);
+
+/* ------------------------------------------------------------------------
  * Reduction (Sec. 5, "block-wide parallel reduction", read as the full sum).
  * out[0] = sum of in[0..n), exact: int32 values are summed in int64.  n = 0
  * writes 0.  `in` int32[n] (may be NULL when n = 0), `out` int64[1].
@@ -273,8 +319,9 @@ desc_status desc_quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t l
  *                     host can only check the planning part; the planning
  *                     kernel checks the rest on the GPU, and if the planes do
  *                     not fit, or a problem has M, N or K above 2^40, it
- *                     computes nothing and sets the uint32 at byte 32 of the
- *                     workspace to 1 (0 after a call that computed).
+ *                     computes nothing and sets the device status word (byte
+ *                     4 of the workspace) to DESC_DEV_PLANES, 0 after a call
+ *                     that computed (see desc_workspace_status).
  * desc_gemm_grouped_workspace_for returns 0 for an unsupported mode, G < 0,
  * problems_host = NULL with G > 0, or a refused shape.
  * ---------------------------------------------------------------------- */
@@ -298,7 +345,7 @@ desc_status desc_gemm_grouped(desc_gemm_mode mode, int64_t G, const desc_gemm_pr
  * (strides in elements, >= 0; row-major, lda >= K, ldb >= N, ldc >= N as
  * for desc_gemm).  Modes DESC_GEMM_F32 and DESC_GEMM_BF16X3, with the
  * arithmetic of desc_gemm_grouped: a kernel writes the G problem
- * descriptors into the front of the workspace and the grouped kernels run
+ * descriptors into the back of the workspace and the grouped kernels run
  * on them.  The workspace (256-byte aligned, no initialisation) must hold
  * desc_gemm_strided_batched_workspace(mode, G, M, N, K, lda, ldb) bytes (0
  * for an unsupported mode or a refused shape).  Checks as for desc_gemm on
@@ -317,10 +364,11 @@ desc_status desc_gemm_strided_batched(desc_gemm_mode mode, int64_t G, int64_t M,
 /* ------------------------------------------------------------------------
  * Uniform batched reduce and scan: `in` is a row-major batch x len int32
  * matrix, each row one segment of the segmented forms below (offsets
- * s * len, written by a kernel into the front of the workspace).
+ * s * len, written by a kernel into the back of the workspace).
  *   reduce : out[b] = exact int64 sum of row b (0 when len = 0).
  *   scan   : out[b][i] = in[b][0] + ... + in[b][i] modulo 2^32.
- * Workspaces (8-byte aligned, no initialisation): the matching
+ * Workspaces (8-byte aligned, zeroed once before first use as for the
+ * segmented forms, whose workspace is their front part): the matching
  * *_batched_i32_workspace(batch, len) bytes.  batch = 0 (and, for the scan,
  * len = 0) launches nothing.
  * ---------------------------------------------------------------------- */
@@ -342,8 +390,10 @@ desc_status desc_scan_batched_i32(const int32_t* in, int32_t* out, int64_t batch
  *   scan   : out[i] = in[offsets[s]] + ... + in[i] modulo 2^32 for i in
  *            segment s; positions outside every segment are not written.
  * Each runs as a one-block planning kernel and one main kernel; all state
- * lives in the workspace (no initialisation needed), so both may be
- * captured in a HIP graph and replayed.
+ * lives in the workspace, so both may be captured in a HIP graph and
+ * replayed.  The workspace is zeroed once before its first use (its header
+ * holds the device status word and the wait limit; the planning kernel
+ * resets everything else on every call).
  * ---------------------------------------------------------------------- */
 size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments);
 desc_status desc_reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets,

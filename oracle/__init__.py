@@ -26,13 +26,68 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
+_OMP_SRC = os.path.join(_HERE, "cpu_parallel.c")
+_OMP_LIB = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc (a plain host build)."""
+    """Compile oracle.c into liboracle.so with gcc (a plain host build), and
+    the all-core baseline loops of cpu_parallel.c into liboracle_omp.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_OMP_LIB) or \
+            os.path.getmtime(_OMP_LIB) < os.path.getmtime(_OMP_SRC):
+        tmp = _OMP_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _OMP_SRC,
+                        "-o", tmp], check=True)
+        os.replace(tmp, _OMP_LIB)
     return _LIB
+
+
+_omp = None
+
+
+def omp_lib() -> ctypes.CDLL:
+    """The all-core OpenMP loops (measurement baseline, not the oracle)."""
+    global _omp
+    if _omp is None:
+        if not os.path.exists(_OMP_LIB) or os.path.getmtime(_OMP_LIB) < os.path.getmtime(_OMP_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_OMP_LIB)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        L.omp_threads.restype = ctypes.c_int
+        L.omp_reduce_i32.argtypes = [P, I64]
+        L.omp_reduce_i32.restype = I64
+        L.omp_scan_i32.argtypes = [P, P, I64]
+        L.omp_transpose_u32.argtypes = [P, P, I64, I64]
+        _omp = L
+    return _omp
+
+
+def omp_threads() -> int:
+    return omp_lib().omp_threads()
+
+
+def omp_reduce_i32(x) -> int:
+    x = _c(x, np.int32)
+    return int(omp_lib().omp_reduce_i32(_p(x), x.size))
+
+
+def omp_scan_i32(x):
+    x = _c(x, np.int32)
+    y = np.empty_like(x)
+    omp_lib().omp_scan_i32(_p(x), _p(y), x.size)
+    return y
+
+
+def omp_transpose_u32(m):
+    m = np.ascontiguousarray(m).view(np.uint32)
+    rows, cols = m.shape
+    out = np.empty((cols, rows), np.uint32)
+    omp_lib().omp_transpose_u32(_p(m), _p(out), rows, cols)
+    return out
 
 
 _lib = None

@@ -7,10 +7,12 @@ and turns a non-zero status into :class:`DescError`.  Every step of the
 computation runs in the library's HIP kernels; there is no other path, and
 importing this module fails loudly when the library has not been built.
 
-Workspaces: calls that keep state in a workspace get one from a per-device
-cache when ``ws`` is omitted.  The cache hands out zero-filled buffers and
-keeps them for later calls, which is the contract the library expects (zero
-before the first use, reused by ordered calls afterwards).
+Workspaces: calls that keep state in a workspace get one from a cache keyed
+by device, operation and stream when ``ws`` is omitted.  The cache hands out
+zero-filled buffers and keeps them for later calls on the same stream, which
+is the contract the library expects (zero before the first use, reused by
+ordered calls afterwards).  Failures seen only on the GPU are read from a
+workspace's device status word with ``desc_workspace_status``.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ LIB_PATH = os.path.join(HERE, "libdesc.so")
 
 __all__ = [
     "DescError", "lib", "desc_status_string", "desc_version",
+    "desc_workspace_status", "workspace_status", "desc_workspace_set_wait_limit", "DEV_STATUS",
     "desc_reduce_i32_workspace", "desc_reduce_i32",
     "desc_reduce_op_workspace", "desc_reduce_minmax_i32", "desc_reduce_sum_f32",
     "desc_scan_f32_workspace", "desc_scan_f32",
@@ -52,6 +55,8 @@ _ST = ctypes.c_int
 # name -> (restype, argtypes) of every exported entry point.
 SIGNATURES = {
     "desc_status_string": (ctypes.c_char_p, [_ST]),
+    "desc_workspace_status": (_ST, [_P, _SZ, _P, _P]),
+    "desc_workspace_set_wait_limit": (_ST, [_P, _SZ, _I64, _P]),
     "desc_last_hip_error": (ctypes.c_int, []),
     "desc_version": (ctypes.c_int, []),
     "desc_set_pointer_classifier": (None, [_P]),
@@ -181,23 +186,81 @@ def _ptr(t: torch.Tensor | None):
 
 
 _ws_cache: dict = {}
+# Cached workspaces that a larger one has replaced.  They stay allocated: a
+# graph captured with one, or a kernel still running on another stream, may
+# use it later, and the caching allocator could otherwise hand its memory to
+# a new tensor.
+_ws_retired: list = []
 
 
-def workspace(kind: str, nbytes: int, device) -> torch.Tensor:
-    """A zero-filled workspace of at least ``nbytes`` kept per (device, kind)."""
+def _stream_of(device: torch.device, stream):
+    """The torch stream object for `stream` (None: the current stream)."""
+    if stream is None:
+        return torch.cuda.current_stream(device)
+    if isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(stream), device=device)
+
+
+def workspace(kind: str, nbytes: int, device, stream=None) -> torch.Tensor:
+    """A zero-filled workspace of at least ``nbytes`` kept per (device, kind,
+    stream): calls that share a workspace must be ordered, which calls on one
+    stream are.  A new buffer is allocated and zeroed on that stream, so the
+    fill is ordered before the call that uses it."""
     device = torch.device(device)
-    key = (device.index if device.index is not None else torch.cuda.current_device(), kind)
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    device = torch.device("cuda", idx)
+    s = _stream_of(device, stream)
+    key = (idx, kind, s.cuda_stream)
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < nbytes:
-        ws = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
-        _ws_cache[key] = ws
+        with torch.cuda.stream(s):
+            new = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        if ws is not None:
+            _ws_retired.append(ws)
+        _ws_cache[key] = new
+        ws = new
     return ws
 
 
-def _ws(kind, nbytes, ref: torch.Tensor, ws):
+def _ws(kind, nbytes, ref: torch.Tensor, ws, stream=None):
     if ws is None:
-        return workspace(kind, nbytes, ref.device)
+        return workspace(kind, nbytes, ref.device, stream)
     return _dev(ws, torch.uint8, "ws")
+
+
+# ------------------------------------------------------------------ device status word
+DEV_STATUS = {0: "ok", 1: "wait limit reached", 2: "bf16 planes do not fit"}
+
+
+def desc_workspace_status(ws: torch.Tensor, out: torch.Tensor | None = None,
+                          stream=None) -> torch.Tensor:
+    """Copies the device status word of ``ws`` into ``out`` (int32[1] on the
+    GPU, allocated if omitted) and resets it, in stream order."""
+    _dev(ws, torch.uint8, "ws")
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=ws.device)
+    _dev(out, torch.int32, "out")
+    if out.numel() != 1:
+        raise ValueError("out must hold one int32")
+    _check(lib().desc_workspace_status(_ptr(ws), ws.numel(), _ptr(out), _stream(ws, stream)),
+           "desc_workspace_status")
+    return out
+
+
+def workspace_status(ws: torch.Tensor, stream=None) -> int:
+    """The device status word of ``ws`` as a host int (synchronises), reset to 0."""
+    out = desc_workspace_status(ws, stream=stream)
+    return int(out.item())
+
+
+def desc_workspace_set_wait_limit(ws: torch.Tensor, max_polls: int, stream=None) -> None:
+    """Debugging: every bounded wait of later calls on ``ws`` gives up after
+    ``max_polls`` polls (0: at once); a negative value restores the default."""
+    _dev(ws, torch.uint8, "ws")
+    _check(lib().desc_workspace_set_wait_limit(_ptr(ws), ws.numel(), int(max_polls),
+                                               _stream(ws, stream)),
+           "desc_workspace_set_wait_limit")
 
 
 # ------------------------------------------------------------------ reduce
@@ -212,7 +275,7 @@ def desc_reduce_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None 
     if out.numel() != 1:
         raise ValueError("out must hold one int64")
     n = x.numel()
-    w = _ws("reduce_i32", desc_reduce_i32_workspace(n), x, ws)
+    w = _ws("reduce_i32", desc_reduce_i32_workspace(n), x, ws, stream)
     _check(lib().desc_reduce_i32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(), _stream(x, stream)),
            "desc_reduce_i32")
     return out
@@ -230,7 +293,7 @@ def desc_reduce_minmax_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor 
     if out.numel() != 2:
         raise ValueError("out must hold two int32")
     n = x.numel()
-    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws)
+    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws, stream)
     _check(lib().desc_reduce_minmax_i32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(),
                                         _stream(x, stream)), "desc_reduce_minmax_i32")
     return out
@@ -243,7 +306,7 @@ def desc_reduce_sum_f32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | N
     if out.numel() != 1:
         raise ValueError("out must hold one float64")
     n = x.numel()
-    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws)
+    w = _ws("reduce_op", desc_reduce_op_workspace(n), x, ws, stream)
     _check(lib().desc_reduce_sum_f32(_ptr(x), n, _ptr(out), _ptr(w), w.numel(),
                                      _stream(x, stream)), "desc_reduce_sum_f32")
     return out
@@ -262,7 +325,7 @@ def desc_scan_f32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = 
     if out.numel() != x.numel():
         raise ValueError("out must have as many elements as x")
     n = x.numel()
-    w = _ws("scan_f32", desc_scan_f32_workspace(n), x, ws)
+    w = _ws("scan_f32", desc_scan_f32_workspace(n), x, ws, stream)
     _check(lib().desc_scan_f32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
            "desc_scan_f32")
     return out
@@ -280,7 +343,7 @@ def desc_scan_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = 
     if out.numel() != x.numel():
         raise ValueError("out must have as many elements as x")
     n = x.numel()
-    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
+    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws, stream)
     _check(lib().desc_scan_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
            "desc_scan_i32")
     return out
@@ -294,7 +357,7 @@ def desc_scan_exclusive_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor
     if out.numel() != x.numel():
         raise ValueError("out must have as many elements as x")
     n = x.numel()
-    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws)
+    w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws, stream)
     _check(lib().desc_scan_exclusive_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(),
                                          _stream(x, stream)), "desc_scan_exclusive_i32")
     return out
@@ -323,7 +386,7 @@ def desc_scan_two_pass_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor 
     if out.numel() != x.numel():
         raise ValueError("out must have as many elements as x")
     n = x.numel()
-    w = _ws("scan_two_pass_i32", desc_scan_two_pass_i32_workspace(n), x, ws)
+    w = _ws("scan_two_pass_i32", desc_scan_two_pass_i32_workspace(n), x, ws, stream)
     _check(lib().desc_scan_two_pass_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(),
                                         _stream(x, stream)), "desc_scan_two_pass_i32")
     return out
@@ -467,7 +530,7 @@ def desc_gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, mode="f32",
     need = desc_gemm_workspace(m, M, N, K)
     w = None
     if need:
-        w = _ws(f"gemm{m}", need, A, ws) if ws is None else _dev(ws, torch.uint8, "ws")
+        w = _ws(f"gemm{m}", need, A, ws, stream)
     _check(lib().desc_gemm(m, M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc, _ptr(w),
                            w.numel() if w is not None else 0, _stream(A, stream)), "desc_gemm")
     return C
@@ -545,7 +608,7 @@ def desc_reduce_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch
     if S < 0 or out.numel() != S:
         raise ValueError("offsets must hold S + 1 entries and out S")
     n = x.numel()
-    w = _ws("reduce_segmented_i32", desc_reduce_segmented_i32_workspace(n, S), x, ws)
+    w = _ws("reduce_segmented_i32", desc_reduce_segmented_i32_workspace(n, S), x, ws, stream)
     _check(lib().desc_reduce_segmented_i32(_ptr(x), n, _ptr(offsets), S, _ptr(out), _ptr(w),
                                            w.numel(), _stream(x, stream)),
            "desc_reduce_segmented_i32")
@@ -560,7 +623,7 @@ def desc_scan_segmented_i32(x: torch.Tensor, offsets: torch.Tensor, out: torch.T
     if S < 0 or out.numel() != x.numel():
         raise ValueError("offsets must hold S + 1 entries and out as many elements as x")
     n = x.numel()
-    w = _ws("scan_segmented_i32", desc_scan_segmented_i32_workspace(n, S), x, ws)
+    w = _ws("scan_segmented_i32", desc_scan_segmented_i32_workspace(n, S), x, ws, stream)
     _check(lib().desc_scan_segmented_i32(_ptr(x), _ptr(out), n, _ptr(offsets), S, _ptr(w),
                                          w.numel(), _stream(x, stream)),
            "desc_scan_segmented_i32")
@@ -641,7 +704,7 @@ def desc_reduce_batched_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor
     if x.dim() != 2 or out.numel() != x.shape[0]:
         raise ValueError("x must be 2-D and out hold one int64 per row")
     B, L = x.shape
-    w = _ws("batched_reduce", desc_reduce_batched_i32_workspace(B, L), x, ws)
+    w = _ws("batched_reduce", desc_reduce_batched_i32_workspace(B, L), x, ws, stream)
     _check(lib().desc_reduce_batched_i32(_ptr(x), B, L, _ptr(out), _ptr(w), w.numel(),
                                          _stream(x, stream)), "desc_reduce_batched_i32")
     return out
@@ -654,7 +717,7 @@ def desc_scan_batched_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor |
     if x.dim() != 2 or out.shape != x.shape:
         raise ValueError("x must be 2-D and out of the same shape")
     B, L = x.shape
-    w = _ws("batched_scan", desc_scan_batched_i32_workspace(B, L), x, ws)
+    w = _ws("batched_scan", desc_scan_batched_i32_workspace(B, L), x, ws, stream)
     _check(lib().desc_scan_batched_i32(_ptr(x), _ptr(out), B, L, _ptr(w), w.numel(),
                                        _stream(x, stream)), "desc_scan_batched_i32")
     return out
@@ -686,7 +749,7 @@ def desc_gemm_strided_batched(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor,
     need = desc_gemm_strided_batched_workspace(mode, G, M, N, K, lda, ldb)
     if need == 0 and G > 0 and M > 0 and N > 0:
         raise ValueError("shape refused by this mode")
-    w = _ws("strided_batched_" + str(mode), need, C, ws)
+    w = _ws("strided_batched_" + str(mode), need, C, ws, stream)
     _check(lib().desc_gemm_strided_batched(_mode(mode), G, M, N, K, _ptr(A), lda, A.stride(0),
                                            _ptr(B), ldb, B.stride(0), _ptr(C), ldc, C.stride(0),
                                            _ptr(w), w.numel(), _stream(C, stream)),

@@ -109,6 +109,27 @@ void desc_set_pointer_classifier(desc_pointer_classifier fn) {
   g_classifier.store(fn, std::memory_order_release);
 }
 
+// ----------------------------------------------------------------- device status
+desc_status desc_workspace_status(void* ws, size_t ws_bytes, int32_t* status, void* stream) {
+  if (ws == nullptr || status == nullptr) return DESC_ERR_NULL;
+  DESC_TRY(check_device({ws, status}));
+  if (misaligned(ws, 8) || misaligned(status, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({status, 4}, {ws, (int64_t)ws_bytes})) return DESC_ERR_ALIAS;
+  if (ws_bytes < 64) return DESC_ERR_WORKSPACE;
+  return hip_status(desc::launch::workspace_status(ws, status, (hipStream_t)stream));
+}
+
+desc_status desc_workspace_set_wait_limit(void* ws, size_t ws_bytes, int64_t max_polls,
+                                          void* stream) {
+  if (ws == nullptr) return DESC_ERR_NULL;
+  if (max_polls > (int64_t)0xFFFFFFFEu) return DESC_ERR_SIZE;
+  DESC_TRY(check_device({ws}));
+  if (misaligned(ws, 8)) return DESC_ERR_ALIGNMENT;
+  if (ws_bytes < 64) return DESC_ERR_WORKSPACE;
+  const uint32_t encoded = max_polls < 0 ? 0u : (uint32_t)max_polls + 1u;
+  return hip_status(desc::launch::workspace_set_wait_limit(ws, encoded, (hipStream_t)stream));
+}
+
 // ----------------------------------------------------------------- reduce
 size_t desc_reduce_i32_workspace(int64_t n) { return desc::launch::reduce_i32_workspace(n); }
 
@@ -487,13 +508,18 @@ int64_t batch_span_bytes(int64_t G, int64_t stride, int64_t rows, int64_t cols, 
 size_t desc_gemm_strided_batched_workspace(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
                                            int64_t K, int64_t lda, int64_t ldb) {
   if (G < 0 || G > INT32_MAX || M < 0 || N < 0 || K < 0) return 0;
-  const size_t head = desc::launch::strided_problems_bytes(G);
-  if (mode == DESC_GEMM_F32) return head + desc::launch::gemm_grouped_workspace(G);
-  if (mode != DESC_GEMM_BF16X3) return 0;
-  const desc_gemm_problem p{M, N, K, lda, ldb, N, nullptr, nullptr, nullptr};
-  const size_t rest = desc::launch::gemm_grouped_bf16x3_workspace_uniform(p, G);
-  if (rest == SIZE_MAX || rest > SIZE_MAX - head) return 0;
-  return head + rest;
+  // the grouped workspace first (rounded up to 256 bytes), then the descriptors
+  const size_t descs = desc::launch::strided_problems_bytes(G);
+  size_t rest = 0;
+  if (mode == DESC_GEMM_F32) {
+    rest = desc::launch::gemm_grouped_workspace(G);
+  } else {
+    if (mode != DESC_GEMM_BF16X3) return 0;
+    const desc_gemm_problem p{M, N, K, lda, ldb, N, nullptr, nullptr, nullptr};
+    rest = desc::launch::gemm_grouped_bf16x3_workspace_uniform(p, G);
+  }
+  if (rest >= SIZE_MAX - 511 - descs) return 0;
+  return ((rest + 255) & ~(size_t)255) + descs;
 }
 
 desc_status desc_gemm_strided_batched(desc_gemm_mode mode, int64_t G, int64_t M, int64_t N,
@@ -534,14 +560,12 @@ desc_status desc_gemm_strided_batched(desc_gemm_mode mode, int64_t G, int64_t M,
 // ----------------------------------------------------------------- uniform batched reduce/scan
 size_t desc_reduce_batched_i32_workspace(int64_t batch, int64_t len) {
   if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return 0;
-  return desc::launch::batched_offsets_bytes(batch) +
-         desc::launch::segmented_workspace(batch * len, batch, false);
+  return desc::launch::batched_workspace(batch, len, false);
 }
 
 size_t desc_scan_batched_i32_workspace(int64_t batch, int64_t len) {
   if (batch < 0 || len < 0 || (len > 0 && batch > INT64_MAX / len)) return 0;
-  return desc::launch::batched_offsets_bytes(batch) +
-         desc::launch::segmented_workspace(batch * len, batch, true);
+  return desc::launch::batched_workspace(batch, len, true);
 }
 
 namespace {

@@ -232,7 +232,7 @@ GroupedWs carve(void* ws, int64_t G) {
   uint8_t* w = (uint8_t*)ws;
   GroupedWs r;
   size_t o = 64;
-  r.total = (int64_t*)w;
+  r.total = (int64_t*)(w + 8);   // (bytes 0-7 left alone: byte 4 is the status word of other calls)
   r.tile_start = (int64_t*)(w + o);
   o += ((G + 1) * 8 + 63) & ~(size_t)63;
   r.order = (int32_t*)(w + o);
@@ -328,7 +328,7 @@ __device__ __forceinline__ int64_t tile_edge(int64_t, int64_t) {
 
 struct Bf16Ws {
   int64_t* totals;       // [0] NT tiles, [1] split items, [2] fused tiles
-  uint32_t* error;       // set when the planes do not fit
+  uint32_t* error;       // kDevPlanes when the planes do not fit, else 0 (every call)
   int64_t* nt_start;     // [G + 1]
   int64_t* split_start;  // [G + 1]
   int64_t* plane_off;    // [G]
@@ -344,8 +344,8 @@ Bf16Ws bf16_carve(void* ws, size_t ws_bytes, int64_t G) {
   uint8_t* w = (uint8_t*)ws;
   const size_t arr = ((G + 1) * 8 + 255) & ~(size_t)255;
   Bf16Ws r;
-  r.totals = (int64_t*)w;
-  r.error = (uint32_t*)(w + 32);   // after the three totals
+  r.error = (uint32_t*)(w + 4);    // the device status word, where every workspace has it
+  r.totals = (int64_t*)(w + 8);
   r.nt_start = (int64_t*)(w + 256);
   r.split_start = (int64_t*)(w + 256 + arr);
   r.plane_off = (int64_t*)(w + 256 + 2 * arr);
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_probl
     w.totals[0] = fits ? c_nt : 0;
     w.totals[1] = fits ? c_sp : 0;
     w.totals[2] = fits ? c_ft : 0;
-    w.error[0] = fits ? 0u : 1u;
+    w.error[0] = fits ? 0u : kDevPlanes;
   }
 }
 

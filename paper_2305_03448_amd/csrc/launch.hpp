@@ -80,6 +80,7 @@ hipError_t gemm_grouped_f32(const desc_gemm_problem* problems, int64_t G, void* 
 
 // batched.hip
 size_t batched_offsets_bytes(int64_t B);
+size_t batched_workspace(int64_t B, int64_t L, bool scan);   // segmented ws, then the offsets
 size_t strided_problems_bytes(int64_t G);
 hipError_t reduce_batched_i32(const int32_t* in, int64_t B, int64_t L, int64_t* out, void* ws,
                               hipStream_t s);
@@ -95,6 +96,10 @@ size_t gemm_grouped_bf16x3_workspace_uniform(const desc_gemm_problem& p, int64_t
 // copy.hip
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t reverse_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+
+// status.hip
+hipError_t workspace_status(void* ws, int32_t* out, hipStream_t s);
+hipError_t workspace_set_wait_limit(void* ws, uint32_t encoded, hipStream_t s);
 
 // variants.hip
 hipError_t reduce_blocks_i32(const int32_t* in, int64_t n, int64_t E, int64_t* out,

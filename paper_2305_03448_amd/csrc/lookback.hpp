@@ -7,7 +7,10 @@
 // flag 1 (aggregate): the value is the tile's own sum; flag 2 (prefix): the
 // value is the inclusive prefix up to the tile's end.  Words whose tag is
 // not the current generation read as "not ready", which lets the next call
-// reuse the workspace without a clearing pass.
+// reuse the workspace without a clearing pass.  A call writes the word of
+// every one of its tiles, and the block that advances the generation clears
+// the words the previous call left beyond its own tiles, so no word older
+// than the previous call survives to match a later call's tag.
 #pragma once
 #include "common.hpp"
 #include "view.hpp"
@@ -28,16 +31,19 @@ __device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t gen, uint32_t v
 // Called by one whole wave; the result is valid in every lane.  Window
 // position p = q * 64 + lane (q < kLookWords) reads tile pos - p, so the
 // window runs backwards from `pos` in order of p.
+// At most `max_polls` polls (none with max_polls = 0); a wait that runs out
+// records kDevWaitLimit and returns the partial prefix.
 __device__ __forceinline__ uint32_t look_back(const uint64_t* __restrict__ status, idx_t tile,
-                                              uint32_t gen, WsHeader* __restrict__ hdr) {
+                                              uint32_t gen, uint32_t max_polls,
+                                              WsHeader* __restrict__ hdr) {
   const int lane = wave::lane_id();
   const uint32_t tag = gen & kTagMask;
   uint32_t excl = 0;
   idx_t pos = tile - 1;
   auto st = array(status, tile);
   for (uint32_t polls = 0;; ++polls) {
-    if (polls == kSpinLimit) {     // inconsistent workspace: give up, flag it
-      if (lane == 0) store_u32(&hdr->error, 1u);
+    if (polls == max_polls) {      // inconsistent workspace: give up, flag it
+      if (lane == 0) set_error(hdr, kDevWaitLimit);
       break;
     }
     uint64_t w[kLookWords];

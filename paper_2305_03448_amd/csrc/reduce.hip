@@ -8,9 +8,10 @@
 // thread 0 publishes the block sum in the block's slot of the workspace as
 // one 64-bit word {tag:13, value:51}, the tag naming the call's generation.
 // The last block of the grid waits until every slot carries the current tag,
-// adds the slots in a fixed order, writes the result and advances the
-// generation.  No block waits on a later one and no counter is shared, so
-// there are no same-address atomics and no fences.
+// adds the slots in a fixed order, clears each slot it has read (so no word
+// of an earlier call is left to match a later call's tag), writes the result
+// and advances the generation.  No block waits on a later one and no counter
+// is shared, so there are no same-address atomics and no fences.
 //
 // The grid is sized so that no block sums more than 2^19 elements, which
 // bounds a block sum by 2^50 in magnitude and fits the 51-bit field.
@@ -70,10 +71,10 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
     int64_t nhead, const int32_t* __restrict__ tail, int64_t ntail, int64_t* __restrict__ out,
     WsHeader* __restrict__ hdr, uint64_t* __restrict__ partials) {
   __shared__ int64_t lds[kBlock / kWave];
-  __shared__ uint32_t s_gen;
+  __shared__ CallState s_call;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
-  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
+  if (thread.index() == 0) s_call = read_call_state(hdr);
 
   auto vecs = array(body, ntiles * (kBlock * kU));   // [tiles][kU][kBlock] int32x4
 
@@ -94,26 +95,32 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
     for (idx_t i = thread.index(); i < nhead; i += kBlock) acc += h[i];
     for (idx_t i = thread.index(); i < ntail; i += kBlock) acc += tl[i];
   }
-  const int64_t s = block_sum(acc, lds);   // (its barrier also publishes s_gen)
-  const uint32_t gen = s_gen;
+  const int64_t s = block_sum(acc, lds);   // (its barrier also publishes s_call)
+  const uint32_t gen = s_call.gen;
   auto parts = array(partials, block.count());
   if (!last) {
     if (thread.index() == 0) store_status(&parts[block.index()], pack_sum(s, gen));
     return;
   }
 
-  // Last block: wait for every slot of this generation, then add them.
+  // Last block: wait for every slot of this generation, add it and clear it.
   const uint64_t want = tag_of(gen);
+  const uint32_t maxp = s_call.polls;
   int64_t acc2 = thread.index() == 0 ? s : 0;
   for (idx_t b = thread.index(); b < parts.extent() - 1; b += kBlock) {
-    uint64_t w = load_status(&parts[b]);
-    for (uint32_t polls = 0; (w >> kValueBits) != want; ++polls) {
-      if (polls == kSpinLimit) {     // inconsistent workspace
-        store_u32(&hdr->error, 1u);
+    uint64_t w = 0;
+    for (uint32_t polls = 0;; ++polls) {
+      if (polls == maxp) {     // a bounded wait gave up: report it, leave the slot
+        set_error(hdr, kDevWaitLimit);
+        w = 0;
+        break;
+      }
+      w = load_status(&parts[b]);
+      if ((w >> kValueBits) == want) {
+        store_status(&parts[b], 0);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
-      w = load_status(&parts[b]);
     }
     acc2 += unpack_sum(w);
   }
@@ -121,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void reduce_i32_kernel(
   const int64_t total = block_sum(acc2, lds);
   if (thread.index() == 0) {
     out[0] = total;
-    store_u32(&hdr->gen, gen + 1u);
+    store_u32(&hdr->gen, next_gen(gen));
   }
 }
 

@@ -34,7 +34,8 @@
 // fence.  A block publishes its value in its two-word slot of the workspace,
 // each 64-bit word {tag:32, half of the value:32}, the tag naming the call's
 // generation; the last block waits until both words of every slot carry the
-// current tag, and advances the generation when it is done.
+// current tag, clears each slot it has read, and advances the generation
+// when it is done.
 #include "common.hpp"
 #include "handover.hpp"
 #include "launch.hpp"
@@ -117,10 +118,10 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
                                                            uint64_t* __restrict__ slots) {
   typedef typename Op::Acc Acc;
   __shared__ Acc lds[kWaves];
-  __shared__ uint32_t s_gen;
+  __shared__ CallState s_call;
   auto block = block_x();
   auto thread = thread_x<kBlock>();
-  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
+  if (thread.index() == 0) s_call = read_call_state(hdr);
 
   const int64_t nfull = n / kChunk;
   // [chunks][kGroups][kBlock] groups of four elements; this lane's [kGroups]
@@ -154,8 +155,8 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
         if (i < n) acc = Op::step(acc, x[i]);
       }
   }
-  const Acc mine = block_tree<Op>(acc, lds);   // (its barrier also publishes s_gen)
-  const uint32_t gen = s_gen;
+  const Acc mine = block_tree<Op>(acc, lds);   // (its barrier also publishes s_call)
+  const uint32_t gen = s_call.gen;
   const uint64_t tag = handover::tag_of(gen);
   auto slot = array(slots, 2 * block.count()).template group<2>();   // [G][2]
   const bool last = block.index() == block.count() - 1;
@@ -167,13 +168,16 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
   }
 
   // Step 3: the last block gathers the block values, lane t those of blocks
-  // t, t + 256, ...
+  // t, t + 256, ..., and clears each slot it has read.
   Acc g = Op::identity();
   for (idx_t b = thread.index(); b < block.count(); b += kBlock) {
     Acc v = mine;
     if (b != block.index()) {
       uint64_t w = 0;
-      if (!handover::poll(&slot.idx(b)[0], tag, w)) store_u32(&hdr->error, 1u);
+      if (handover::poll(&slot.idx(b)[0], tag, w, s_call.polls))
+        handover::clear(&slot.idx(b)[0]);
+      else
+        set_error(hdr, kDevWaitLimit);
       v = Op::from_halves((uint32_t)w, (uint32_t)(w >> 32));
     }
     g = Op::join(g, v);
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void reduce_op_kernel(const uint32_t* __res
   const Acc total = block_tree<Op>(g, lds);
   if (thread.index() == 0) {
     Op::write(out, total);
-    store_u32(&hdr->gen, gen + 1u);
+    store_u32(&hdr->gen, next_gen(gen));
   }
 }
 

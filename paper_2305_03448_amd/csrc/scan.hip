@@ -27,7 +27,9 @@
 //     and written with single 64-bit relaxed atomics, so no fence is needed
 //     to make the value visible to blocks on other XCDs.  Words whose tag is
 //     not the current generation read as "not ready", which is what lets the
-//     next call reuse the workspace without a clearing pass.
+//     next call reuse the workspace without a clearing pass.  The last tile
+//     also clears the words an earlier, larger call left past this call's
+//     tiles, so only the previous call's tag or zero is ever found.
 //
 // Integer addition modulo 2^32 is associative, so the result equals the
 // sequential definition bit for bit.
@@ -98,7 +100,8 @@ struct alignas(16) ScanLds {
 };
 template <class C, bool kVec, bool kExcl>
 __device__ __forceinline__ void scan_tile(int32_t* __restrict__ out, int64_t n, idx_t tile,
-                                          idx_t ntiles, uint32_t gen, WsHeader* __restrict__ hdr,
+                                          idx_t ntiles, CallState call,
+                                          WsHeader* __restrict__ hdr,
                                           uint64_t* __restrict__ status,
                                           uint32_t (&x)[C::rounds][4], ScanLds& sl) {
   constexpr int R = C::rounds, NW = C::waves, TILE = C::tile;
@@ -127,17 +130,23 @@ __device__ __forceinline__ void scan_tile(int32_t* __restrict__ out, int64_t n, 
   if (wv.index() == 0) {
     uint32_t excl = 0;
     if (tile == 0) {
-      if (lane.index() == 0) store_status(&st[0], pack(kFlagPrefix, gen, agg));
+      if (lane.index() == 0) store_status(&st[0], pack(kFlagPrefix, call.gen, agg));
     } else {
-      if (lane.index() == 0) store_status(&st[tile], pack(kFlagAggregate, gen, agg));
-      excl = look_back(status, tile, gen, hdr);
-      if (lane.index() == 0) store_status(&st[tile], pack(kFlagPrefix, gen, excl + agg));
+      if (lane.index() == 0) store_status(&st[tile], pack(kFlagAggregate, call.gen, agg));
+      excl = look_back(status, tile, call.gen, call.polls, hdr);
+      if (lane.index() == 0) store_status(&st[tile], pack(kFlagPrefix, call.gen, excl + agg));
     }
-    if (lane.index() == 0) {
-      sl.prefix = excl;
+    if (lane.index() == 0) sl.prefix = excl;
+    if (tile == ntiles - 1) {
       // Every tile before the last has published, so every block of this
-      // call has read the generation: the last tile may advance it.
-      if (tile == ntiles - 1) store_u32(&hdr->gen, gen + 1u);
+      // call has read the generation: the last tile may advance it, and
+      // clear what the previous call left past this call's tiles.
+      const uint64_t hw = __hip_atomic_load(&hdr->hw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      clear_words<kWave>(status, (uint64_t)ntiles, hw, lane.index());
+      if (lane.index() == 0) {
+        __hip_atomic_store(&hdr->hw, (uint64_t)ntiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        store_u32(&hdr->gen, next_gen(call.gen));
+      }
     }
   }
 
@@ -192,16 +201,16 @@ __global__ __launch_bounds__(C::block) void scan_i32_kernel(const int32_t* __res
                                                             int32_t* __restrict__ out, int64_t n,
                                                             WsHeader* __restrict__ hdr,
                                                             uint64_t* __restrict__ status) {
-  __shared__ uint32_t s_gen;
+  __shared__ CallState s_call;
   __shared__ ScanLds sl;
   auto tile_res = block_x();
   auto thread = thread_x<C::block>();
-  if (thread.index() == 0) s_gen = load_u32(&hdr->gen);
+  if (thread.index() == 0) s_call = read_call_state(hdr);
   sync(thread);
-  const uint32_t gen = s_gen;
+  const CallState call = s_call;
   uint32_t x[C::rounds][4];
   load_tile<C, kVec>(in, n, tile_res.index(), tile_res.count(), x);
-  scan_tile<C, kVec, kExcl>(out, n, tile_res.index(), tile_res.count(), gen, hdr, status, x, sl);
+  scan_tile<C, kVec, kExcl>(out, n, tile_res.index(), tile_res.count(), call, hdr, status, x, sl);
 }
 
 template <class C, bool kExcl>

@@ -37,7 +37,10 @@
 // written and read with single relaxed atomics, the tag naming the call's
 // generation.  Tile t waits only on tiles before it (blocks are dispatched in
 // order); the last tile advances the generation once everything before it
-// has published.
+// has published.  Every word of a call's region (T aggregates, then one Q per
+// group, the last, partial group's included) is written by the call, and the
+// last tile clears what the previous call left beyond that region, so no
+// word older than the previous call survives to match a later call's tag.
 #include "common.hpp"
 #include "handover.hpp"
 #include "launch.hpp"
@@ -120,7 +123,7 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
                                               WsHeader* __restrict__ hdr,
                                               uint64_t* __restrict__ aggs,
                                               uint64_t* __restrict__ groups, ScanF32Lds& sl,
-                                              const uint32_t& s_gen) {
+                                              const CallState& s_call) {
   auto tile_res = block_x();
   auto thread = thread_x<kBlock>();
   auto wv = wave_of_block<kBlock>();
@@ -157,8 +160,8 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
   reload_barrier(x);
   const double wsum = wave_sum_f64(ls);
   if (lane.index() == 0) sl.wtot[wv.index()] = wsum;
-  sync(thread);   // (also publishes s_gen)
-  const uint32_t gen = s_gen;
+  sync(thread);   // (also publishes s_call)
+  const uint32_t gen = s_call.gen;
   double wex = 0.0, agg = 0.0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
@@ -177,24 +180,33 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
     if (lane.index() == 0) handover::publish(&ag.idx(tile)[0], tag, bits(agg));
     bool ok = true;
     uint64_t vb = bits(lane.index() == p ? agg : 0.0), qb = bits(0.0);
-    if (lane.index() < p) ok = handover::poll(&ag.idx(g * kGroup + lane.index())[0], tag, vb);
-    if (g > 0 && lane.index() == 0) ok = handover::poll(&gq.idx(g - 1)[0], tag, qb) && ok;
+    if (lane.index() < p)
+      ok = handover::poll(&ag.idx(g * kGroup + lane.index())[0], tag, vb, s_call.polls);
+    if (g > 0 && lane.index() == 0)
+      ok = handover::poll(&gq.idx(g - 1)[0], tag, qb, s_call.polls) && ok;
     const double v = from_bits(vb);
     double q = from_bits(qb);
-    if (__ballot(!ok) != 0 && lane.index() == 0) store_u32(&hdr->error, 1u);
+    if (__ballot(!ok) != 0 && lane.index() == 0) set_error(hdr, kDevWaitLimit);
     q = lane_read_f64(q, 0);
     const double e = wave_sum_f64(lane.index() < p ? v : 0.0);
     const double carry = q + e;
-    if (p == kGroup - 1) {
+    if (p == kGroup - 1 || tile == ntiles - 1) {   // (the last group's Q is not read)
       const double s = wave_sum_f64(v);
       if (lane.index() == 0) handover::publish(&gq.idx(g)[0], tag, bits(q + s));
     }
-    if (lane.index() == 0) {
-      sl.carry = carry;
+    if (lane.index() == 0) sl.carry = carry;
+    if (tile == ntiles - 1) {
       // Everything before the last tile has published (the last tile has
       // seen its group's aggregates and the chain of Q), so every block of
-      // this call has read the generation.
-      if (tile == ntiles - 1) store_u32(&hdr->gen, gen + 1u);
+      // this call has read the generation: advance it, and clear what the
+      // previous call left past this call's region.
+      const uint64_t used = (uint64_t)(2 * ntiles + 2 * ((ntiles + kGroup - 1) / kGroup));
+      const uint64_t hw = __hip_atomic_load(&hdr->hw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      clear_words<kWave>(aggs, used, hw, lane.index());
+      if (lane.index() == 0) {
+        __hip_atomic_store(&hdr->hw, used, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        store_u32(&hdr->gen, next_gen(gen));
+      }
     }
   }
 
@@ -252,13 +264,13 @@ __global__ __launch_bounds__(kBlock) void scan_f32_kernel(const float* __restric
                                                           WsHeader* __restrict__ hdr,
                                                           uint64_t* __restrict__ aggs,
                                                           uint64_t* __restrict__ groups) {
-  __shared__ uint32_t s_gen;
+  __shared__ CallState s_call;
   __shared__ ScanF32Lds sl;
-  if (thread_x<kBlock>().index() == 0) s_gen = load_u32(&hdr->gen);
+  if (thread_x<kBlock>().index() == 0) s_call = read_call_state(hdr);
   if (kVec && ((int64_t)block_x().index() + 1) * kTile <= n)
-    scan_f32_tile<true>(in, out, n, hdr, aggs, groups, sl, s_gen);
+    scan_f32_tile<true>(in, out, n, hdr, aggs, groups, sl, s_call);
   else
-    scan_f32_tile<false>(in, out, n, hdr, aggs, groups, sl, s_gen);
+    scan_f32_tile<false>(in, out, n, hdr, aggs, groups, sl, s_call);
 }
 
 int64_t tiles_of(int64_t n) { return (n + kTile - 1) / kTile; }

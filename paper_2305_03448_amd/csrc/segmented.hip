@@ -240,15 +240,17 @@ __device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t v) { return (fl
 
 // Exclusive prefix of unit u from the earlier units of its segment
 // (j of them); one whole wave.
+// At most `max_polls` polls (none with max_polls = 0); a wait that runs out
+// records kDevWaitLimit and returns the partial prefix.
 __device__ __forceinline__ uint32_t seg_look_back(const uint64_t* status, idx_t u, idx_t j,
-                                                  uint32_t* error) {
+                                                  uint32_t max_polls, WsHeader* hdr) {
   const int lane = wave::lane_id();
   uint32_t excl = 0;
   idx_t pos = u - 1, left = j;        // `left` earlier units still to cover
   auto st = array(status, u);
   for (uint32_t polls = 0; left > 0; ++polls) {
-    if (polls == kSpinLimit) {
-      if (lane == 0) __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (polls == max_polls) {
+      if (lane == 0) set_error(hdr, kDevWaitLimit);
       break;
     }
     const bool in_seg = lane < left;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(C::block) void seg_scan_kernel(const int32_t* __res
                                                           const int64_t* __restrict__ total,
                                                           const int64_t* __restrict__ unit_start,
                                                           uint64_t* __restrict__ status,
-                                                          uint32_t* __restrict__ error) {
+                                                          WsHeader* __restrict__ hdr) {
   constexpr int kBlock = C::block, kWaves = C::waves, kRounds = C::rounds, kUnit = C::unit;
   __shared__ uint32_t s_wtot[kWaves];
   __shared__ uint32_t s_prefix;
@@ -311,7 +313,10 @@ __global__ __launch_bounds__(C::block) void seg_scan_kernel(const int32_t* __res
       if (lane.index() == 0) store_status(&st[u], pack(kFlagPrefix, agg));
     } else {
       if (lane.index() == 0) store_status(&st[u], pack(kFlagAggregate, agg));
-      excl = seg_look_back(status, u, ui.j, error);
+      excl = seg_look_back(status, u, ui.j,
+                           max_polls(__hip_atomic_load(&hdr->wait_limit, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)),
+                           hdr);
       if (lane.index() == 0) store_status(&st[u], pack(kFlagPrefix, excl + agg));
     }
     if (lane.index() == 0) s_prefix = excl;
@@ -389,7 +394,7 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, const int64_t
                      w.total, w.unit_start, (int64_t*)nullptr, w.status, mu);
   if (mu > 0)
     hipLaunchKernelGGL(seg_scan_kernel<C>, dim3((unsigned)mu), dim3(C::block), 0, s, in, out, n,
-                       offsets, S, w.total, w.unit_start, w.status, &((WsHeader*)ws)->error);
+                       offsets, S, w.total, w.unit_start, w.status, (WsHeader*)ws);
   return hipGetLastError();
 }
 

@@ -7,8 +7,9 @@
 // (int64) and synchronisation of the view kernel it mirrors, in one of that
 // kernel's configurations:
 //   reduce     256 threads, 4 int32x4 per lane per tile, non-temporal loads;
-//   scan       512 threads x 32 rounds x 4 int32 per tile (64K elements),
-//              non-temporal loads and stores, 256-word look-back window;
+//   scan       1024 threads x 16 rounds x 4 int32 per tile (64K elements),
+//              non-temporal loads and stores, 256-word look-back window
+//              (the configuration the library runs from 2^24 elements);
 //   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32].
 // Only the index expressions differ: here they are written out by hand
 // instead of being derived from a composition of views.  The helpers shared
@@ -29,7 +30,7 @@ using desc::i32x4;
 using desc::u32x4;
 using desc::kWave;
 using desc::WsHeader;
-using desc::kSpinLimit;
+using desc::CallState;
 
 // ---------------------------------------------------------------- reduce
 constexpr int kRBlock = 256, kRUnroll = 4;
@@ -55,9 +56,9 @@ __global__ __launch_bounds__(kRBlock) void reduce_i32_hand(
     int64_t nhead, const int32_t* __restrict__ tail, int64_t ntail, int64_t* __restrict__ out,
     WsHeader* __restrict__ hdr, uint64_t* __restrict__ partials) {
   __shared__ int64_t lds[kRBlock / kWave];
-  __shared__ uint32_t s_gen;
+  __shared__ CallState s_call;
   const int64_t b = blockIdx.x, nb = gridDim.x, tid = threadIdx.x;
-  if (tid == 0) s_gen = desc::load_u32(&hdr->gen);
+  if (tid == 0) s_call = desc::read_call_state(hdr);
   int64_t acc = 0;
   for (int64_t t = b; t < ntiles; t += nb) {
     const i32x4* p = body + t * kRTileVec + tid;
@@ -74,23 +75,29 @@ __global__ __launch_bounds__(kRBlock) void reduce_i32_hand(
     for (int64_t i = tid; i < ntail; i += kRBlock) acc += tail[i];
   }
   const int64_t s = block_sum(acc, lds);
-  const uint32_t gen = s_gen;
+  const uint32_t gen = s_call.gen;
   if (!last) {
     if (tid == 0)
       desc::store_status(&partials[b], (tag_of(gen) << kValueBits) | ((uint64_t)s & kValueMask));
     return;
   }
   const uint64_t want = tag_of(gen);
+  const uint32_t maxp = s_call.polls;
   int64_t acc2 = tid == 0 ? s : 0;
   for (int64_t i = tid; i < nb - 1; i += kRBlock) {
-    uint64_t w = desc::load_status(&partials[i]);
-    for (uint32_t polls = 0; (w >> kValueBits) != want; ++polls) {
-      if (polls == kSpinLimit) {
-        desc::store_u32(&hdr->error, 1u);
+    uint64_t w = 0;
+    for (uint32_t polls = 0;; ++polls) {
+      if (polls == maxp) {
+        desc::set_error(hdr, desc::kDevWaitLimit);
+        w = 0;
+        break;
+      }
+      w = desc::load_status(&partials[i]);
+      if ((w >> kValueBits) == want) {
+        desc::store_status(&partials[i], 0);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
-      w = desc::load_status(&partials[i]);
     }
     acc2 += (int64_t)(w << (64 - kValueBits)) >> (64 - kValueBits);
   }
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(kRBlock) void reduce_i32_hand(
   const int64_t total = block_sum(acc2, lds);
   if (tid == 0) {
     out[0] = total;
-    desc::store_u32(&hdr->gen, gen + 1u);
+    desc::store_u32(&hdr->gen, desc::next_gen(gen));
   }
 }
 
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(kRBlock) void reduce_i32_hand(
 constexpr uint64_t kFlagAggregate = 1, kFlagPrefix = 2;
 constexpr uint32_t kTagMask = 0x3fffffffu;
 constexpr int kLookWords = 4, kWindow = kWave * kLookWords;
-constexpr int kSBlock = 512, kSRounds = 32, kSWaves = kSBlock / kWave;
+constexpr int kSBlock = 1024, kSRounds = 16, kSWaves = kSBlock / kWave;
 constexpr int kSTile = kSBlock * kSRounds * 4;
 
 __device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t gen, uint32_t v) {
@@ -114,14 +121,15 @@ __device__ __forceinline__ uint64_t pack(uint64_t flag, uint32_t gen, uint32_t v
 }
 
 __device__ __forceinline__ uint32_t look_back(const uint64_t* __restrict__ status, int64_t tile,
-                                              uint32_t gen, WsHeader* __restrict__ hdr) {
+                                              uint32_t gen, uint32_t max_polls,
+                                              WsHeader* __restrict__ hdr) {
   const int lane = (int)(threadIdx.x & 63);
   const uint32_t tag = gen & kTagMask;
   uint32_t excl = 0;
   int64_t pos = tile - 1;
   for (uint32_t polls = 0;; ++polls) {
-    if (polls == kSpinLimit) {
-      if (lane == 0) desc::store_u32(&hdr->error, 1u);
+    if (polls == max_polls) {
+      if (lane == 0) desc::set_error(hdr, desc::kDevWaitLimit);
       break;
     }
     uint64_t w[kLookWords];
@@ -165,13 +173,15 @@ __global__ __launch_bounds__(kSBlock) void scan_i32_hand(const int32_t* __restri
                                                          WsHeader* __restrict__ hdr,
                                                          uint64_t* __restrict__ status) {
   constexpr int R = kSRounds, NW = kSWaves;
-  __shared__ uint32_t s_gen, s_prefix;
+  __shared__ CallState s_call;
+  __shared__ uint32_t s_prefix;
   __shared__ uint32_t s_wtot[NW];
   const int64_t ntiles = gridDim.x, tile = blockIdx.x, tid = threadIdx.x;
   const int64_t wv = tid / kWave, lane = tid % kWave;
-  if (tid == 0) s_gen = desc::load_u32(&hdr->gen);
+  if (tid == 0) s_call = desc::read_call_state(hdr);
   __syncthreads();
-  const uint32_t gen = s_gen;
+  const CallState call = s_call;
+  const uint32_t gen = call.gen;
 
   // group g = ((tile * NW + wave) * R + r) * 64 + lane holds elements 4g..4g+3
   const int64_t g0 = ((tile * NW + wv) * R) * kWave + lane;
@@ -214,12 +224,18 @@ __global__ __launch_bounds__(kSBlock) void scan_i32_hand(const int32_t* __restri
       if (lane == 0) desc::store_status(&status[0], pack(kFlagPrefix, gen, agg));
     } else {
       if (lane == 0) desc::store_status(&status[tile], pack(kFlagAggregate, gen, agg));
-      excl = look_back(status, tile, gen, hdr);
+      excl = look_back(status, tile, gen, call.polls, hdr);
       if (lane == 0) desc::store_status(&status[tile], pack(kFlagPrefix, gen, excl + agg));
     }
-    if (lane == 0) {
-      s_prefix = excl;
-      if (tile == ntiles - 1) desc::store_u32(&hdr->gen, gen + 1u);
+    if (lane == 0) s_prefix = excl;
+    if (tile == ntiles - 1) {
+      const uint64_t hw = __hip_atomic_load(&hdr->hw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int64_t i = ntiles + (uint32_t)lane; i < (int64_t)hw; i += kWave)
+        __hip_atomic_store(&status[i], (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) {
+        __hip_atomic_store(&hdr->hw, (uint64_t)ntiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        desc::store_u32(&hdr->gen, desc::next_gen(gen));
+      }
     }
   }
 

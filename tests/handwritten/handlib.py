@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libdesc_hand.so")
 
 # The one configuration of each library kernel that the twins mirror; the
 # comparison sets the library to these.
-VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b512_r32_nt", "transpose_32": "t128"}
+VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b1024_r16_nt", "transpose_32": "t128"}
 
 
 def build() -> str:

@@ -383,3 +383,41 @@ def test_tuning_table_names_known_configurations():
             assert desc.desc_config_get(op, int(cls)) == names.index(name), line
             seen += 1
     assert seen == 4 * len(desc.OPS)          # four size classes for every operation
+
+
+def test_workspace_status_checks(fake_pointers):
+    L = fake_pointers
+    st = D(1 << 20)
+    assert L.desc_workspace_status(None, 64, st, None) == NULL
+    assert L.desc_workspace_status(D(0), 64, None, None) == NULL
+    assert L.desc_workspace_status(HOSTP, 64, st, None) == HOST
+    assert L.desc_workspace_status(D(0), 64, HOSTP, None) == HOST
+    assert L.desc_workspace_status(D(4), 64, st, None) == ALIGN       # ws 8-byte aligned
+    assert L.desc_workspace_status(D(0), 64, D(2), None) == ALIGN     # status 4-byte aligned
+    assert L.desc_workspace_status(D(0), 64, D(4), None) == ALIAS     # status inside ws
+    assert L.desc_workspace_status(D(0), 63, st, None) == WS          # no room for the header
+    assert L.desc_workspace_set_wait_limit(None, 64, 0, None) == NULL
+    assert L.desc_workspace_set_wait_limit(D(0), 64, (1 << 32) - 1, None) == SIZE
+    assert L.desc_workspace_set_wait_limit(HOSTP, 64, 0, None) == HOST
+    assert L.desc_workspace_set_wait_limit(D(4), 64, 0, None) == ALIGN
+    assert L.desc_workspace_set_wait_limit(D(0), 32, 0, None) == WS
+
+
+def test_batched_workspaces_put_the_segmented_header_first():
+    # the segmented workspace (header with the status word at byte 4) is the
+    # front part of a batched one; the offsets follow, 256-byte aligned
+    L = desc.lib()
+    for B, n in ((1, 5), (300, 4099), (4096, 1 << 16)):
+        seg_r = L.desc_reduce_segmented_i32_workspace(B * n, B)
+        seg_s = L.desc_scan_segmented_i32_workspace(B * n, B)
+        offs = (8 * (B + 1) + 255) // 256 * 256
+        assert L.desc_reduce_batched_i32_workspace(B, n) == (seg_r + 255) // 256 * 256 + offs
+        assert L.desc_scan_batched_i32_workspace(B, n) == (seg_s + 255) // 256 * 256 + offs
+    F32, BF = 0, 1
+    for mode in (F32, BF):
+        for G in (1, 7, 512):
+            descs = (72 * G + 255) // 256 * 256
+            total = L.desc_gemm_strided_batched_workspace(mode, G, 100, 60, 30, 30, 60)
+            assert total > descs and (total - descs) % 256 == 0
+            if mode == F32:
+                assert total - descs >= L.desc_gemm_grouped_workspace(G)

@@ -163,6 +163,72 @@ def test_gemm_workload_4096(mode):
     print(f"[result] gemm {mode} 4096 max componentwise error {e:.3e}", flush=True)
 
 
+@pytest.fixture(scope="module")
+def workload_8192():
+    """The 8192^3 precision workload: A (seed 7), B (seed 8), 4096 sampled
+    entries (seed 9) and their FP64 references."""
+    A = workloads.matrix_f32(8192, 8192, seed=7); B = workloads.matrix_f32(8192, 8192, seed=8)
+    ii, jj = workloads.sample_pairs(8192, 8192, 4096, seed=9)
+    R, D = oracle.gemm_ref_sampled(A, B, ii, jj)
+    return A, B, ii, jj, R, D
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_gemm_workload_8192(workload_8192, mode):
+    A, B, ii, jj, R, D = workload_8192
+    case(f"gemm {mode} 8192^3 (seeds 7/8, 4096 samples seed 9)")
+    C = _run(A, B, mode)
+    e = _check_against(C[ii, jj], R, D, TOL[mode], f"{mode} 8192")
+    print(f"[result] gemm {mode} 8192 max componentwise error {e:.3e}", flush=True)
+
+
+# A-priori bound of the FP8 product against the exact one, componentwise.
+# With inv = fl32(448 / alpha) and s = fl32(alpha / 448), a normal code is
+# within half an e4m3 spacing of the scaled value, relative 2^-4, and a
+# subnormal one within 2^-10 in scaled units, 2^-10 alpha / 448 in the
+# input's; the FP32 steps add a few 2^-24.  So each operand carries
+# |e_a| <= (2^-4 + 2^-20) |a| + t_a, t_a = 2^-10 alpha (1 + 2^-20) / 448, and
+# a product |(a + e_a)(b + e_b) - a b| <= (2^-3 + 2^-7) |a b| +
+# (1 + 2^-3)(|a| t_b + |b| t_a) + t_a t_b, with |a| <= alpha, |b| <= beta.
+# Summed over k, plus the accumulation tolerance on the quantised sum
+# (whose absolute sum is at most (1 + 2^-3) D).  Loose, but a wrong scale or
+# layout exceeds it; the observed error is reported beside it.
+def _fp8_apriori(A, B, ii, jj, D):
+    al = np.abs(A).max(axis=1).astype(np.float64)[ii]
+    be = np.abs(B).max(axis=0).astype(np.float64)[jj]
+    K = A.shape[1]
+    ta, tb = 2.0 ** -10 * al * (1 + 2.0 ** -20) / 448, 2.0 ** -10 * be * (1 + 2.0 ** -20) / 448
+    per_k = (1 + 2.0 ** -3) * (al * tb + be * ta) + ta * tb
+    return (2.0 ** -3 + 2.0 ** -7 + (1 + 2.0 ** -3) * FP8_ACC_TOL) * D + K * per_k
+
+
+def _fp8_workload(A, B, ii, jj, R, D, size):
+    C = _run(A, B, "fp8")
+    qa, _, sa = oracle.quant_rows_e4m3(A)
+    qb, _, sb = oracle.quant_cols_e4m3(B)
+    Rq, Dq = oracle.gemm_fp8_sampled(qa, qb, sa, sb, ii, jj)
+    e_q = _check_against(C[ii, jj], Rq, Dq, FP8_ACC_TOL, f"fp8 {size} vs Rq")
+    dev_abs = np.abs(C[ii, jj].astype(np.float64) - R)
+    assert (dev_abs <= _fp8_apriori(A, B, ii, jj, D)).all(), "fp8 beyond its a-priori bound"
+    e = dev_abs / D
+    print(f"[result] fp8 {size}: vs its own codes {e_q:.3e}; vs the exact product max "
+          f"{e.max():.3e} median {np.median(e):.3e}", flush=True)
+
+
+def test_fp8_workload_4096():
+    case("gemm fp8 4096^3 (seeds 4/5, 4096 samples seed 6)")
+    A = workloads.matrix_f32(4096, 4096, seed=4); B = workloads.matrix_f32(4096, 4096, seed=5)
+    ii, jj = workloads.sample_pairs(4096, 4096, 4096, seed=6)
+    R, D = oracle.gemm_ref_sampled(A, B, ii, jj)
+    _fp8_workload(A, B, ii, jj, R, D, "4096^3")
+
+
+def test_fp8_workload_8192(workload_8192):
+    A, B, ii, jj, R, D = workload_8192
+    case("gemm fp8 8192^3 (seeds 7/8, 4096 samples seed 9)")
+    _fp8_workload(A, B, ii, jj, R, D, "8192^3")
+
+
 # ------------------------------------------------------------------ operand preparation
 def _patterns(rows, cols, seed):
     g = workloads.rng(seed)
