@@ -51,7 +51,8 @@ typedef enum {
   DESC_ERR_WORKSPACE = -5,     /* workspace smaller than the query returned */
   DESC_ERR_UNSUPPORTED = -6,   /* mode or shape the library does not provide */
   DESC_ERR_HIP = -7,           /* a HIP call failed; see desc_last_hip_error() */
-  DESC_ERR_ALIGNMENT = -8      /* pointer not aligned to its element size */
+  DESC_ERR_ALIGNMENT = -8,     /* pointer not aligned to its element size */
+  DESC_ERR_LIMIT = -9          /* size above an allocation-free call's fixed scratch */
 } desc_status;
 
 /* Human-readable name of a status code (static storage). */
@@ -173,6 +174,20 @@ desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
  * (desc_scan_i32_workspace(n) bytes), same checks. */
 desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
                                     size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): desc_scan_i32 without a
+ * workspace.  Its state lives in a fixed device array of the library
+ * (2 MiB + 64 bytes per GPU, held until the process ends, set up and
+ * cleared by the first call on each GPU); n up to DESC_SCAN_NOALLOC_MAX_N
+ * elements, larger n returns DESC_ERR_LIMIT before anything is launched.
+ * Every call on one GPU shares that array: calls that overlap in time race
+ * (order them on one stream or synchronise), and a device-side failure of
+ * a call is not reported (it can only come from such an overlap).  Same
+ * result, checks and stream semantics as desc_scan_i32; nothing is
+ * allocated, freed or synchronised. */
+#define DESC_SCAN_NOALLOC_MAX_N ((int64_t)1 << 31)
+desc_status desc_scan_i32_noalloc(const int32_t* in, int32_t* out, int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------
  * Inclusive scan of float32 values (the scan of Sec. 5 over floats):

@@ -31,6 +31,7 @@ __all__ = [
     "desc_reduce_op_workspace", "desc_reduce_minmax_i32", "desc_reduce_sum_f32",
     "desc_scan_f32_workspace", "desc_scan_f32",
     "desc_scan_i32_workspace", "desc_scan_i32", "desc_scan_exclusive_i32", "desc_reduce_blocks_i32",
+    "desc_scan_i32_noalloc",
     "desc_scan_two_pass_i32_workspace", "desc_scan_two_pass_i32",
     "desc_transpose_f32", "desc_transpose_batched_f32", "desc_transpose_batched", "desc_copy_32", "desc_reverse_u32",
     "desc_config_count", "desc_config_name", "desc_op_name", "desc_size_class",
@@ -70,6 +71,7 @@ SIGNATURES = {
     "desc_scan_i32_workspace": (_SZ, [_I64]),
     "desc_scan_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
     "desc_scan_exclusive_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
+    "desc_scan_i32_noalloc": (_ST, [_P, _P, _I64, _P]),
     "desc_reduce_blocks_i32": (_ST, [_P, _I64, _I64, _P, _P]),
     "desc_scan_two_pass_i32_workspace": (_SZ, [_I64]),
     "desc_scan_two_pass_i32": (_ST, [_P, _P, _I64, _P, _SZ, _P]),
@@ -346,6 +348,17 @@ def desc_scan_i32(x: torch.Tensor, out: torch.Tensor, ws: torch.Tensor | None = 
     w = _ws("scan_i32", desc_scan_i32_workspace(n), x, ws, stream)
     _check(lib().desc_scan_i32(_ptr(x), _ptr(out), n, _ptr(w), w.numel(), _stream(x, stream)),
            "desc_scan_i32")
+    return out
+
+
+def desc_scan_i32_noalloc(x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """Inclusive scan of int32 ``x`` into ``out`` through the entry point that
+    allocates nothing (the library's fixed per-GPU scratch; n <= 2^31)."""
+    _dev(x, torch.int32, "x"); _dev(out, torch.int32, "out")
+    if out.numel() != x.numel():
+        raise ValueError("out must have as many elements as x")
+    _check(lib().desc_scan_i32_noalloc(_ptr(x), _ptr(out), x.numel(), _stream(x, stream)),
+           "desc_scan_i32_noalloc")
     return out
 
 

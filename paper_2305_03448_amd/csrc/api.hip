@@ -97,6 +97,8 @@ const char* desc_status_string(desc_status s) {
     case DESC_ERR_UNSUPPORTED: return "DESC_ERR_UNSUPPORTED: mode or shape not provided";
     case DESC_ERR_HIP: return "DESC_ERR_HIP: a HIP call failed";
     case DESC_ERR_ALIGNMENT: return "DESC_ERR_ALIGNMENT: pointer not aligned to its element";
+    case DESC_ERR_LIMIT:
+      return "DESC_ERR_LIMIT: size above the fixed scratch of an allocation-free entry point";
   }
   return "unknown desc_status";
 }
@@ -212,6 +214,22 @@ desc_status desc_scan_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
 desc_status desc_scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, void* ws,
                                     size_t ws_bytes, void* stream) {
   return scan_checked(in, out, n, ws, ws_bytes, stream, true);
+}
+
+desc_status desc_scan_i32_noalloc(const int32_t* in, int32_t* out, int64_t n, void* stream) {
+  if ((in == nullptr || out == nullptr) && n > 0) return DESC_ERR_NULL;
+  const int64_t nb = bytes_of(n, 4);
+  if (nb < 0) return DESC_ERR_SIZE;
+  if (n == 0) return DESC_OK;
+  DESC_TRY(check_device({in, out}));
+  if (misaligned(in, 4) || misaligned(out, 4)) return DESC_ERR_ALIGNMENT;
+  if (overlap({out, nb}, {in, nb})) return DESC_ERR_ALIAS;
+  if (n > desc::launch::scan_noalloc_max_n()) return DESC_ERR_LIMIT;
+  void* scratch = nullptr;
+  size_t bytes = 0;
+  DESC_TRY(hip_status(desc::launch::noalloc_scratch((hipStream_t)stream, &scratch, &bytes)));
+  if (bytes < desc_scan_i32_workspace(n)) return DESC_ERR_LIMIT;
+  return hip_status(desc::launch::scan_i32(in, out, n, scratch, (hipStream_t)stream, false));
 }
 
 // ----------------------------------------------------------------- fixed-order float scan

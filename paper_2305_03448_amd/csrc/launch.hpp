@@ -97,6 +97,10 @@ size_t gemm_grouped_bf16x3_workspace_uniform(const desc_gemm_problem& p, int64_t
 hipError_t copy_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t reverse_32(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 
+// noalloc.hip
+int64_t scan_noalloc_max_n();
+hipError_t noalloc_scratch(hipStream_t s, void** out, size_t* bytes);
+
 // status.hip
 hipError_t workspace_status(void* ws, int32_t* out, hipStream_t s);
 hipError_t workspace_set_wait_limit(void* ws, uint32_t encoded, hipStream_t s);

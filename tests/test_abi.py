@@ -421,3 +421,18 @@ def test_batched_workspaces_put_the_segmented_header_first():
             assert total > descs and (total - descs) % 256 == 0
             if mode == F32:
                 assert total - descs >= L.desc_gemm_grouped_workspace(G)
+
+
+def test_scan_noalloc_checks(fake_pointers):
+    L = fake_pointers
+    LIMIT = -9
+    big = (1 << 31) + 1
+    assert L.desc_scan_i32_noalloc(None, D(0), 5, None) == NULL
+    assert L.desc_scan_i32_noalloc(D(0), D(1 << 20), -1, None) == SIZE
+    assert L.desc_scan_i32_noalloc(HOSTP, D(1 << 20), 5, None) == HOST
+    assert L.desc_scan_i32_noalloc(D(2), D(1 << 20), 5, None) == ALIGN
+    assert L.desc_scan_i32_noalloc(D(0), D(8), 5, None) == ALIAS
+    # above the fixed scratch: refused after the pointer checks, before any launch
+    assert L.desc_scan_i32_noalloc(D(0), D(1 << 36), big, None) == LIMIT
+    assert L.desc_scan_i32_noalloc(D(0), D(1 << 20), 0, None) == OK     # n = 0: nothing to do
+    assert "allocation-free" in desc.desc_status_string(LIMIT)
