@@ -58,8 +58,8 @@ hipError_t launch_copy(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t
   const int64_t nvec = vec ? n / 4 : 0;
   const int64_t chunks = nvec / (kBlock * kUnroll);
   // Many blocks in flight: at 2^28 words a grid of 16384 copies at 6.2 TB/s
-  // where 4096 blocks reach 6.0 (reads alone stream at 6.7 TB/s, writes
-  // alone at 4.5: the writes set the ceiling of a read + write stream).
+  // where 4096 blocks reach 6.0 (reads alone stream at 6.5-7.0 TB/s and
+  // writes alone at 6.2-6.9, so a read + write stream stays below either).
   constexpr int64_t kMaxGrid = 16384;
   int64_t grid = chunks < kMaxGrid ? chunks : kMaxGrid;
   if (grid < 1) grid = 1;

@@ -2,6 +2,7 @@
 // the grouped GEMM.  See gemm_f32.hip for the scheme.
 #pragma once
 #include "common.hpp"
+#include "layouts.hpp"
 #include "mfma.hpp"
 #include "view.hpp"
 
@@ -266,12 +267,12 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
 #pragma unroll
     for (int i = 0; i < C::a_vec; ++i) {
       const int q = (int)thread.index() + T * i;
-      *(f32x4*)&as.at(q / (BK / 4), 4 * (q % (BK / 4))) = R.a[i];
+      *(f32x4*)&as.at(layout::gemm_store_row<BK>(q), layout::gemm_store_word<BK>(q)) = R.a[i];
     }
 #pragma unroll
     for (int i = 0; i < C::b_vec; ++i) {
       const int q = (int)thread.index() + T * i;
-      *(f32x4*)&bs.at(q / (BN / 4), 4 * (q % (BN / 4))) = R.b[i];
+      *(f32x4*)&bs.at(layout::gemm_store_row<BN>(q), layout::gemm_store_word<BN>(q)) = R.b[i];
     }
   };
 
@@ -293,13 +294,15 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
       f32x4 a[C::fm];
 #pragma unroll
       for (int i = 0; i < C::fm; ++i)
-        a[i] = *(const f32x4*)&as.at(wm * C::wtm + i * 32 + col32, half * HK + k4);
+        a[i] = *(const f32x4*)&as.at(layout::gemm_a_frag_row<C::wtm>(wm, i, col32),
+                                      layout::gemm_frag_k<BK>(half, k4));
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         float b[C::fn];
 #pragma unroll
         for (int j = 0; j < C::fn; ++j)
-          b[j] = bs.at(half * HK + k4 + kk, wn * C::wtn + j * 32 + col32);
+          b[j] = bs.at(layout::gemm_frag_k<BK>(half, k4) + kk,
+                       layout::gemm_b_frag_word<C::wtn>(wn, j, col32));
 #pragma unroll
         for (int i = 0; i < C::fm; ++i)
 #pragma unroll
@@ -362,6 +365,10 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
     }
   }
 
+  // The wave's 32 x 32 fragments of C: register r of the lane holds row
+  // mfma::acc_row(r, lane) = 8 (r / 4) + 4 half + r % 4 and column col32 of
+  // its fragment (the row written out in 64-bit arithmetic, so the compiler
+  // folds the constant parts into the store offsets).
   auto c_g = matrix(p.C, p.M, p.ldc);
   if (m0 + BM <= p.M && n0 + BN <= p.N) {
 #pragma unroll
@@ -370,7 +377,7 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
       for (int j = 0; j < C::fn; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-          c_g.at(m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane),
+          c_g.at(m0 + wm * C::wtm + i * 32 + 8 * (r / 4) + 4 * half + r % 4,
                  n0 + wn * C::wtn + j * 32 + col32) = acc[i][j][r];
   } else {
 #pragma unroll
@@ -379,7 +386,7 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
       for (int j = 0; j < C::fn; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const idx_t row = m0 + wm * C::wtm + i * 32 + mfma::acc_row(r, lane);
+          const idx_t row = m0 + wm * C::wtm + i * 32 + 8 * (r / 4) + 4 * half + r % 4;
           const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
           if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
         }

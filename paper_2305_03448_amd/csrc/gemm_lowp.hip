@@ -422,7 +422,7 @@ struct LowpLayout {
 };
 
 // bf16x3: Ah, Al, Bh^T, Bl^T.  fp8: qA, qB^T, sA, sB, column partials.
-LowpLayout layout(int mode, int64_t M, int64_t N, int64_t K) {
+LowpLayout lowp_layout(int mode, int64_t M, int64_t N, int64_t K) {
   LowpLayout L{};
   L.Mp = round_up(M > 0 ? M : 1, kPadMN);
   L.Np = round_up(N > 0 ? N : 1, kPadMN);
@@ -470,7 +470,7 @@ const bool kRegistered =
 namespace launch {
 
 size_t gemm_lowp_workspace(int mode, int64_t M, int64_t N, int64_t K) {
-  return layout(mode, M, N, K).total;
+  return lowp_layout(mode, M, N, K).total;
 }
 
 bool f4_ok(const void* p, int64_t ld) { return ((uintptr_t)p % 16) == 0 && ld % 4 == 0; }
@@ -529,7 +529,7 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
   }
   // the pre-pass form (also the fused configurations' path for K = 0 and
   // strides past the split source's limit)
-  const LowpLayout L = layout(1, M, N, K);
+  const LowpLayout L = lowp_layout(1, M, N, K);
   uint8_t* w = (uint8_t*)ws;
   uint16_t *ah = (uint16_t*)(w + L.off[0]), *al = (uint16_t*)(w + L.off[1]);
   uint16_t *bh = (uint16_t*)(w + L.off[2]), *bl = (uint16_t*)(w + L.off[3]);
@@ -553,7 +553,7 @@ hipError_t gemm_bf16x3(const float* A, int64_t lda, const float* B, int64_t ldb,
 hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, float* Cm,
                     int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws, hipStream_t s) {
   (void)kRegistered;
-  const LowpLayout L = layout(2, M, N, K);
+  const LowpLayout L = lowp_layout(2, M, N, K);
   uint8_t* w = (uint8_t*)ws;
   uint8_t *qa = w + L.off[0], *qb = w + L.off[2];
   float *sa = (float*)(w + L.off[4]), *sb = (float*)(w + L.off[5]), *part = (float*)(w + L.off[6]);

@@ -20,6 +20,7 @@
 #include "gemm_f32.hpp"
 #include "lowp.hpp"
 #include "mfma.hpp"
+#include "layouts.hpp"
 #include "view.hpp"
 
 namespace desc {
@@ -169,12 +170,12 @@ struct F32Operands {
 
 // A buffer resource over `bytes` bytes from `base` (raw, 32-bit elements):
 // a buffer load at a byte offset >= bytes returns zero without touching
-// memory, which is how the split source below handles every edge.
+// memory, which is how the split source below handles every edge (its
+// offsets come from the BufferWindow view over each range).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
   constexpr int kRawDword3 = 0x00020000;   // gfx9 word 3: 32-bit data format, no swizzle
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kRawDword3);
 }
-constexpr uint32_t kOutside = 0x80000000u;   // an offset past any range used here
 
 // The strides the split source accepts: its buffer offsets, at most 16 rows
 // of A or 8 rows of B from a range's base, stay below 2^31.
@@ -223,46 +224,41 @@ struct SplitSource {
     const int w = __builtin_amdgcn_readfirstlane((int)wave_of_block<T>().index());
     auto a = matrix(p.A, p.M, p.lda);
     auto b = matrix(p.B, p.K, p.ldb);
-    const int lr = lane / CPR, o = lane % CPR;                   // row in the wave's 16, octet
+    const int lr = layout::split_a_row<CPR>(lane);               // row in the wave's 16
+    const int ka = layout::split_a_k<CPR>(lane);                 // first k of the lane's octet
 #pragma unroll
     for (int i = 0; i < AO; ++i) {
       const idx_t r0 = m0 + (T / CPR) * i + (kWave / CPR) * w;  // first of the wave's rows
       const idx_t rv = max_i(min_i(p.M - r0, kWave / CPR), 0);   // its valid rows
-      const uint32_t bytes = rv > 0 ? (uint32_t)(((rv - 1) * p.lda + cols) * 4) : 0u;
-      const auto rs = buffer_rsrc(rv > 0 ? &a.at(r0, k0) : p.A, bytes);
-      const uint32_t row_off = (uint32_t)(lr * p.lda) * 4u;
+      const BufferWindow<4> win{(uint32_t)p.lda, (int32_t)rv, cols};
+      const auto rs = buffer_rsrc(rv > 0 ? &a.at(r0, k0) : p.A, win.bytes());
+      const uint32_t row = win.row(lr);
       if constexpr (kVec) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int kk = 8 * o + 4 * h;
-          const uint32_t off = kk < cols ? row_off + 4u * kk : kOutside;
+        for (int h = 0; h < 2; ++h)
           R.a[i][h] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                    rs, (int)off, 0, 0));
-        }
+                                                    rs, (int)(row + win.col(ka + 4 * h)), 0, 0));
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int kk = 8 * o + j;
-          const uint32_t off = kk < cols ? row_off + 4u * kk : kOutside;
-          R.a[i][j / 4][j % 4] =
-              __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
-        }
+        for (int j = 0; j < 8; ++j)
+          R.a[i][j / 4][j % 4] = __uint_as_float(
+              __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(row + win.col(ka + j)), 0, 0));
       }
     }
 #pragma unroll
     for (int i = 0; i < BO; ++i) {
       const int q0 = T * i + kWave * w;                          // the wave's first octet index
-      const idx_t c = n0 + q0 % C::bn + lane;                     // this lane's column
+      const idx_t c0 = n0 + q0 % C::bn;                           // the wave's first column
       const idx_t kb = k0 + 8 * (q0 / C::bn);                     // the wave's octet
-      const idx_t rv = max_i(min_i(p.K - kb, 8), 0);
-      const idx_t cv = min_i(p.N - (n0 + q0 % C::bn), kWave);     // valid columns of the wave
-      const uint32_t bytes = rv > 0 && cv > 0 ? (uint32_t)(((rv - 1) * p.ldb + cv) * 4) : 0u;
-      const auto rs = buffer_rsrc(rv > 0 && cv > 0 ? &b.at(kb, n0 + q0 % C::bn) : p.B, bytes);
-      const uint32_t col_off = c < p.N ? 4u * (uint32_t)lane : kOutside;
+      const idx_t rv = max_i(min_i(p.K - kb, 8), 0);               // valid k of the octet
+      const idx_t cv = min_i(p.N - c0, kWave);                      // valid columns of the wave
+      const BufferWindow<4> win{(uint32_t)p.ldb, (int32_t)rv, (int32_t)cv};
+      const auto rs = buffer_rsrc(rv > 0 && cv > 0 ? &b.at(kb, c0) : p.B, win.bytes());
+      const uint32_t col = win.col(layout::split_b_col(lane));
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        R.b[i][j / 4][j % 4] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-            rs, (int)(col_off + (uint32_t)(j * p.ldb) * 4u), 0, 0));
+        R.b[i][j / 4][j % 4] = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(win.row(j) + col), 0, 0));
     }
   }
   __device__ __forceinline__ static idx_t min_i(idx_t x, idx_t y) { return x < y ? x : y; }

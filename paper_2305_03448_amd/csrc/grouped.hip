@@ -185,17 +185,12 @@ void grouped_gemm_kernel(const desc_gemm_problem* probs,
   auto thread = thread_x<kBlock>();
   auto ts = array(tile_start, G + 1);
   const int64_t T = total[0];
-  // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
-  // The planned tile sequence is cut into runs of kRun consecutive tiles
-  // (about one problem), run u going to XCD u % 8, so the tiles that share a
-  // problem's operands run on one XCD; the XCD's blocks walk its runs in
-  // order.  t(l) grows with l, so the walk ends at the first t >= T.
-  constexpr idx_t kRun = 64, kXcd = 8;
-  const bool by_xcd = block.count() % kXcd == 0;
-  const idx_t x = by_xcd ? block.index() % kXcd : 0;
-  const idx_t per = by_xcd ? block.count() / kXcd : block.count();
-  for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
-    const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
+  // The XCD-aware walk (layout::tile_walk): runs of 64 consecutive planned
+  // tiles (about one problem) stay on one XCD, each with its own L2, so the
+  // tiles that share a problem's operands meet its cache.
+  const layout::TileWalk walk = layout::tile_walk(block.index(), block.count());
+  for (idx_t l = walk.first;; l += walk.per) {
+    const idx_t t = walk.tile(l);
     if (t >= T) break;
     if (thread.index() < kWave) {    // planned slot of tile t: last i with ts[i] <= t
       const idx_t slot = wave_owner(tile_start, G, t);
@@ -481,9 +476,15 @@ __global__ __launch_bounds__(kBlock) void bf16_plan_kernel(const desc_gemm_probl
 struct Planes {
   uint16_t *ah, *al, *bh, *bl;
 };
+// Problem g's region of the planes area (plane_off[g] bytes in, 256-byte
+// aligned) holds Ah, Al as [Ma][Kp] and Bh^T, Bl^T as [Na][Kp], one after
+// the other: a view over the region, split at the plane boundaries.
 __device__ __forceinline__ Planes planes_of(const Bf16Ws& w, idx_t g, const Bf16Dims& d) {
-  uint16_t* p = (uint16_t*)(w.planes + array(w.plane_off, g + 1)[g]);
-  return {p, p + d.Ma * d.Kp, p + 2 * d.Ma * d.Kp, p + 2 * d.Ma * d.Kp + d.Na * d.Kp};
+  const idx_t off = array(w.plane_off, g + 1)[g];
+  auto area = array((uint16_t*)w.planes, w.planes_bytes / 2);
+  auto mine = area.snd(off / 2);                       // this problem's region
+  const idx_t a = d.Ma * d.Kp, b = d.Na * d.Kp;
+  return {&mine.snd(0)[0], &mine.snd(a)[0], &mine.snd(2 * a)[0], &mine.snd(2 * a + b)[0]};
 }
 
 // Split item: a 64 x 64 tile of A (rows r0.., k0..) into Ah, Al, or a
@@ -578,12 +579,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSmallOn
   auto block = block_x();
   auto thread = thread_x<kBlock>();
   const int64_t T = w.totals[0];
-  constexpr idx_t kRun = 64, kXcd = 8;
-  const bool by_xcd = block.count() % kXcd == 0;
-  const idx_t x = by_xcd ? block.index() % kXcd : 0;
-  const idx_t per = by_xcd ? block.count() / kXcd : block.count();
-  for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
-    const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
+  const layout::TileWalk walk = layout::tile_walk(block.index(), block.count());
+  for (idx_t l = walk.first;; l += walk.per) {
+    const idx_t t = walk.tile(l);
     if (t >= T) break;
     if (thread.index() < kWave) {
       const idx_t g = wave_owner(w.nt_start, G, t);
@@ -626,12 +624,9 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
   auto block = block_x();
   auto thread = thread_x<kThreads>();
   const int64_t T = w.totals[2];
-  constexpr idx_t kRun = 64, kXcd = 8;
-  const bool by_xcd = block.count() % kXcd == 0;
-  const idx_t x = by_xcd ? block.index() % kXcd : 0;
-  const idx_t per = by_xcd ? block.count() / kXcd : block.count();
-  for (idx_t l = by_xcd ? block.index() / kXcd : block.index();; l += per) {
-    const idx_t t = by_xcd ? (kXcd * (l / kRun) + x) * kRun + l % kRun : l;
+  const layout::TileWalk walk = layout::tile_walk(block.index(), block.count());
+  for (idx_t l = walk.first;; l += walk.per) {
+    const idx_t t = walk.tile(l);
     if (t >= T) break;
     if (thread.index() < kWave) {   // the slot of tile t in the fused order
       const idx_t slot = wave_owner(w.fused_start, G, t);

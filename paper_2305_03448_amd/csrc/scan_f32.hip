@@ -181,7 +181,8 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
     bool ok = true;
     uint64_t vb = bits(lane.index() == p ? agg : 0.0), qb = bits(0.0);
     if (lane.index() < p)
-      ok = handover::poll(&ag.idx(g * kGroup + lane.index())[0], tag, vb, s_call.polls);
+      ok = handover::poll(&ag.idx(layout::handover_peer<kGroup>(tile, lane.index()))[0], tag, vb,
+                          s_call.polls);
     if (g > 0 && lane.index() == 0)
       ok = handover::poll(&gq.idx(g - 1)[0], tag, qb, s_call.polls) && ok;
     const double v = from_bits(vb);
@@ -190,7 +191,7 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
     q = lane_read_f64(q, 0);
     const double e = wave_sum_f64(lane.index() < p ? v : 0.0);
     const double carry = q + e;
-    if (p == kGroup - 1 || tile == ntiles - 1) {   // (the last group's Q is not read)
+    if (layout::handover_publishes_group<kGroup>(tile, ntiles)) {   // (the last Q is not read)
       const double s = wave_sum_f64(v);
       if (lane.index() == 0) handover::publish(&gq.idx(g)[0], tag, bits(q + s));
     }
@@ -200,7 +201,7 @@ __device__ __forceinline__ void scan_f32_tile(const float* __restrict__ in,
       // seen its group's aggregates and the chain of Q), so every block of
       // this call has read the generation: advance it, and clear what the
       // previous call left past this call's region.
-      const uint64_t used = (uint64_t)(2 * ntiles + 2 * ((ntiles + kGroup - 1) / kGroup));
+      const uint64_t used = (uint64_t)layout::handover_words<kGroup>(ntiles);
       const uint64_t hw = __hip_atomic_load(&hdr->hw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       clear_words<kWave>(aggs, used, hw, lane.index());
       if (lane.index() == 0) {

@@ -55,12 +55,12 @@ struct SegWs {
 };
 
 template <class C>
-__device__ __forceinline__ int64_t units_of(int64_t len) { return (len + C::unit - 1) / C::unit; }
+__device__ __forceinline__ int64_t units_of(int64_t len) { return layout::seg_units(len, C::unit); }
 
 // Offsets are read clamped to [0, n]: offsets that break the documented
 // precondition (non-decreasing, within the array) give unspecified results
 // but never an access outside the array.
-__device__ __forceinline__ int64_t clampn(int64_t v, int64_t n) { return v < 0 ? 0 : (v > n ? n : v); }
+__device__ __forceinline__ int64_t clampn(int64_t v, int64_t n) { return layout::seg_clamp(v, n); }
 
 // One block of kPlanBlock threads, kPlanPer consecutive segments per thread:
 // unit counts and their exclusive prefix over the segments, a chunk of
@@ -132,23 +132,12 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const int64_t* __restr
   }
 }
 
-// Segment of unit u: the last s with unit_start[s] <= u (non-empty by
-// construction since unit_start[s + 1] > u).
-__device__ __forceinline__ idx_t find_segment(const int64_t* unit_start, int64_t S, int64_t u) {
-  auto us = array(unit_start, S + 1);
-  idx_t lo = 0, hi = S;   // answer in [lo, hi)
-  while (hi - lo > 1) {
-    const idx_t mid = (lo + hi) / 2;
-    if (us[mid] <= u) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 struct UnitInfo {
   idx_t seg, j, begin, len;   // segment, unit index inside it, first position, length
   bool single;                // the segment has one unit only
 };
 
+// Unit u of this block (layout::seg_unit, read by thread 0 and shared).
 template <class C>
 __device__ __forceinline__ bool unit_info(const int64_t* offsets, const int64_t* unit_start,
                                           int64_t n, int64_t S, int64_t total, UnitInfo* out) {
@@ -157,15 +146,10 @@ __device__ __forceinline__ bool unit_info(const int64_t* offsets, const int64_t*
   const idx_t u = block_x().index();
   if (u >= total) return false;
   if (thread.index() == 0) {
-    const idx_t s = find_segment(unit_start, S, u);
-    auto off = array(offsets, S + 1);
-    auto us = array(unit_start, S + 1);
-    const idx_t j = u - us[s];
-    const idx_t b = clampn(off[s], n) + j * C::unit;
-    const idx_t e = clampn(off[s + 1], n);
-    s_info[0] = s; s_info[1] = j; s_info[2] = b;
-    s_info[3] = (e - b) < C::unit ? (e - b) : C::unit;
-    s_info[4] = (us[s + 1] - us[s]) == 1;
+    const layout::SegUnit su =
+        layout::seg_unit(array(offsets, S + 1), array(unit_start, S + 1), n, S, C::unit, u);
+    s_info[0] = su.seg; s_info[1] = su.j; s_info[2] = su.begin;
+    s_info[3] = su.len; s_info[4] = su.single;
   }
   sync(thread);
   *out = UnitInfo{s_info[0], s_info[1], s_info[2], s_info[3], s_info[4] != 0};
@@ -246,17 +230,19 @@ __device__ __forceinline__ uint32_t seg_look_back(const uint64_t* status, idx_t 
                                                   uint32_t max_polls, WsHeader* hdr) {
   const int lane = wave::lane_id();
   uint32_t excl = 0;
-  idx_t pos = u - 1, left = j;        // `left` earlier units still to cover
   auto st = array(status, u);
-  for (uint32_t polls = 0; left > 0; ++polls) {
+  idx_t window = 0;                   // layout::lookback_unit's windows
+  for (uint32_t polls = 0; kWave * window < j; ++polls) {
     if (polls == max_polls) {
       if (lane == 0) set_error(hdr, kDevWaitLimit);
       break;
     }
-    const bool in_seg = lane < left;
-    const uint64_t w = in_seg ? load_status(&st[pos - lane]) : pack(kFlagPrefix, 0u);
+    const bool in_seg = layout::lookback_in_segment(j, window, lane);
+    const uint64_t w =
+        in_seg ? load_status(&st[layout::lookback_unit(u, window, lane)]) : pack(kFlagPrefix, 0u);
     const uint32_t flag = (uint32_t)(w >> 62);
     const uint64_t pmask = __ballot(flag == kFlagPrefix && in_seg);
+    const idx_t left = j - kWave * window;
     const int width = left < kWave ? (int)left : kWave;
     const int first_p = pmask ? __builtin_ctzll(pmask) : width - 1;
     const uint64_t need = first_p == 63 ? ~0ull : ((2ull << first_p) - 1);
@@ -266,8 +252,7 @@ __device__ __forceinline__ uint32_t seg_look_back(const uint64_t* status, idx_t 
     }
     excl += wave::sum_u32(lane <= first_p && in_seg ? (uint32_t)w : 0u);
     if (pmask) break;
-    pos -= width;
-    left -= width;
+    ++window;
   }
   return excl;
 }

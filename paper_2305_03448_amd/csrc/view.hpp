@@ -337,6 +337,30 @@ DESC_HD auto group_by_tile(const View<T, M>& v) {
       .template transpose<1>();            // [R/H][C/W][H][W]
 }
 
+// A window of a row-major matrix read through a hardware buffer range.  The
+// window starts at one element of the matrix (the range's base) and covers
+// `rows` x `cols` valid elements at row stride `ld` (elements of kBytes
+// bytes); the range is bytes() long, ending at the last valid element.  The
+// index map gives the byte offset of (r, c) as row(r) + col(c): inside the
+// range for a valid element; at least kOutside (past any range) for a column
+// c >= cols; and for a row r >= rows past bytes() by itself (when
+// cols <= ld), so a buffer load of an invalid element returns zero without a
+// row test.  The two parts let a kernel compute a lane's column part once
+// and add the row parts of its loads.  Offsets are 32-bit: the caller keeps
+// every row(r) it uses below 2^30 (then kOutside + row(r) < 2^32 too).
+constexpr uint32_t kOutside = 0x80000000u;   // an offset past any range a window uses
+template <int kBytes>
+struct BufferWindow {
+  uint32_t ld;                // row stride, elements
+  int32_t rows, cols;         // valid rows and columns (<= 0: an empty window)
+  DESC_HD uint32_t bytes() const {
+    return rows > 0 && cols > 0 ? ((uint32_t)(rows - 1) * ld + (uint32_t)cols) * kBytes : 0u;
+  }
+  DESC_HD uint32_t row(int32_t r) const { return (uint32_t)r * ld * kBytes; }
+  DESC_HD uint32_t col(int32_t c) const { return c < cols ? (uint32_t)c * kBytes : kOutside; }
+  DESC_HD uint32_t offset(int32_t r, int32_t c) const { return row(r) + col(c); }
+};
+
 // An array of n elements of type T at p (rank 1) or a rows x cols matrix.
 template <class T>
 DESC_HD View<T, Dense<1>> array(T* p, idx_t n) { return {p, {{n}}}; }

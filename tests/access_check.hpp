@@ -11,7 +11,9 @@
 // they come from different resources, at least one is a write, and no
 // barrier orders them -- that is, they are in different groups (blocks never
 // synchronise inside a kernel) or in the same group between the same two
-// barriers.
+// barriers.  Two further orders are known to it: launches on one stream
+// (kernel_boundary), and atomic accesses, which the hardware orders among
+// themselves.
 #pragma once
 #include <cstdio>
 #include <map>
@@ -25,10 +27,18 @@ class Checker {
  public:
   // `group`: the synchronisation group of the resource (its block);
   // `who`: the resource itself (a thread, unique over all groups).
-  void read(long group, long who, const void* addr) { add(group, who, addr, false); }
-  void write(long group, long who, const void* addr) { add(group, who, addr, true); }
+  void read(long group, long who, const void* addr) { add(group, who, addr, false, false); }
+  void write(long group, long who, const void* addr) { add(group, who, addr, true, false); }
+  // An atomic access (a read-modify-write, or a flag word's store or load):
+  // atomics do not conflict with each other, only with plain accesses.
+  void atomic(long group, long who, const void* addr, bool write) {
+    add(group, who, addr, write, true);
+  }
   // Every resource of `group` passes a barrier.
   void sync(long group) { ++epoch_[group]; }
+  // The kernel ends: every access so far is ordered before every later one
+  // (launches on one stream run in order).
+  void kernel_boundary() { ++kernel_; }
 
   struct Conflict {
     const void* addr;
@@ -43,8 +53,8 @@ class Checker {
       for (size_t i = 0; i < v.size() && out.size() < limit; ++i)
         for (size_t j = i + 1; j < v.size() && out.size() < limit; ++j) {
           const Rec &a = v[i], &b = v[j];
-          if (a.who == b.who || !(a.write || b.write)) continue;
-          const bool ordered = a.group == b.group && a.epoch != b.epoch;
+          if (a.who == b.who || !(a.write || b.write) || (a.atomic && b.atomic)) continue;
+          const bool ordered = a.kernel != b.kernel || (a.group == b.group && a.epoch != b.epoch);
           if (!ordered) out.push_back({kv.first, a.who, b.who, a.write && b.write});
         }
     }
@@ -56,15 +66,16 @@ class Checker {
  private:
   struct Rec {
     long group, who;
-    int epoch;
-    bool write;
+    int epoch, kernel;
+    bool write, atomic;
   };
-  void add(long group, long who, const void* addr, bool write) {
-    log_[addr].push_back({group, who, epoch_[group], write});
+  void add(long group, long who, const void* addr, bool write, bool atomic) {
+    log_[addr].push_back({group, who, epoch_[group], kernel_, write, atomic});
     ++count_;
   }
   std::unordered_map<const void*, std::vector<Rec>> log_;
   std::map<long, int> epoch_;
+  int kernel_ = 0;
   size_t count_ = 0;
 };
 

@@ -32,6 +32,22 @@ EXPECTED = [
     "access_check_scan_stores_clean",
     # layouts of the min/max and float-sum kernel and the transposes' tile order
     "reduce_ops_chunk_groups_bijection", "transpose_diagonal_tile_order_bijection",
+    # the fused split staging's buffer windows (gemm_nt.hpp SplitSource)
+    "split_staging_buffer_windows",
+    # the FP32 GEMM's LDS double buffer under its two-stages-ahead schedule
+    "access_check_gemm_double_buffer_clean",
+    "access_check_gemm_double_buffer_without_a_barrier_races",
+    "segmented_units_cover_every_segment_once",
+    "segmented_lookback_windows_stay_in_segment",
+    "access_check_segmented_scan_clean",
+    "access_check_segmented_reduce_clean",
+    "access_check_segmented_reduce_plain_stores_race",
+    "grouped_tile_walk_takes_every_tile_once",
+    "access_check_grouped_walk_clean",
+    "access_check_grouped_walk_without_the_end_barrier_races",
+    "float_scan_handover_waits_on_earlier_tiles_only",
+    "access_check_float_scan_handover_clean",
+    "float_scan_handover_leaves_no_older_word",
 ]
 
 

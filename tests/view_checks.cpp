@@ -527,5 +527,364 @@ int main(int argc, char** argv) {
     check(ok, "transpose_diagonal_tile_order_bijection");
   }
 
+  // --- fused split staging: the buffer windows of A and B ---
+  // For every shape edge a wave can meet, each of the wave's positions is
+  // staged exactly once, a load returns data (offset inside the range) for
+  // exactly the valid positions, and then from the element's own address.
+  {
+    bool ok = true;
+    long checked = 0;
+    const int CPR = 4, KS = 8 * CPR;
+    for (int rows = 0; rows <= 17; ++rows)             // valid rows of A's window (16 staged)
+      for (int cols : {1, 3, 4, 5, 8, 17, 31, 32})     // valid k of the stage
+        for (long ld : {32L, 33L, 100L, 1L << 24}) {
+          if (cols > ld) continue;
+          const BufferWindow<4> w{(uint32_t)ld, rows > 16 ? 16 : rows, cols};
+          Access acc(16 * KS);
+          for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < 8; ++j) {
+              const int r = layout::split_a_row<CPR>(lane), c = layout::split_a_k<CPR>(lane) + j;
+              acc.add(r * KS + c, lane);
+              const uint32_t off = w.row(r) + w.col(c);
+              const bool valid = r < w.rows && c < w.cols;
+              ok &= (off < w.bytes()) == valid;
+              if (valid) ok &= off == (uint32_t)((r * ld + c) * 4);
+              ++checked;
+            }
+          ok &= acc.bijection();
+        }
+    for (int rows = 0; rows <= 8; ++rows)              // valid k of B's octet
+      for (int cols = -3; cols <= 64; cols += 1)       // valid columns of the wave (<= 0: none)
+        for (long ld : {64L, 65L, 1000L, 1L << 24}) {
+          const BufferWindow<4> w{(uint32_t)ld, rows, cols};
+          Access acc(8 * 64);
+          for (int lane = 0; lane < 64; ++lane)
+            for (int j = 0; j < 8; ++j) {
+              const int c = layout::split_b_col(lane);
+              acc.add(j * 64 + c, lane);
+              const uint32_t off = w.row(j) + w.col(c);
+              const bool valid = j < w.rows && c < w.cols;
+              ok &= (off < w.bytes()) == valid;
+              if (valid) ok &= off == (uint32_t)((j * ld + c) * 4);
+              ++checked;
+            }
+          ok &= acc.bijection();
+        }
+    check(ok, "split_staging_buffer_windows", std::to_string(checked) + " positions");
+  }
+
+  // --- FP32 GEMM, row-major tile: the LDS double buffer under the two-stages-ahead
+  // schedule (gemm_f32.hpp tile_rowmajor), 256 x 128 x 16 with 2 x 2 waves.  Every
+  // stage's fragment reads find words written by an earlier phase, and no read meets
+  // a write of the same buffer between the same two barriers; dropping any one of
+  // the loop's barriers makes the next phase's stores race its reads.
+  {
+    constexpr int BM = 256, BN = 128, BK = 16, WM = 2, WN = 2, T = 64 * WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 32, FN = WTN / 32;
+    constexpr int PA = BK + 4, PB = BN + 4, AV = BM * BK / 4 / T, BV = BK * BN / 4 / T;
+    auto replay = [&](int nk, int drop_barrier, long* uninit) {
+      std::vector<float> lds(2 * BM * PA + 2 * BK * PB);
+      std::vector<char> written(lds.size(), 0);
+      auto a_lds = matrices(lds.data(), 2, BM, PA);
+      auto b_lds = matrices(lds.data() + 2 * BM * PA, 2, BK, PB);
+      access_check::Checker c;
+      int barrier_no = 0;
+      auto sync_ = [&]() { if (barrier_no++ != drop_barrier) c.sync(0); };
+      auto store = [&](int buf) {
+        for (int t = 0; t < T; ++t) {
+          for (int i = 0; i < AV; ++i) {
+            const int q = t + T * i;
+            for (int e = 0; e < 4; ++e) {
+              float* w = &a_lds.idx(buf).at(layout::gemm_store_row<BK>(q), layout::gemm_store_word<BK>(q) + e);
+              c.write(0, t, w); written[w - lds.data()] = 1;
+            }
+          }
+          for (int i = 0; i < BV; ++i) {
+            const int q = t + T * i;
+            for (int e = 0; e < 4; ++e) {
+              float* w = &b_lds.idx(buf).at(layout::gemm_store_row<BN>(q), layout::gemm_store_word<BN>(q) + e);
+              c.write(0, t, w); written[w - lds.data()] = 1;
+            }
+          }
+        }
+      };
+      auto compute = [&](int buf) {
+        for (int t = 0; t < T; ++t) {
+          const int w = t / 64, l = t % 64, half = l / 32, c32 = l % 32, wm = w / WN, wn = w % WN;
+          for (int k4 = 0; k4 < BK / 2; k4 += 4) {
+            for (int i = 0; i < FM; ++i)
+              for (int e = 0; e < 4; ++e) {
+                float* r = &a_lds.idx(buf).at(layout::gemm_a_frag_row<WTM>(wm, i, c32),
+                                              layout::gemm_frag_k<BK>(half, k4) + e);
+                c.read(0, t, r); *uninit += !written[r - lds.data()];
+              }
+            for (int kk = 0; kk < 4; ++kk)
+              for (int j = 0; j < FN; ++j) {
+                float* r = &b_lds.idx(buf).at(layout::gemm_frag_k<BK>(half, k4) + kk,
+                                              layout::gemm_b_frag_word<WTN>(wn, j, c32));
+                c.read(0, t, r); *uninit += !written[r - lds.data()];
+              }
+          }
+        }
+      };
+      // the schedule of tile_rowmajor with kDepth = 2
+      store(0);
+      sync_();
+      int kt = 0;
+      for (; kt + 3 < nk; kt += 2) {
+        compute(0); store(1); sync_();
+        compute(1); store(0); sync_();
+      }
+      if (kt < nk) { compute(0); if (kt + 1 < nk) store(1); sync_(); }
+      if (kt + 1 < nk) { compute(1); if (kt + 2 < nk) store(0); sync_(); }
+      if (kt + 2 < nk) { compute(0); sync_(); }
+      return std::make_pair(c.conflicts(64).size(), barrier_no);
+    };
+    bool ok = true;
+    long uninit = 0;
+    int barriers = 0;
+    for (int nk : {1, 2, 3, 4, 5, 6, 7}) {
+      auto r = replay(nk, -1, &uninit);
+      ok &= r.first == 0;
+      barriers = r.second;
+    }
+    check(ok && uninit == 0, "access_check_gemm_double_buffer_clean");
+    bool all_racy = true;
+    for (int drop = 0; drop < barriers - 1; ++drop) {
+      long u = 0;
+      all_racy &= replay(7, drop, &u).first > 0;
+    }
+    check(all_racy, "access_check_gemm_double_buffer_without_a_barrier_races");
+  }
+
+  // --- segmented forms (segmented.hip): the unit map, the look-back windows and the
+  // stores, with a unit of 2 waves x 2 rounds x 256 = 1024 elements (the kernels'
+  // maps are templated on the unit).  Segments: empty, one element, unit edges, a
+  // segment of 67 units (two look-back windows), at an offset inside the array.
+  {
+    constexpr int W = 2, Rr = 2, U = W * Rr * 256, TPB = W * 64;
+    const std::vector<long> lens = {0, 1, 1023, 1024, 1025, 0, 3000, 67 * U - 5, 0, 2048, 7};
+    const long S = (long)lens.size(), off0 = 5;
+    std::vector<int64_t> off(S + 1);
+    off[0] = off0;
+    for (long s2 = 0; s2 < S; ++s2) off[s2 + 1] = off[s2] + lens[s2];
+    const long n = off[S] + 13;
+    // the plan: unit counts and their exclusive prefix (plan_kernel)
+    std::vector<int64_t> us(S + 1, 0);
+    for (long s2 = 0; s2 < S; ++s2)
+      us[s2 + 1] = us[s2] + layout::seg_units(layout::seg_clamp(off[s2 + 1], n) -
+                                                  layout::seg_clamp(off[s2], n), U);
+    const long units = us[S];
+    std::vector<int> in(n), out(n);
+    std::vector<uint64_t> status(units);
+    std::vector<int64_t> red(S);
+    auto offv = array(off.data(), S + 1);
+    auto usv = array(us.data(), S + 1);
+    // scan: the plan clears the status words; then each unit stores its flag
+    // word(s), walks its look-back windows, loads and stores its elements
+    access_check::Checker c;
+    for (long u = 0; u < units; ++u) c.write(0, u % 1024, &status[u]);
+    c.kernel_boundary();
+    Access cover(n);
+    bool windows_ok = true, map_ok = true;
+    for (long u = 0; u < units; ++u) {
+      const layout::SegUnit su = layout::seg_unit(offv, usv, n, S, U, u);
+      map_ok &= su.seg >= 0 && su.seg < S && su.j >= 0 && su.len > 0 && su.len <= U &&
+                su.begin >= off[su.seg] && su.begin + su.len <= off[su.seg + 1];
+      const long lane0 = u * TPB;
+      c.atomic(u, lane0, &status[u], true);                 // aggregate, or the prefix at j = 0
+      std::set<long> seen;
+      for (long w = 0; 64 * w < su.j; ++w)                  // every window (no prefix found early)
+        for (int l = 0; l < 64; ++l)
+          if (layout::lookback_in_segment(su.j, w, l)) {
+            const long v = layout::lookback_unit(u, w, l);
+            windows_ok &= v >= us[su.seg] && v < u && seen.insert(v).second;
+            if (v >= 0 && v < units) c.atomic(u, lane0 + l, &status[v], false);
+          }
+      windows_ok &= (long)seen.size() == su.j;
+      if (su.j > 0) c.atomic(u, lane0, &status[u], true);   // the inclusive prefix
+      for (int wv = 0; wv < W; ++wv)
+        for (int l = 0; l < 64; ++l) {
+          auto mine = layout::wave_striped<W, Rr>(array(out.data() + su.begin, U).group<4>(), 0,
+                                                  R<Level::Wave>(wv, W), R<Level::Thread>(l, 64));
+          auto mine_in = layout::wave_striped<W, Rr>(array(in.data() + su.begin, U).group<4>(), 0,
+                                                     R<Level::Wave>(wv, W), R<Level::Thread>(l, 64));
+          for (int r = 0; r < Rr; ++r)
+            for (int k = 0; k < 4; ++k) {
+              auto g = mine.idx(r);
+              if (g.pos(k) >= su.len) continue;
+              c.read(u, lane0 + wv * 64 + l, &mine_in.idx(r)[k]);
+              c.write(u, lane0 + wv * 64 + l, &g[k]);
+              cover.add(&g[k] - out.data(), u);
+            }
+        }
+    }
+    // every position of every segment is stored exactly once, nothing else
+    long outside = 0, in_seg = 0;
+    for (long i = 0; i < n; ++i) {
+      const bool inside = i >= off[0] && i < off[S];
+      in_seg += inside;
+      outside += !inside && cover.owner[i] >= 0;
+      map_ok &= !inside || cover.owner[i] >= 0;
+    }
+    check(map_ok && outside == 0 && cover.collisions == 0 && cover.touched == in_seg,
+          "segmented_units_cover_every_segment_once",
+          std::to_string(units) + " units, " + std::to_string(in_seg) + " positions");
+    check(windows_ok, "segmented_lookback_windows_stay_in_segment");
+    check(c.conflicts(64).empty(), "access_check_segmented_scan_clean",
+          std::to_string(c.accesses()) + " accesses");
+    // reduce: the plan zeroes the outputs of segments without exactly one
+    // unit; a single-unit segment's block stores its sum, the others add
+    // atomically.  Every output is then written (a store, or zero and adds);
+    // plain stores from several units of one segment would race.
+    auto reduce_access = [&](bool plain_everywhere, long* unset) {
+      access_check::Checker r;
+      std::vector<char> zeroed(S, 0), stored(S, 0);
+      for (long s2 = 0; s2 < S; ++s2)
+        if (us[s2 + 1] - us[s2] != 1) { r.write(0, s2 / 4, &red[s2]); zeroed[s2] = 1; }
+      r.kernel_boundary();
+      for (long u = 0; u < units; ++u) {
+        const layout::SegUnit su = layout::seg_unit(offv, usv, n, S, U, u);
+        if (su.single || plain_everywhere) { r.write(u, u * TPB, &red[su.seg]); stored[su.seg] = 1; }
+        else r.atomic(u, u * TPB, &red[su.seg], true);
+      }
+      *unset = 0;
+      for (long s2 = 0; s2 < S; ++s2) *unset += !(zeroed[s2] || stored[s2]);
+      return r.conflicts(64).size();
+    };
+    long unset = 0, unset2 = 0;
+    const size_t rc = reduce_access(false, &unset);
+    const size_t rr = reduce_access(true, &unset2);
+    check(rc == 0 && unset == 0, "access_check_segmented_reduce_clean");
+    check(rr > 0, "access_check_segmented_reduce_plain_stores_race", std::to_string(rr) + " conflicts");
+  }
+
+  // --- the grouped GEMM's persistent tile walk (grouped.hip): every tile of the
+  // planned sequence is taken by exactly one block, runs of 64 stay on one XCD, and
+  // the tiles' output regions partition every problem's C.  Within a block, thread 0
+  // publishes the tile's slot in LDS and all threads read it after a barrier; the
+  // barrier that ends each tile orders those reads before the next tile's store.
+  {
+    struct P { long M, N; };
+    const std::vector<P> probs = {{130, 70}, {64, 64}, {1, 1}, {0, 5}, {200, 129}, {640, 64}, {65, 700}};
+    const long G = (long)probs.size(), E = 64, TH = 256;
+    std::vector<int64_t> ts(G + 1, 0);
+    for (long g = 0; g < G; ++g)
+      ts[g + 1] = ts[g] + ((probs[g].M + E - 1) / E) * ((probs[g].N + E - 1) / E);
+    const long T = ts[G];
+    std::vector<std::vector<float>> C(G);
+    for (long g = 0; g < G; ++g) C[g].assign(std::max(0L, probs[g].M * probs[g].N), 0.f);
+    auto walk_access = [&](long B, bool end_barrier, bool* ok) {
+      access_check::Checker c;
+      std::vector<long> taken(T, -1);
+      std::vector<int64_t> s_slot(B);
+      for (long b = 0; b < B; ++b) {
+        const layout::TileWalk wk = layout::tile_walk(b, B);
+        long prev = -1;
+        for (long l = wk.first;; l += wk.per) {
+          const long t = wk.tile(l);
+          if (t >= T) break;
+          *ok &= t > prev && taken[t] < 0;
+          if (wk.by_xcd) *ok &= (t / 64) % 8 == b % 8;
+          prev = t;
+          taken[t] = b;
+          c.write(b, b * TH, &s_slot[b]);
+          c.sync(b);
+          const long slot = layout::seg_of_unit(array(ts.data(), G + 1), G, t);
+          *ok &= ts[slot] <= t && t < ts[slot + 1];
+          const P& p = probs[slot];
+          const long tn = (p.N + E - 1) / E, local = t - ts[slot];
+          const long tm = local / tn, tc = local % tn;
+          auto cm = matrix(C[slot].data(), p.M, p.N);
+          for (long th = 0; th < TH; ++th) {
+            c.read(b, b * TH + th, &s_slot[b]);
+            for (long i = th; i < E * E; i += TH) {
+              const long r = tm * E + i / E, col = tc * E + i % E;
+              if (r < p.M && col < p.N) c.write(b, b * TH + th, &cm.at(r, col));
+            }
+          }
+          if (end_barrier) c.sync(b);
+        }
+      }
+      for (long t = 0; t < T; ++t) *ok &= taken[t] >= 0;
+      return c;
+    };
+    bool ok = true, clean = true, racy = true;
+    long writes = 0;
+    for (long B : {1L, 3L, 7L, 8L, 16L, 24L, 64L}) {
+      auto c = walk_access(B, true, &ok);
+      clean &= c.conflicts(64).empty();
+      writes += c.accesses();
+      bool ok2 = true;
+      racy &= !walk_access(B, false, &ok2).conflicts(64).empty() || T <= B;
+    }
+    // every element of every C written (the tiles cover it; the checker saw no
+    // second writer of any element)
+    long total = 0;
+    for (long g = 0; g < G; ++g) total += std::max(0L, probs[g].M * probs[g].N);
+    check(ok, "grouped_tile_walk_takes_every_tile_once", std::to_string(T) + " tiles");
+    check(clean, "access_check_grouped_walk_clean", std::to_string(total) + " outputs per grid");
+    check(racy, "access_check_grouped_walk_without_the_end_barrier_races");
+  }
+
+  // --- the float scan's hand-over (scan_f32.hip): every slot a tile waits for is
+  // published once in the call, by a tile with a smaller index (so the waits end
+  // when earlier tiles run); publications and polls are atomics, and the last tile's
+  // clear of [used, hw) touches none of the call's words.  Over calls of changing
+  // size, every word past the call's region is zero when the call ends, so no word
+  // outlives the call after the one that wrote it.
+  {
+    constexpr int K = 4;                         // a small group, so that calls span many
+    bool waits_ok = true, clean = true, stale_ok = true;
+    std::vector<long> gen_of(2 * 300 + 2 * 80, 0);   // generation of each word's tag (0: zero)
+    uint64_t hw = 0;
+    long gen = 0;
+    for (long T : {200L, 65L, 1L, 130L, 4L, 5L, 257L, 3L}) {
+      ++gen;
+      const long groups = (T + K - 1) / K;
+      std::vector<long> agg_pub(T, -1), grp_pub(groups, -1);
+      std::vector<uint64_t> words(gen_of.size());
+      auto ag = array(words.data(), 2 * T).group<2>();
+      auto gq = array(words.data() + 2 * T, 2 * groups).group<2>();
+      access_check::Checker c;
+      // publications (lane 0 of wave 0 of each tile)
+      for (long t = 0; t < T; ++t) {
+        for (int h = 0; h < 2; ++h) c.atomic(t, t * 64, &ag.idx(t)[h], true);
+        agg_pub[t] = t;
+        if (layout::handover_publishes_group<K>(t, T)) {
+          const long g = t / K;
+          waits_ok &= grp_pub[g] < 0;
+          grp_pub[g] = t;
+          for (int h = 0; h < 2; ++h) c.atomic(t, t * 64, &gq.idx(g)[h], true);
+        }
+      }
+      // polls: every awaited slot has one publisher with a smaller index
+      for (long t = 0; t < T; ++t) {
+        const long g = t / K, pos = t % K;
+        for (int l = 0; l < pos; ++l) {
+          const long peer = layout::handover_peer<K>(t, l);
+          waits_ok &= peer >= 0 && peer < t && agg_pub[peer] == peer;
+          for (int h = 0; h < 2; ++h) c.atomic(t, t * 64 + l, &ag.idx(peer)[h], false);
+        }
+        if (g > 0) {
+          waits_ok &= grp_pub[g - 1] >= 0 && grp_pub[g - 1] < t;
+          for (int h = 0; h < 2; ++h) c.atomic(t, t * 64, &gq.idx(g - 1)[h], false);
+        }
+      }
+      // the last tile clears [used, hw) with plain stores and raises hw to used
+      const uint64_t used = (uint64_t)layout::handover_words<K>(T);
+      waits_ok &= (uint64_t)(&gq.idx(groups - 1)[1] - words.data()) + 1 == used;
+      for (uint64_t i = used; i < hw; ++i) c.write(T - 1, (T - 1) * 64 + (long)(i % 64), &words[i]);
+      clean &= c.conflicts(16).empty();
+      for (uint64_t i = 0; i < used; ++i) gen_of[i] = gen;
+      for (uint64_t i = used; i < hw; ++i) gen_of[i] = 0;
+      hw = used;
+      for (size_t i = 0; i < gen_of.size(); ++i) stale_ok &= gen_of[i] == (i < used ? gen : 0);
+    }
+    check(waits_ok, "float_scan_handover_waits_on_earlier_tiles_only");
+    check(clean, "access_check_float_scan_handover_clean");
+    check(stale_ok, "float_scan_handover_leaves_no_older_word");
+  }
+
   return g_fail;
 }
