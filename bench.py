@@ -47,10 +47,23 @@ STEP_BYTES = SCAN_BYTES + TRANSPOSE_BYTES
 
 # HBM traffic of one scan launch from rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by what the counter reads for the copy kernel of known size
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), taken for ScanCfg<1024, 16, true>;
-# None when the kernel has changed since the counters were taken.
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0), taken for ScanCfg<1024, 16, true>
+# built from the sources whose hash is SCAN_TRAFFIC_SRC_HASH; reported as
+# None once the kernel's sources (or its configuration) have changed.
 SCAN_TRAFFIC_BYTES = 2152064430
 SCAN_TRAFFIC_CONFIG = "b1024_r16_nt"
+SCAN_TRAFFIC_SRC_HASH = None
+SCAN_SOURCES = ("scan.hip", "lookback.hpp", "common.hpp", "layouts.hpp", "view.hpp", "wave.hpp")
+
+
+def scan_source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the scan kernel's source files."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in SCAN_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_03448_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg: str) -> None:
@@ -131,9 +144,11 @@ def op_views(desc, torch, workloads, reps: int = 100):
     """The evaluation of Sec. 5 on this GPU: the library's view kernels against
     their hand-indexed twins (same algorithm and configuration, indices
     written by hand; the library is set to the twins' configurations for the
-    comparison), for 256 MB, 512 MB and 1 GB of memory per operation,
-    100 runs each, alternating the two; reported as median kernel times and
-    the relative runtime hand / view (above 1: the view kernel is faster)."""
+    comparison), for 256 MB, 512 MB and 1 GB of memory per operation (for
+    the FP32 GEMM: n x n operands with 3 n^2 words within that size, n =
+    4608, 6528, 9216), 100 runs each, alternating the two; reported as median
+    kernel times and the relative runtime hand / view (above 1: the view
+    kernel is faster)."""
     import statistics
     sys.path.insert(0, os.path.join(ROOT, "tests", "handwritten"))
     import handlib
@@ -159,7 +174,15 @@ def op_views(desc, torch, workloads, reps: int = 100):
         y1, y2 = torch.empty_like(xs), torch.empty_like(xs)
         t1 = torch.empty((m.shape[1], m.shape[0]), dtype=torch.float32, device="cuda")
         t2 = torch.empty_like(t1)
+        # matrix multiplication: A, B, C of n x n FP32 taking the memory size
+        gn = {256: 4608, 512: 6528, 1024: 9216}[mb]
+        ga = torch.from_numpy(workloads.matrix_f32(gn, gn, seed=4)).cuda()
+        gb = torch.from_numpy(workloads.matrix_f32(gn, gn, seed=5)).cuda()
+        gc1, gc2 = torch.empty_like(ga), torch.empty_like(ga)
         cases = [
+            ("gemm_f32", lambda: desc.desc_gemm(ga, gb, gc1, mode="f32"),
+             lambda: handlib.gemm_f32(ga, gb, gc2),
+             lambda: torch.equal(gc1.view(torch.int32), gc2.view(torch.int32))),
             ("reduce", lambda: desc.desc_reduce_i32(x, r1), lambda: handlib.reduce_i32(x, r2),
              lambda: torch.equal(r1, r2)),
             ("scan", lambda: desc.desc_scan_i32(xs, y1), lambda: handlib.scan_i32(xs, y2),
@@ -178,11 +201,12 @@ def op_views(desc, torch, workloads, reps: int = 100):
             torch.cuda.synchronize()
             mv, mh = median_ms(tv), median_ms(th)
             r = {"op": name, "memory_MB": mb, "view_us": round(mv * 1e3, 2),
+                 **({"n": gn} if name == "gemm_f32" else {}),
                  "hand_us": round(mh * 1e3, 2), "hand_over_view": round(mh / mv, 4),
                  "equal": bool(check())}
             log(f"views {r}")
             results.append(r)
-        del x, xs, m, y1, y2, t1, t2
+        del x, xs, m, y1, y2, t1, t2, ga, gb, gc1, gc2
         torch.cuda.empty_cache()
     for op in handlib.VIEW_CONFIGS:
         for cls in range(4):
@@ -607,7 +631,8 @@ def main(argv=None):
     value = STEP_BYTES / (ms_per_step * 1e-3) / 1e9
     scan_cfg = desc.desc_config_name(
         "scan_i32", desc.desc_config_get("scan_i32", desc.desc_size_class("scan_i32", SCAN_N)))
-    traffic = SCAN_TRAFFIC_BYTES if scan_cfg == SCAN_TRAFFIC_CONFIG else None
+    traffic = (SCAN_TRAFFIC_BYTES if scan_cfg == SCAN_TRAFFIC_CONFIG
+               and scan_source_hash() == SCAN_TRAFFIC_SRC_HASH else None)
     scan_gbs = SCAN_BYTES / (scan_ms * 1e-3) / 1e9
     tr_gbs = TRANSPOSE_BYTES / (tr_ms * 1e-3) / 1e9
     result = {

@@ -10,7 +10,10 @@
 //   scan       1024 threads x 16 rounds x 4 int32 per tile (64K elements),
 //              non-temporal loads and stores, 256-word look-back window
 //              (the configuration the library runs from 2^24 elements);
-//   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32].
+//   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32];
+//   FP32 GEMM  256 x 128 x 16 tiles, 2 x 2 waves, A row-major in LDS, loads
+//              two stages ahead (the configuration the library runs from
+//              2^30 M N K on).
 // Only the index expressions differ: here they are written out by hand
 // instead of being derived from a composition of views.  The helpers shared
 // with the library (relaxed status-word atomics, DPP wave sums) hold no index
@@ -324,6 +327,175 @@ __global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restri
   }
 }
 
+// ---------------------------------------------------------------- FP32 GEMM
+// Twin of gemm_f32w_kernel<GemmCfgF32W<256, 128, 16, 2, 2, 2>> (the library's
+// FP32 GEMM from 2^30 M N K on): 256 threads as 2 x 2 waves of 128 x 64, A
+// staged in LDS as [m][k] (pitch 20 words) and B as [k][n] (pitch 132), two
+// LDS buffers, loads two stages ahead through two register sets, the
+// matrix instruction's two k slots taking the two halves of a stage.
+constexpr int kGM = 256, kGN = 128, kGK = 16, kGT = 256, kGWN = 2;
+constexpr int kGWTM = kGM / 2, kGWTN = kGN / 2, kGFM = kGWTM / 32, kGFN = kGWTN / 32;
+constexpr int kGPA = kGK + 4, kGPB = kGN + 4;
+constexpr int kGAV = kGM * kGK / 4 / kGT, kGBV = kGK * kGN / 4 / kGT;
+constexpr int kGLds = 2 * kGM * kGPA + 2 * kGK * kGPB;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int64_t gemm_tile_of(int64_t u, int64_t tiles_m, int64_t tiles_n) {
+  const int64_t T = tiles_m * tiles_n;
+  if (T % 8 == 0) u = (u % 8) * (T / 8) + u / 8;
+  const int64_t per_group = 8 * tiles_n, g = u / per_group, first_m = g * 8;
+  const int64_t gsize = tiles_m - first_m < 8 ? tiles_m - first_m : 8;
+  const int64_t r = u - g * per_group;
+  return (first_m + r % gsize) * tiles_n + r / gsize;
+}
+
+template <bool kVec>
+__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(2)))
+void gemm_f32_hand(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                   int64_t ldb, float* __restrict__ Cm, int64_t ldc, int64_t M, int64_t N,
+                   int64_t K) {
+  __shared__ __attribute__((aligned(16))) float lds[kGLds];
+  float* const a_lds = lds;                          // [2][256][20]
+  float* const b_lds = lds + 2 * kGM * kGPA;         // [2][16][132]
+  const int64_t tiles_n = (N + kGN - 1) / kGN;
+  const int64_t t = gemm_tile_of(blockIdx.x, (M + kGM - 1) / kGM, tiles_n);
+  const int64_t m0 = t / tiles_n * kGM, n0 = t % tiles_n * kGN;
+  const int tid = (int)threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int half = lane / 32, col32 = lane % 32, wm = w / kGWN, wn = w % kGWN;
+  struct Regs {
+    f32x4 a[kGAV], b[kGBV];
+  };
+  Regs R0, R1;
+  auto load = [&](int64_t kt, Regs& R) {
+    const int64_t k0 = kt * kGK;
+#pragma unroll
+    for (int i = 0; i < kGAV; ++i) {
+      const int q = tid + kGT * i;
+      const int64_t r = m0 + q / (kGK / 4), c = k0 + 4 * (q % (kGK / 4));
+      if constexpr (kVec) {
+        const bool in = r < M && c < K;
+        const f32x4 v = *(const f32x4*)(A + (r < M ? r : M - 1) * lda + (c < K ? c : K - 4));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.a[i][j] = in ? v[j] : 0.f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.a[i][j] = (r < M && c + j < K) ? A[r * lda + c + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kGBV; ++i) {
+      const int q = tid + kGT * i;
+      const int64_t r = k0 + q / (kGN / 4), c = n0 + 4 * (q % (kGN / 4));
+      if constexpr (kVec) {
+        const bool in = r < K && c < N;
+        const f32x4 v = *(const f32x4*)(B + (r < K ? r : K - 1) * ldb + (c < N ? c : N - 4));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.b[i][j] = in ? v[j] : 0.f;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) R.b[i][j] = (r < K && c + j < N) ? B[r * ldb + c + j] : 0.f;
+      }
+    }
+  };
+  auto store = [&](const Regs& R, int buf) {
+#pragma unroll
+    for (int i = 0; i < kGAV; ++i) {
+      const int q = tid + kGT * i;
+      *(f32x4*)(a_lds + (buf * kGM + q / (kGK / 4)) * kGPA + 4 * (q % (kGK / 4))) = R.a[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kGBV; ++i) {
+      const int q = tid + kGT * i;
+      *(f32x4*)(b_lds + (buf * kGK + q / (kGN / 4)) * kGPB + 4 * (q % (kGN / 4))) = R.b[i];
+    }
+  };
+  f32x16 acc[kGFM][kGFN];
+#pragma unroll
+  for (int i = 0; i < kGFM; ++i)
+#pragma unroll
+    for (int j = 0; j < kGFN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int k4 = 0; k4 < kGK / 2; k4 += 4) {
+      f32x4 a[kGFM];
+#pragma unroll
+      for (int i = 0; i < kGFM; ++i)
+        a[i] = *(const f32x4*)(a_lds + (buf * kGM + wm * kGWTM + i * 32 + col32) * kGPA +
+                               half * (kGK / 2) + k4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        float b[kGFN];
+#pragma unroll
+        for (int j = 0; j < kGFN; ++j)
+          b[j] = b_lds[(buf * kGK + half * (kGK / 2) + k4 + kk) * kGPB + wn * kGWTN + j * 32 + col32];
+#pragma unroll
+        for (int i = 0; i < kGFM; ++i)
+#pragma unroll
+          for (int j = 0; j < kGFN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  };
+  const int64_t nk = (K + kGK - 1) / kGK;
+  if (nk > 0) {
+    load(0, R0);
+    store(R0, 0);
+  }
+  if (nk > 1) load(1, R1);
+  __syncthreads();
+  int64_t kt = 0;
+  for (; kt + 3 < nk; kt += 2) {
+    load(kt + 2, R0);
+    compute(0);
+    store(R1, 1);
+    __syncthreads();
+    load(kt + 3, R1);
+    compute(1);
+    store(R0, 0);
+    __syncthreads();
+  }
+  if (kt < nk) {
+    if (kt + 2 < nk) load(kt + 2, R0);
+    compute(0);
+    if (kt + 1 < nk) store(R1, 1);
+    __syncthreads();
+  }
+  if (kt + 1 < nk) {
+    compute(1);
+    if (kt + 2 < nk) store(R0, 0);
+    __syncthreads();
+  }
+  if (kt + 2 < nk) {
+    compute(0);
+    __syncthreads();
+  }
+  // accumulator register r of lane l: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+  if (m0 + kGM <= M && n0 + kGN <= N) {
+#pragma unroll
+    for (int i = 0; i < kGFM; ++i)
+#pragma unroll
+      for (int j = 0; j < kGFN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          Cm[(m0 + wm * kGWTM + i * 32 + 8 * (r / 4) + 4 * half + r % 4) * ldc + n0 + wn * kGWTN +
+             j * 32 + col32] = acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < kGFM; ++i)
+#pragma unroll
+      for (int j = 0; j < kGFN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * kGWTM + i * 32 + 8 * (r / 4) + 4 * half + r % 4;
+          const int64_t col = n0 + wn * kGWTN + j * 32 + col32;
+          if (row < M && col < N) Cm[row * ldc + col] = acc[i][j][r];
+        }
+  }
+}
+
 // ---------------------------------------------------------------- e4m3 check
 // The library's e4m3 quantisers use the hardware conversion for groups whose
 // magnitudes are all finite and <= 448 and the software encoder otherwise.
@@ -447,6 +619,21 @@ int hand_transpose_f32(const float* in, float* out, int64_t rows, int64_t cols, 
   else
     hipLaunchKernelGGL(hand::transpose32_hand<false>, grid, dim3(256), 0, s,
                        (const uint32_t*)in, (uint32_t*)out, rows, cols);
+  return (int)hipGetLastError();
+}
+
+int hand_gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, float* C,
+                  int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s) {
+  if (M == 0 || N == 0) return 0;
+  const int64_t tiles = ((M + hand::kGM - 1) / hand::kGM) * ((N + hand::kGN - 1) / hand::kGN);
+  const bool vec = ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && lda % 4 == 0 &&
+                   ldb % 4 == 0 && K % 4 == 0 && N % 4 == 0 && K > 0;
+  if (vec)
+    hipLaunchKernelGGL(hand::gemm_f32_hand<true>, dim3((unsigned)tiles), dim3(hand::kGT), 0, s, A,
+                       lda, B, ldb, C, ldc, M, N, K);
+  else
+    hipLaunchKernelGGL(hand::gemm_f32_hand<false>, dim3((unsigned)tiles), dim3(hand::kGT), 0, s,
+                       A, lda, B, ldb, C, ldc, M, N, K);
   return (int)hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(HERE, "libdesc_hand.so")
 
 # The one configuration of each library kernel that the twins mirror; the
 # comparison sets the library to these.
-VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b1024_r16_nt", "transpose_32": "t128"}
+VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b1024_r16_nt", "transpose_32": "t128",
+                "gemm_f32": "m256n128k16_rm_d2"}
 
 
 def build() -> str:
@@ -58,6 +59,9 @@ def lib() -> ctypes.CDLL:
                                         c.c_void_p]),
             ("hand_transpose_f32", c.c_int, [c.c_void_p, c.c_void_p, c.c_int64, c.c_int64,
                                              c.c_void_p]),
+            ("hand_gemm_f32", c.c_int, [c.c_void_p, c.c_int64, c.c_void_p, c.c_int64,
+                                        c.c_void_p, c.c_int64, c.c_int64, c.c_int64, c.c_int64,
+                                        c.c_void_p]),
             ("hand_e4m3_all_inputs", c.c_int, [c.c_void_p, c.c_void_p]),
             ("hand_bf16_all_inputs", c.c_int, [c.c_void_p, c.c_void_p]),
         ):
@@ -120,6 +124,21 @@ def transpose_f32(x, out):
     _check(lib().hand_transpose_f32(x.data_ptr(), out.data_ptr(), x.shape[0], x.shape[1],
                                     _stream(x)), "hand_transpose_f32")
     return out
+
+
+def gemm_f32(A, B, C):
+    """C = A @ B (contiguous row-major float32 GPU tensors) with the twin of
+    the library's 256 x 128 x 16 row-major FP32 tile."""
+    import torch
+    for t, name in ((A, "A"), (B, "B"), (C, "C")):
+        _contig(t, torch.float32, name)
+    M, K = A.shape
+    N = B.shape[1]
+    if tuple(B.shape) != (K, N) or tuple(C.shape) != (M, N):
+        raise ValueError("shapes must be A (M,K), B (K,N), C (M,N)")
+    _check(lib().hand_gemm_f32(A.data_ptr(), K, B.data_ptr(), N, C.data_ptr(), N, M, N, K,
+                               _stream(A)), "hand_gemm_f32")
+    return C
 
 
 def e4m3_all_inputs():

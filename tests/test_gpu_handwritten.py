@@ -64,6 +64,30 @@ def test_hand_equals_view_at_comparison_sizes():
     assert torch.equal(t1.view(torch.int32), t2.view(torch.int32))
 
 
+@pytest.mark.parametrize("M,N,K", [(256, 128, 16), (300, 200, 50), (1000, 1000, 1000),
+                                   (513, 129, 257), (4, 4, 4)])
+def test_hand_gemm_equals_the_view_gemm(M, N, K):
+    # same tile, same k assignment, same accumulation order: bit-equal
+    case(f"hand vs view gemm f32 {M}x{N}x{K}")
+    A = to_dev(workloads.matrix_f32(M, K, seed=302)); B = to_dev(workloads.matrix_f32(K, N, seed=303))
+    C1 = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
+    C2 = torch.full((M, N), float("nan"), dtype=torch.float32, device=dev())
+    cls = desc.desc_size_class("gemm_f32", M * N * K)
+    cfg = [desc.desc_config_name("gemm_f32", i) for i in range(desc.desc_config_count("gemm_f32"))]
+    try:
+        desc.desc_config_set("gemm_f32", cls, cfg.index(handlib.VIEW_CONFIGS["gemm_f32"]))
+        desc.desc_gemm(A, B, C1, mode="f32")
+    finally:
+        desc.desc_config_set("gemm_f32", cls, -1)
+    handlib.gemm_f32(A, B, C2)
+    torch.cuda.synchronize()
+    assert torch.equal(C1.view(torch.int32), C2.view(torch.int32))
+    Ai = workloads.rng(304).integers(-4, 5, (M, K)).astype(np.float32)
+    Bi = workloads.rng(305).integers(-4, 5, (K, N)).astype(np.float32)
+    handlib.gemm_f32(to_dev(Ai), to_dev(Bi), C2)
+    assert np.array_equal(C2.cpu().numpy(), (Ai.astype(np.int64) @ Bi.astype(np.int64)).astype(np.float32))
+
+
 def test_hardware_e4m3_matches_encoder_on_every_input():
     # the quantisers use the hardware conversion only where this holds
     case("e4m3 hardware vs software over all 2^32 inputs")

@@ -17,7 +17,10 @@ written out), and compared kernel by kernel:
     applies to the once-per-call ragged-tail path (measured: the reduction is
     identical, the transpose is 2 % shorter with views, the scan's vector
     kernel is 12 % longer, all of it in the tail path, which executes for
-    one tile per call).
+    one tile per call; the GEMM's element-guarded form, for unaligned
+    operands or K, N not multiples of 4, guards its loads with branches where
+    the compiler turns the twin's into selects: 10 % more instructions; its
+    aligned form, which the comparison times, matches the twin within one).
 
 The executed instruction counts of both at full size are taken on the GPU
 with rocprofv3 counters (profiles/); this test needs only hipcc.
@@ -52,6 +55,10 @@ PAIRS = [
     ("transpose.hip",
      "transpose32_kernel<desc::(anonymous namespace)::TransposeCfg<128, false>, false>",
      "hand::transpose32_hand<false>", 1.0),
+    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<256, 128, 16, 2, 2, 2>, true>",
+     "hand::gemm_f32_hand<true>", 1.05),
+    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<256, 128, 16, 2, 2, 2>, false>",
+     "hand::gemm_f32_hand<false>", 1.12),
 ]
 
 
