@@ -13,9 +13,10 @@
 // FP32 division and one FP32 multiply; s_i = alpha_i / 448 (an all-zero row
 // uses 448/alpha = 1 and s = 0).  Columns of B likewise with beta_j.  Then
 // C_ij = s_i * t_j * sum_k q_ik q_kj, the sum on the matrix cores in FP32.
-// Pre-pass: one block per row of A (absmax, then encode); column absmax of
-// B as partial maxima over K slices; an LDS-tiled transpose of B that
-// encodes with the column scales and writes q^T as [Np][Kp].
+// Pre-pass, two launches: one block per row of A (absmax, then encode)
+// beside the column absmax of B as partial maxima over K slices; then an
+// LDS-tiled transpose of B that encodes with the column scales and writes
+// q^T as [Np][Kp].
 //
 // Padding: Mp, Np are multiples of 256 and Kp a multiple of 128 elements;
 // the pre-pass writes zeros there, so the GEMM main loop has no guards.
@@ -162,19 +163,17 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 // phases, so the row is read once; longer rows are read again to encode.
 // q is rows_out x k_out (stride ldq); rows >= M and columns >= K get zero.
 constexpr int kRowCache = 8;   // float4 per thread
+constexpr int kColTiles = 1;   // k tiles of 64 per block of quant_cols_t_kernel (4: slower)
 
-__global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restrict__ A,
-                                                            int64_t M, int64_t K, int64_t lda,
-                                                            uint8_t* __restrict__ q,
-                                                            int64_t k_out, int64_t ldq,
-                                                            float* __restrict__ scale,
-                                                            bool vec_in, bool vec_out) {
+// Row r of rows_out (the block's row; the caller's grid may hold other work).
+__device__ __forceinline__ void quant_row(const float* __restrict__ A, int64_t M, int64_t K,
+                                          int64_t lda, uint8_t* __restrict__ q, int64_t rows_out,
+                                          int64_t k_out, int64_t ldq, float* __restrict__ scale,
+                                          bool vec_in, bool vec_out, idx_t r) {
   __shared__ float red[kBlock / kWave];
-  auto row = block_x();
   auto thread = thread_x<kBlock>();
-  const idx_t r = row.index();
   auto a = matrix(A, M, lda);
-  auto qr = matrix(q, row.count(), ldq).idx(r);
+  auto qr = matrix(q, rows_out, ldq).idx(r);
   auto load4 = [&](idx_t c) {
     f32x4 v;
     if (vec_in && r < M && c + 4 <= K) {
@@ -244,24 +243,32 @@ __global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restr
   } else {
     for (idx_t c = 4 * thread.index(); c < k_out; c += 4 * kBlock) encode(c, load4(c), inv);
   }
-  if (thread.index() == 0) array(scale, row.count())[r] = amax / 448.0f;
+  if (thread.index() == 0) array(scale, rows_out)[r] = amax / 448.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void quant_rows_kernel(const float* __restrict__ A,
+                                                            int64_t M, int64_t K, int64_t lda,
+                                                            uint8_t* __restrict__ q,
+                                                            int64_t k_out, int64_t ldq,
+                                                            float* __restrict__ scale,
+                                                            bool vec_in, bool vec_out) {
+  auto row = block_x();
+  quant_row(A, M, K, lda, q, row.count(), k_out, ldq, scale, vec_in, vec_out, row.index());
 }
 
 // Partial column maxima of |B| over K slices: part[s][n] for slice s of
 // `rows_per` rows; grid (column blocks of 1024, slices).  Thread = 4
 // consecutive columns, read as one 16-byte vector per row when aligned;
 // eight rows are loaded before they are combined.
-__global__ __launch_bounds__(kBlock) void colmax_partial_kernel(const float* __restrict__ B,
-                                                                int64_t K, int64_t N,
-                                                                int64_t ldb, int64_t rows_per,
-                                                                float* __restrict__ part,
-                                                                int64_t ldp, bool vec_in) {
-  auto cb = block_x();
-  auto sl = block_y();
+// Column block cb (kBlock * 4 columns) of slice sl (of nslices).
+__device__ __forceinline__ void colmax_part(const float* __restrict__ B, int64_t K, int64_t N,
+                                            int64_t ldb, int64_t rows_per,
+                                            float* __restrict__ part, int64_t ldp, bool vec_in,
+                                            idx_t cb, idx_t sl, idx_t nslices) {
   auto thread = thread_x<kBlock>();
   auto b = matrix(B, K, ldb);
-  const idx_t n = (cb.index() * kBlock + thread.index()) * 4;
-  const idx_t k0 = sl.index() * rows_per;
+  const idx_t n = (cb * kBlock + thread.index()) * 4;
+  const idx_t k0 = sl * rows_per;
   const idx_t k1 = k0 + rows_per < K ? k0 + rows_per : K;
   f32x4 m = {0.f, 0.f, 0.f, 0.f};
   if (vec_in && n + 4 <= N) {
@@ -277,15 +284,45 @@ __global__ __launch_bounds__(kBlock) void colmax_partial_kernel(const float* __r
       for (int j = 0; j < 4; ++j)
         if (n + j < N) m[j] = fmaxf(m[j], fabsf(b.at(k, n + j)));
   }
-  auto pr = matrix(part, sl.count(), ldp).idx(sl.index());
+  auto pr = matrix(part, nslices, ldp).idx(sl);
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if (n + j < ldp) pr[n + j] = m[j];
 }
 
+__global__ __launch_bounds__(kBlock) void colmax_partial_kernel(const float* __restrict__ B,
+                                                                int64_t K, int64_t N,
+                                                                int64_t ldb, int64_t rows_per,
+                                                                float* __restrict__ part,
+                                                                int64_t ldp, bool vec_in) {
+  auto sl = block_y();
+  colmax_part(B, K, N, ldb, rows_per, part, ldp, vec_in, block_x().index(), sl.index(),
+              sl.count());
+}
+
+// The FP8 GEMM's first pass in one launch: the column-maximum partials of B
+// (the first cblocks * nslices blocks, the longer ones, so they start first)
+// and the row quantisation of A (one block per padded row), which do not
+// depend on each other.
+__global__ __launch_bounds__(kBlock) void fp8_prepass_kernel(
+    const float* __restrict__ A, int64_t M, int64_t K, int64_t lda, uint8_t* __restrict__ qa,
+    int64_t rows_out, int64_t k_out, int64_t ldqa, float* __restrict__ sa, bool a_vec_in,
+    const float* __restrict__ B, int64_t N, int64_t ldb, int64_t rows_per,
+    float* __restrict__ part, int64_t ldp, bool b_vec_in, int64_t cblocks, int64_t nslices) {
+  const idx_t blk = block_x().index(), col_blocks = cblocks * nslices;
+  if (blk < col_blocks)
+    colmax_part(B, K, N, ldb, rows_per, part, ldp, b_vec_in, blk % cblocks, blk / cblocks,
+                nslices);
+  else
+    quant_row(A, M, K, lda, qa, rows_out, k_out, ldqa, sa, a_vec_in, true, blk - col_blocks);
+}
+
 // Encode 64 x 64 tiles of B with their column scales and write them
-// transposed: qt is n_out x k_out (stride ldq).  The first k tile of each
-// column block also writes the column scales.  Reads run along n (thread =
+// transposed: qt is n_out x k_out (stride ldq).  A block takes kColTiles
+// consecutive k tiles of one column block, the column maxima it gathers from
+// the slice partials serving all of them (one tile per block measured
+// fastest at 4096^2: more blocks in flight); the first block of each column
+// block also writes the column scales.  Reads run along n (thread =
 // 4 columns of one row), writes along k (thread = 4 consecutive k, one
 // 4-byte store).
 __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __restrict__ B,
@@ -307,7 +344,7 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
   auto b = matrix(B, K, ldb);
   auto pm = matrix(part, nslices, ldp);
   auto out = matrix(qt, n_out, ldq);
-  const idx_t k0 = kt.index() * 64, n0 = nt.index() * 64;
+  const idx_t n0 = nt.index() * 64;
   {
     // column maxima of the 64 columns from the slice partials: thread
     // (g, c) takes slices g, g + 4, ... of column c (loads coalesced along
@@ -330,6 +367,10 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
   }
   sync(thread);
   const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
+  for (int t = 0; t < kColTiles; ++t) {
+  const idx_t k0 = (kt.index() * kColTiles + t) * 64;
+  if (k0 >= k_out) break;
+  if (t > 0) sync(thread);                      // the previous tile's codes are read
 #pragma unroll
   for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
     const idx_t r = ty + 16 * i, c = 4 * tx;
@@ -363,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
       for (int j = 0; j < 4; ++j)
         if (k0 + r + j < k_out) out.at(n0 + c, k0 + r + j) = e[j];
     }
+  }
   }
 }
 
@@ -459,11 +501,12 @@ constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32
                                       "m256n256k32_d1", "m256n256k32_w8d1",
                                       "m128n128k32_fused", "m256n256k32_w8d1_fused"};
 constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
-                                     "m128n256k128", "m256n128k64", "m256n256k64_w8d1"};
+                                     "m128n256k128", "m256n128k64", "m256n256k64_w8d1",
+                                     "m256n256k128_w8d1"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
     (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 7, kNamesBf16, kDefaults),
-     tune::register_op(tune::kGemmFp8, "gemm_fp8", 6, kNamesFp8, kDefaults), true);
+     tune::register_op(tune::kGemmFp8, "gemm_fp8", 7, kNamesFp8, kDefaults), true);
 
 }  // namespace
 
@@ -512,7 +555,9 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
   hipLaunchKernelGGL(colmax_partial_kernel,
                      dim3((unsigned)((N + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
                      dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N, f4_ok(B, ldb));
-  hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)((K + 63) / 64), (unsigned)((N + 63) / 64)),
+  hipLaunchKernelGGL(quant_cols_t_kernel,
+                     dim3((unsigned)((K + 64 * kColTiles - 1) / (64 * kColTiles)),
+                          (unsigned)((N + 63) / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale,
                      f4_ok(B, ldb), w_ok(qt, ldq, 1));
   return hipGetLastError();
@@ -557,13 +602,14 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
   uint8_t* w = (uint8_t*)ws;
   uint8_t *qa = w + L.off[0], *qb = w + L.off[2];
   float *sa = (float*)(w + L.off[4]), *sb = (float*)(w + L.off[5]), *part = (float*)(w + L.off[6]);
-  hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)L.Mp), dim3(kBlock), 0, s, A, M, K, lda, qa,
-                     L.Kp, L.Kp, sa, f4_ok(A, lda), true);
   const int64_t S = colmax_slices(K, N), rows_per = (K + S - 1) / S;
-  hipLaunchKernelGGL(colmax_partial_kernel,
-                     dim3((unsigned)((L.Np + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
-                     dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, L.Np, f4_ok(B, ldb));
-  hipLaunchKernelGGL(quant_cols_t_kernel, dim3((unsigned)(L.Kp / 64), (unsigned)(L.Np / 64)),
+  const int64_t cblocks = (L.Np + 4 * kBlock - 1) / (4 * kBlock);
+  hipLaunchKernelGGL(fp8_prepass_kernel, dim3((unsigned)(cblocks * S + L.Mp)), dim3(kBlock), 0, s,
+                     A, M, K, lda, qa, L.Mp, L.Kp, L.Kp, sa, f4_ok(A, lda), B, N, ldb, rows_per,
+                     part, L.Np, f4_ok(B, ldb), cblocks, S);
+  hipLaunchKernelGGL(quant_cols_t_kernel,
+                     dim3((unsigned)((L.Kp + 64 * kColTiles - 1) / (64 * kColTiles)),
+                          (unsigned)(L.Np / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb,
                      f4_ok(B, ldb), true);
   NtOperands p{{qa, nullptr}, {qb, nullptr}, L.Kp, Cm, ldc, M, N, sa, sb};
@@ -573,6 +619,7 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
     case 3: return launch_nt<NtCfg<128, 256, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
     case 4: return launch_nt<NtCfg<256, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
     case 5: return launch_nt<NtCfg<256, 256, 64, Fp8Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
+    case 6: return launch_nt<NtCfg<256, 256, 128, Fp8Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
   }
 }

@@ -154,7 +154,7 @@ def tune(ops, reps: int = 20):
 
 def write_table(table, path: str) -> None:
     with open(path, "w") as f:
-        f.write("# op size_class config -- written by paper_2305_03448_amd/tune.py\n")
+        f.write("# op size_class config -- timed per size class by paper_2305_03448_amd/tune.py\n")
         for (op, cls), cfg in sorted(table.items()):
             f.write(f"{op} {cls} {cfg}\n")
 
