@@ -502,7 +502,7 @@ def op_segmented(desc, torch, workloads):
     off = torch.from_numpy(off_np).cuda()
     r = torch.empty(S, dtype=torch.int64, device="cuda")
     y = torch.empty_like(x)
-    wr = torch.empty(desc.desc_reduce_segmented_i32_workspace(T, S), dtype=torch.uint8,
+    wr = torch.zeros(desc.desc_reduce_segmented_i32_workspace(T, S), dtype=torch.uint8,
                      device="cuda")
     wy = torch.zeros(desc.desc_scan_segmented_i32_workspace(T, S), dtype=torch.uint8,
                      device="cuda")

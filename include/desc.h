@@ -85,8 +85,8 @@ void desc_set_pointer_classifier(desc_pointer_classifier fn);
  *                        until read.  Reported by the workspaces of
  *                        desc_reduce_i32, desc_reduce_op (min/max, float
  *                        sum), desc_scan_i32 / desc_scan_exclusive_i32,
- *                        desc_scan_f32, the segmented scan and the batched
- *                        scan.
+ *                        desc_scan_f32, the segmented reduce and scan and
+ *                        the batched scan.
  *   DESC_DEV_PLANES      desc_gemm_grouped or desc_gemm_strided_batched in
  *                        DESC_GEMM_BF16X3 mode found that the bf16 planes do
  *                        not fit the workspace (or a dimension above 2^40)
@@ -404,11 +404,16 @@ desc_status desc_scan_batched_i32(const int32_t* in, int32_t* out, int64_t batch
  *   reduce : out[s] = exact int64 sum of segment s (0 for an empty segment).
  *   scan   : out[i] = in[offsets[s]] + ... + in[i] modulo 2^32 for i in
  *            segment s; positions outside every segment are not written.
- * Each runs as a one-block planning kernel and one main kernel; all state
- * lives in the workspace, so both may be captured in a HIP graph and
- * replayed.  The workspace is zeroed once before its first use (its header
- * holds the device status word and the wait limit; the planning kernel
- * resets everything else on every call).
+ * The reduce of up to 8192 segments runs as one persistent launch (every
+ * block plans the units of all segments in its LDS and then takes every
+ * G-th unit, G the blocks that fit the device at once; no block waits for
+ * another before the end of the call); the scan, a larger reduce and the
+ * batched forms run as a one-block planning kernel and one main kernel.
+ * All state lives in the workspace, so every form may be captured in a HIP
+ * graph and replayed.  The workspace is zeroed once before its first use
+ * (its header holds the device status word, the wait limit and the
+ * generation that tags the state words); one workspace may serve both
+ * operations if it has the larger size.
  * ---------------------------------------------------------------------- */
 size_t desc_reduce_segmented_i32_workspace(int64_t n, int64_t num_segments);
 desc_status desc_reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets,

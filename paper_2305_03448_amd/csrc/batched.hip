@@ -62,7 +62,7 @@ hipError_t reduce_batched_i32(const int32_t* in, int64_t B, int64_t L, int64_t* 
   int64_t* off = nullptr;
   const hipError_t e = batched_offsets(B, L, false, ws, &off, s);
   if (e != hipSuccess) return e;
-  return reduce_segmented_i32(in, B * L, off, B, out, ws, s);
+  return reduce_segmented_i32(in, B * L, off, B, out, ws, s, false);
 }
 
 hipError_t scan_batched_i32(const int32_t* in, int32_t* out, int64_t B, int64_t L, void* ws,

@@ -239,18 +239,7 @@ GroupedWs carve(void* ws, int64_t G) {
 template <bool kBig, bool kRm>
 int persistent_grid() {
   static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cached[dev] == 0) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, grouped_gemm_kernel<kBig, kRm>,
-                                                     kBlock, 0) != hipSuccess || per < 1)
-      per = 1;
-    cached[dev] = cus * per;
-  }
-  return cached[dev];
+  return launch::resident_grid(grouped_gemm_kernel<kBig, kRm>, cached, 1, kBlock);
 }
 
 // --------------------------------------------------------------------------
@@ -657,23 +646,6 @@ void bf16_fused_kernel(const desc_gemm_problem* probs, int64_t G, Bf16Ws w) {
   }
 }
 
-// Blocks of `kernel` that fit the device at once (per device, computed once).
-template <class K>
-int resident_grid(K kernel, int (&cache)[64], int fallback_per_cu, int threads = kBlock) {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (cache[dev] == 0) {
-    int cus = 0, per = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
-        per < 1)
-      per = fallback_per_cu;
-    cache[dev] = cus * per;
-  }
-  return cache[dev];
-}
-
 template <int kCfg>
 hipError_t launch_bf16x3(const desc_gemm_problem* problems, int64_t G, const Bf16Ws& w,
                          hipStream_t s) {
@@ -682,14 +654,14 @@ hipError_t launch_bf16x3(const desc_gemm_problem* problems, int64_t G, const Bf1
   if constexpr (kFused<kCfg>) {
     static int fused_grid[64] = {0};
     constexpr int kThreads = FusedNt<kCfg>::threads;
-    const int gf = resident_grid(bf16_fused_kernel<kCfg>, fused_grid, 1, kThreads);
+    const int gf = launch::resident_grid(bf16_fused_kernel<kCfg>, fused_grid, 1, kThreads);
     hipLaunchKernelGGL(bf16_fused_kernel<kCfg>, dim3((unsigned)gf), dim3(kThreads), 0, s,
                        problems, G, w);
   }
   // planes: every problem in configurations 0-2, those with strides past the
   // split source's limit in the fused ones (the kernels exit at once if none)
-  const int gs = resident_grid(bf16_split_kernel, split_grid, 4);
-  const int gn = resident_grid(bf16_nt_kernel<kCfg>, nt_grid, 2);
+  const int gs = launch::resident_grid(bf16_split_kernel, split_grid, 4, kBlock);
+  const int gn = launch::resident_grid(bf16_nt_kernel<kCfg>, nt_grid, 2, kBlock);
   hipLaunchKernelGGL(bf16_split_kernel, dim3((unsigned)gs), dim3(kBlock), 0, s, problems, G, w);
   hipLaunchKernelGGL(bf16_nt_kernel<kCfg>, dim3((unsigned)gn), dim3(kBlock), 0, s, problems, G,
                      w);

@@ -11,6 +11,25 @@
 namespace desc {
 namespace launch {
 
+// Blocks of `kernel` (of `threads` threads) that fit the device at once: its
+// occupancy per CU times the CUs, per device, computed on first use
+// (`fallback_per_cu` if the occupancy query fails).
+template <class K>
+int resident_grid(K kernel, int (&cache)[64], int fallback_per_cu, int threads) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        per < 1)
+      per = fallback_per_cu;
+    cache[dev] = cus * per;
+  }
+  return cache[dev];
+}
+
 // reduce.hip
 constexpr int kReduceMaxBlocks = 2048;
 size_t reduce_i32_workspace(int64_t n);
@@ -62,8 +81,10 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
 // segmented.hip
 size_t segmented_workspace(int64_t n, int64_t S, bool scan);
 int64_t segmented_max_grid(int64_t n, int64_t S);
+// persistent: allow the reduce's one-launch form (up to 8192 segments); the
+// batched form passes false, since its offsets share the workspace.
 hipError_t reduce_segmented_i32(const int32_t* in, int64_t n, const int64_t* offsets, int64_t S,
-                                int64_t* out, void* ws, hipStream_t s);
+                                int64_t* out, void* ws, hipStream_t s, bool persistent = true);
 hipError_t scan_segmented_i32(const int32_t* in, int32_t* out, int64_t n, const int64_t* offsets,
                               int64_t S, void* ws, hipStream_t s);
 

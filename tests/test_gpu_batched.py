@@ -42,7 +42,9 @@ def test_scan_batched(B, L):
 
 
 def test_batched_unaligned_and_workspace_reuse():
-    ws = torch.zeros(desc.desc_scan_batched_i32_workspace(300, 4099), dtype=torch.uint8,
+    # one workspace for both operations, sized for the larger
+    ws = torch.zeros(max(desc.desc_scan_batched_i32_workspace(300, 4099),
+                         desc.desc_reduce_batched_i32_workspace(300, 4099)), dtype=torch.uint8,
                      device=dev())
     for rep, (B, L, off) in enumerate([(300, 4099, 1), (5, 3, 3), (299, 4097, 2), (300, 4099, 0)]):
         case(f"batched reuse rep {rep} B={B} L={L} offset={off}")

@@ -59,6 +59,41 @@ def test_gaps_untouched_and_subrange():
     assert np.array_equal(y, oracle.scan_segmented_i32(x, off, fill=-99))
 
 
+def test_one_workspace_across_sizes_and_forms():
+    """One zeroed workspace per operation for a sequence of calls whose
+    sizes, segment counts and forms differ (one persistent launch up to 8192
+    segments, plan + main kernel above): every call equals the oracle, so
+    state words an earlier call left never count for a later one."""
+    g = workloads.rng(23)
+    sets = [
+        [3 * UNIT + 5, 1, 0, 2 * UNIT],                            # persistent, long segments
+        list(g.integers(0, 200, 9000)),                            # 9000 segments: two launches
+        [0, 7, UNIT, 1],                                           # persistent, short
+        list(g.integers(0, 3 * UNIT, 40)),                         # persistent, many units
+        list(g.integers(0, 50, 8192)),                             # the largest persistent count
+        [5 * UNIT + 3],
+    ]
+    cases = []
+    for lengths in sets:
+        off = workloads.offsets_from_lengths(np.array(lengths, np.int64))
+        cases.append((workloads.int_uniform(int(off[-1]), seed=29), off))
+    wr_bytes = max(desc.desc_reduce_segmented_i32_workspace(x.size, off.size - 1) for x, off in cases)
+    ws_bytes = max(desc.desc_scan_segmented_i32_workspace(x.size, off.size - 1) for x, off in cases)
+    wr = torch.zeros(wr_bytes, dtype=torch.uint8, device=dev())
+    wy = torch.zeros(ws_bytes, dtype=torch.uint8, device=dev())
+    for rep in range(2):
+        for i, (x, off) in enumerate(cases):
+            case(f"segmented shared workspace rep {rep} case {i} (S = {off.size - 1})")
+            xt, ot = to_dev(x), to_dev(off)
+            r = torch.full((off.size - 1,), 123, dtype=torch.int64, device=dev())
+            y = torch.full((x.size,), -7, dtype=torch.int32, device=dev())
+            desc.desc_reduce_segmented_i32(xt, ot, r, ws=wr)
+            desc.desc_scan_segmented_i32(xt, ot, y, ws=wy)
+            assert np.array_equal(r.cpu().numpy(), oracle.reduce_segmented_i32(x, off)), i
+            assert np.array_equal(y.cpu().numpy(), oracle.scan_segmented_i32(x, off)), i
+    assert desc.workspace_status(wr) == 0 and desc.workspace_status(wy) == 0
+
+
 def test_extreme_values_exact():
     case("segmented extremes")
     lengths = np.array([1, (1 << 20), 17, UNIT * 3 + 1], np.int64)
@@ -80,10 +115,11 @@ def test_repeated_calls_and_graph_replay():
     want_y = oracle.scan_segmented_i32(x, off)
     r = torch.empty(S, dtype=torch.int64, device=dev())
     y = torch.empty(x.size, dtype=torch.int32, device=dev())
-    wr = torch.empty(desc.desc_reduce_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
+    # zero-filled once, as the workspace contract asks
+    wr = torch.zeros(desc.desc_reduce_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
                      device=dev())
     wy = torch.zeros(desc.desc_scan_segmented_i32_workspace(x.size, S), dtype=torch.uint8,
-                     device=dev())   # zero-filled once, as the workspace contract asks
+                     device=dev())
     for rep in range(3):
         case(f"segmented eager rep {rep}")
         desc.desc_reduce_segmented_i32(xt, ot, r, ws=wr)

@@ -42,6 +42,7 @@ EXPECTED = [
     "access_check_segmented_scan_clean",
     "access_check_segmented_reduce_clean",
     "access_check_segmented_reduce_plain_stores_race",
+    "access_check_segmented_persistent_reduce_clean",
     "grouped_tile_walk_takes_every_tile_once",
     "access_check_grouped_walk_clean",
     "access_check_grouped_walk_without_the_end_barrier_races",

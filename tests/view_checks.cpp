@@ -6,6 +6,7 @@
 // exits non-zero if any fails.
 //
 // Built by tests/test_views.py with: g++ -std=c++17 -O1 -I <csrc> view_checks.cpp
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -757,6 +758,62 @@ int main(int argc, char** argv) {
     const size_t rr = reduce_access(true, &unset2);
     check(rc == 0 && unset == 0, "access_check_segmented_reduce_clean");
     check(rr > 0, "access_check_segmented_reduce_plain_stores_race", std::to_string(rr) + " conflicts");
+    // The persistent reduce: block b of G walks the contiguous units
+    // [T b / G, T (b + 1) / G); a segment that starts and ends in the range
+    // is stored by the block; the range's last segment, if it continues, is
+    // published as the block's tail (every block writes its tail word); the
+    // range's first segment, if it started earlier and ends here, is stored
+    // by this block from the tails of earlier blocks back to the one where
+    // it starts.  Every output is written exactly once, the ranges cover the
+    // units once, and a block reads only tails of blocks of smaller index
+    // whose ranges lie in the segment.
+    auto persistent_reduce = [&](long G, bool, long* writes_bad) {
+      access_check::Checker r;
+      std::vector<uint64_t> tails(2 * G);
+      std::vector<int> written(S, 0), covered(units, 0);
+      const long TH = 64;
+      auto first_unit = [&](long k) { return (long)((int64_t)units * k / G); };
+      for (long b = 0; b < G; ++b)
+        for (long s2 = b * TH; s2 < S; s2 += G * TH)
+          for (long t = 0; t < TH && s2 + t < S; ++t)
+            if (us[s2 + t] == us[s2 + t + 1]) { r.write(b, b * TH + t, &red[s2 + t]); ++written[s2 + t]; }
+      *writes_bad = 0;
+      for (long b = 0; b < G; ++b) {
+        const long u0 = first_unit(b), u1 = first_unit(b + 1);
+        long head_seg = -1;
+        for (long u = u0; u < u1; ++u) {
+          ++covered[u];
+          const layout::SegUnit su = layout::seg_unit(offv, usv, n, S, U, u);
+          if (u + 1 == us[su.seg + 1] || u + 1 == u1) {
+            if (us[su.seg + 1] > u1) continue;                      // tail: published below
+            if (us[su.seg] < u0) { head_seg = su.seg; continue; }
+            r.write(b, b * TH, &red[su.seg]);
+            ++written[su.seg];
+          }
+        }
+        for (int h = 0; h < 2; ++h) r.atomic(b, b * TH, &tails[2 * b + h], true);
+        if (head_seg >= 0) {
+          for (long k = b - 1; k >= 0; --k) {
+            if (first_unit(k) == first_unit(k + 1)) continue;
+            // block k's range lies in the segment (its last unit does)
+            *writes_bad += first_unit(k + 1) - 1 < us[head_seg];
+            for (int h = 0; h < 2; ++h) r.atomic(b, b * TH, &tails[2 * k + h], false);
+            if (first_unit(k) <= us[head_seg]) break;
+          }
+          r.write(b, b * TH, &red[head_seg]);
+          ++written[head_seg];
+        }
+      }
+      for (long s2 = 0; s2 < S; ++s2) *writes_bad += written[s2] != 1;
+      for (long u = 0; u < units; ++u) *writes_bad += covered[u] != 1;
+      return r.conflicts(64).size();
+    };
+    bool pr_ok = true;
+    for (long G : {1L, 2L, 3L, 8L, 77L, 100L, 1000L}) {
+      long bad = 0;
+      pr_ok &= persistent_reduce(G, false, &bad) == 0 && bad == 0;
+    }
+    check(pr_ok, "access_check_segmented_persistent_reduce_clean");
   }
 
   // --- the grouped GEMM's persistent tile walk (grouped.hip): every tile of the
