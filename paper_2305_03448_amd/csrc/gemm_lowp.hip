@@ -496,17 +496,18 @@ unsigned grid_for(int64_t items) {
 }
 
 // "_w8": eight waves (2 x 4) share the tile instead of four (2 x 2);
-// "_fused": the operands split while they are staged (no pre-pass).
+// "_fused": the operands split while they are staged (no pre-pass);
+// "_p": fragment reads one group of matrix ops ahead (NtCfg kPipe).
 constexpr const char* kNamesBf16[] = {"m128n128k32", "m256n128k32", "m128n256k32",
                                       "m256n256k32_d1", "m256n256k32_w8d1",
                                       "m128n128k32_fused", "m256n256k32_w8d1_fused"};
 constexpr const char* kNamesFp8[] = {"m128n128k128", "m128n128k64", "m256n128k128",
                                      "m128n256k128", "m256n128k64", "m256n256k64_w8d1",
-                                     "m256n256k128_w8d1"};
+                                     "m256n256k128_w8d1", "m256n256k128_w8d1_p", "m128n128k128_p"};
 constexpr int kDefaults[tune::kClasses] = {0, 0, 0, 0};
 const bool kRegistered =
     (tune::register_op(tune::kGemmBf16x3, "gemm_bf16x3", 7, kNamesBf16, kDefaults),
-     tune::register_op(tune::kGemmFp8, "gemm_fp8", 7, kNamesFp8, kDefaults), true);
+     tune::register_op(tune::kGemmFp8, "gemm_fp8", 9, kNamesFp8, kDefaults), true);
 
 }  // namespace
 
@@ -620,6 +621,8 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
     case 4: return launch_nt<NtCfg<256, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);
     case 5: return launch_nt<NtCfg<256, 256, 64, Fp8Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
     case 6: return launch_nt<NtCfg<256, 256, 128, Fp8Mode, 1, 2, 4>>(p, L.Mp, L.Np, s);
+    case 7: return launch_nt<NtCfg<256, 256, 128, Fp8Mode, 1, 2, 4, true>>(p, L.Mp, L.Np, s);
+    case 8: return launch_nt<NtCfg<128, 128, 128, Fp8Mode, 2, 2, 2, true>>(p, L.Mp, L.Np, s);
     default: return launch_nt<NtCfg<128, 128, 128, Fp8Mode>>(p, L.Mp, L.Np, s);
   }
 }

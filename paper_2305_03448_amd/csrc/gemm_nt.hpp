@@ -52,11 +52,16 @@ struct Fp8Mode {
 // kDepth: stages in flight in registers (1: the next stage's loads are
 // issued before the current stage's matrix ops; 2: two stages ahead, which
 // needs a second register staging set).  kWM x kWN waves share the tile,
-// each computing a (kBM / kWM) x (kBN / kWN) part of it.
-template <int kBM, int kBN, int kBKB, class Mode, int kDepth = 2, int kWM = 2, int kWN = 2>
+// each computing a (kBM / kWM) x (kBN / kWN) part of it.  kPipe (scaled
+// mode): each group of matrix ops has the LDS reads of the next group
+// issued ahead of it.
+template <int kBM, int kBN, int kBKB, class Mode, int kDepth = 2, int kWM = 2, int kWN = 2,
+          bool kPipe = false>
 struct NtCfg {
   using mode = Mode;
   static constexpr int bm = kBM, bn = kBN, bkb = kBKB, depth = kDepth;
+  static constexpr bool pipe = kPipe;
+  static_assert(!kPipe || (Mode::scaled && Mode::lane_bytes == 32), "pipelined form: scaled mode");
   static constexpr int wm = kWM, wn = kWN, threads = 64 * kWM * kWN;
   static constexpr int wtm = kBM / kWM, wtn = kBN / kWN;
   static constexpr int fm = wtm / 32, fn = wtn / 32;
@@ -376,6 +381,54 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
     }
   };
 
+  // Pipelined matrix ops of one stage (scaled mode): a step's B fragments
+  // stay in registers while its A fragments stream through two register
+  // sets.  Group g is the fn matrix ops of one A fragment; the reads for
+  // group g + 1 (the next A fragment, or the next step's B fragments and
+  // first A fragment, into the other sets) are issued before group g's
+  // matrix ops, so their LDS latency runs under those.  The scheduling
+  // groups pin that order: the compiler would otherwise gather the reads.
+  auto compute_pipe = [&](auto stage) {
+    using F = gemm_nt::Frag<32>;
+    auto s = plane(stage, 0);
+    auto read = [&](int st, idx_t row, F& f) {
+      const int ch = (st * Mode::step_bytes + half * LB) / 16;
+      f.v0 = s.at(row, ch);
+      f.v1 = s.at(row, ch + 1);
+    };
+    auto read_a = [&](int st, int i, F& f) { read(st, wm * C::wtm + i * 32 + col32, f); };
+    auto read_b = [&](int st, int j, F& f) { read(st, C::bm + wn * C::wtn + j * 32 + col32, f); };
+    constexpr unsigned kDsRead = 0x100, kMatrix = 0x008;   // sched_group_barrier masks
+    F fa[2], fb[2][C::fn];
+#pragma unroll
+    for (int j = 0; j < C::fn; ++j) read_b(0, j, fb[0][j]);
+    read_a(0, 0, fa[0]);
+    __builtin_amdgcn_sched_group_barrier(kDsRead, 2 * C::fn + 2, 0);
+#pragma unroll
+    for (int st = 0; st < C::steps; ++st)
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i) {
+        const int g = st * C::fm + i;
+        if (i + 1 < C::fm) {
+          read_a(st, i + 1, fa[(g + 1) & 1]);
+          __builtin_amdgcn_sched_group_barrier(kDsRead, 2, 0);
+        } else if (st + 1 < C::steps) {
+#pragma unroll
+          for (int j = 0; j < C::fn; ++j) read_b(st + 1, j, fb[(st + 1) & 1][j]);
+          read_a(st + 1, 0, fa[(g + 1) & 1]);
+          __builtin_amdgcn_sched_group_barrier(kDsRead, 2 * C::fn + 2, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j)
+          acc[i][j] = mfma::fp8_32x32x64(fa[g & 1].i8(), fb[st & 1][j].i8(), acc[i][j]);
+        __builtin_amdgcn_sched_group_barrier(kMatrix, C::fn, 0);
+      }
+  };
+  auto compute_stage = [&](int stage) {
+    if constexpr (C::pipe) compute_pipe(stage);
+    else compute(stage);
+  };
+
   const idx_t nk = src.stages();
   if constexpr (C::depth == 1) {
     // One stage ahead: iteration kt loads stage kt+1 into registers, computes
@@ -388,12 +441,12 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
       const int stage = (int)(kt & 1);
       load(kt + 1, R0);
       __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the matrix ops
-      compute(stage);
+      compute_stage(stage);
       __builtin_amdgcn_sched_barrier(0);
       store(R0, stage ^ 1);
       sync(thread);
     }
-    compute((int)((nk - 1) & 1));
+    compute_stage((int)((nk - 1) & 1));
   } else {
     // Two stages deep: at the start of iteration kt, LDS buffer kt % 2 holds
     // stage kt and register set (kt+1) % 2 holds stage kt+1 (its loads issued
@@ -410,13 +463,13 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
     for (; kt + 3 < nk; kt += 2) {
       load(kt + 2, R0);
       __builtin_amdgcn_sched_barrier(0);
-      compute(0);
+      compute_stage(0);
       __builtin_amdgcn_sched_barrier(0);
       store(R1, 1);
       sync(thread);
       load(kt + 3, R1);
       __builtin_amdgcn_sched_barrier(0);
-      compute(1);
+      compute_stage(1);
       __builtin_amdgcn_sched_barrier(0);
       store(R0, 0);
       sync(thread);
@@ -428,24 +481,24 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
     if constexpr (Src::kStaticTail) {
       if (kt < nk) {
         if (kt + 2 < nk) load(kt + 2, R0);
-        compute(0);
+        compute_stage(0);
         if (kt + 1 < nk) store(R1, 1);
         sync(thread);
       }
       if (kt + 1 < nk) {
-        compute(1);
+        compute_stage(1);
         if (kt + 2 < nk) store(R0, 0);
         sync(thread);
       }
       if (kt + 2 < nk) {
-        compute(0);
+        compute_stage(0);
         sync(thread);
       }
     } else {
       for (; kt < nk; ++kt) {
         const bool even = (kt & 1) == 0;
         if (kt + 2 < nk) load(kt + 2, even ? R0 : R1);
-        compute((int)(kt & 1));
+        compute_stage((int)(kt & 1));
         if (kt + 1 < nk) store(even ? R1 : R0, (int)((kt + 1) & 1));
         sync(thread);
       }
