@@ -219,24 +219,55 @@ struct SplitSource {
   static constexpr bool kStaticTail = true;
   const F32Operands& p;
   idx_t m0, n0;
+  // What a wave's ranges keep over the whole K loop (uniform values):
+  // each A row group's valid rows and the element offset of its first row
+  // (0 when it has none), each B octet's valid columns, its first k in a
+  // stage and the element offset of its first column at that k of stage 0.
+  int32_t a_rows[AO], b_cols[BO];
+  idx_t a_at[AO], b_at[BO], b_k[BO];
 
-  __device__ __forceinline__ idx_t stages() const { return (p.K + KS - 1) / KS; }
-
-  __device__ __forceinline__ void load(idx_t kt, Regs& R) const {
-    const idx_t k0 = kt * KS;
-    const int32_t cols = (int32_t)min_i(p.K - k0, KS);          // valid k of this stage
-    const int lane = (int)lane_of_wave().index();
+  __device__ __forceinline__ SplitSource(const F32Operands& f, idx_t m0_, idx_t n0_)
+      : p(f), m0(m0_), n0(n0_) {
     const int w = __builtin_amdgcn_readfirstlane((int)wave_of_block<T>().index());
-    auto a = matrix(p.A, p.M, p.lda);
-    auto b = matrix(p.B, p.K, p.ldb);
-    const int lr = layout::split_a_row<CPR>(lane);               // row in the wave's 16
-    const int ka = layout::split_a_k<CPR>(lane);                 // first k of the lane's octet
 #pragma unroll
     for (int i = 0; i < AO; ++i) {
       const idx_t r0 = m0 + (T / CPR) * i + (kWave / CPR) * w;  // first of the wave's rows
       const idx_t rv = max_i(min_i(p.M - r0, kWave / CPR), 0);   // its valid rows
-      const BufferWindow<4> win{(uint32_t)p.lda, (int32_t)rv, cols};
-      const auto rs = buffer_rsrc(rv > 0 ? &a.at(r0, k0) : p.A, win.bytes());
+      a_rows[i] = (int32_t)rv;
+      a_at[i] = rv > 0 ? r0 * p.lda : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < BO; ++i) {
+      const int q0 = T * i + kWave * w;                          // the wave's first octet index
+      const idx_t c0 = n0 + q0 % C::bn;                           // the wave's first column
+      const idx_t cv = max_i(min_i(p.N - c0, kWave), 0);          // valid columns of the wave
+      b_cols[i] = (int32_t)cv;
+      b_k[i] = 8 * (q0 / C::bn);
+      b_at[i] = cv > 0 ? b_k[i] * p.ldb + c0 : 0;
+    }
+  }
+
+  __device__ __forceinline__ idx_t stages() const { return (p.K + KS - 1) / KS; }
+
+  // Stage kt.  Every stage but a last partial one is full (all KS values of
+  // k inside K): then each range's extent and a lane's offsets in it are
+  // the same for every stage, and only the ranges' bases move with k.
+  __device__ __forceinline__ void load(idx_t kt, Regs& R) const {
+    const idx_t k0 = kt * KS;
+    if (k0 + KS <= p.K) load_stage<true>(k0, R);
+    else load_stage<false>(k0, R);
+  }
+  template <bool kFull>
+  __device__ __forceinline__ void load_stage(idx_t k0, Regs& R) const {
+    const int32_t cols = kFull ? KS : (int32_t)min_i(p.K - k0, KS);   // valid k of this stage
+    const int lane = (int)lane_of_wave().index();
+    const int lr = layout::split_a_row<CPR>(lane);               // row in the wave's 16
+    const int ka = layout::split_a_k<CPR>(lane);                 // first k of the lane's octet
+#pragma unroll
+    for (int i = 0; i < AO; ++i) {
+      const BufferWindow<4> win{(uint32_t)p.lda, a_rows[i], cols};
+      // an empty range reads nothing, whatever its base
+      const auto rs = buffer_rsrc(p.A + a_at[i] + (a_rows[i] > 0 ? k0 : 0), win.bytes());
       const uint32_t row = win.row(lr);
       if constexpr (kVec) {
 #pragma unroll
@@ -250,15 +281,14 @@ struct SplitSource {
               __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(row + win.col(ka + j)), 0, 0));
       }
     }
+    const idx_t k0_rows = k0 * p.ldb;                             // B's offset of row k0
 #pragma unroll
     for (int i = 0; i < BO; ++i) {
-      const int q0 = T * i + kWave * w;                          // the wave's first octet index
-      const idx_t c0 = n0 + q0 % C::bn;                           // the wave's first column
-      const idx_t kb = k0 + 8 * (q0 / C::bn);                     // the wave's octet
-      const idx_t rv = max_i(min_i(p.K - kb, 8), 0);               // valid k of the octet
-      const idx_t cv = min_i(p.N - c0, kWave);                      // valid columns of the wave
-      const BufferWindow<4> win{(uint32_t)p.ldb, (int32_t)rv, (int32_t)cv};
-      const auto rs = buffer_rsrc(rv > 0 && cv > 0 ? &b.at(kb, c0) : p.B, win.bytes());
+      // valid k of the octet (all 8 in a full stage)
+      const int32_t rv = kFull ? 8 : (int32_t)max_i(min_i(p.K - k0 - b_k[i], 8), 0);
+      const BufferWindow<4> win{(uint32_t)p.ldb, rv, b_cols[i]};
+      const auto rs =
+          buffer_rsrc(p.B + b_at[i] + (rv > 0 && b_cols[i] > 0 ? k0_rows : 0), win.bytes());
       const uint32_t col = win.col(layout::split_b_col(lane));
 #pragma unroll
       for (int j = 0; j < 8; ++j)
