@@ -219,12 +219,15 @@ struct SplitSource {
   static constexpr bool kStaticTail = true;
   const F32Operands& p;
   idx_t m0, n0;
-  // What a wave's ranges keep over the whole K loop (uniform values):
-  // each A row group's valid rows and the element offset of its first row
-  // (0 when it has none), each B octet's valid columns, its first k in a
-  // stage and the element offset of its first column at that k of stage 0.
+  // What a wave's ranges keep over the whole K loop (uniform values): each
+  // A row group's valid rows and its first row (A's first when it has
+  // none); each B octet's valid columns, its first k in a stage, and B from
+  // that k on at its first column (B itself when it has no valid column).
+  // A stage's range bases are these views at the stage's k.
   int32_t a_rows[AO], b_cols[BO];
-  idx_t a_at[AO], b_at[BO], b_k[BO];
+  idx_t b_k[BO];
+  const float* a_first[AO];
+  const float* b_first[BO];
 
   __device__ __forceinline__ SplitSource(const F32Operands& f, idx_t m0_, idx_t n0_)
       : p(f), m0(m0_), n0(n0_) {
@@ -234,7 +237,7 @@ struct SplitSource {
       const idx_t r0 = m0 + (T / CPR) * i + (kWave / CPR) * w;  // first of the wave's rows
       const idx_t rv = max_i(min_i(p.M - r0, kWave / CPR), 0);   // its valid rows
       a_rows[i] = (int32_t)rv;
-      a_at[i] = rv > 0 ? r0 * p.lda : 0;
+      a_first[i] = &matrix(p.A, p.M, p.lda).at(rv > 0 ? r0 : 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < BO; ++i) {
@@ -243,7 +246,7 @@ struct SplitSource {
       const idx_t cv = max_i(min_i(p.N - c0, kWave), 0);          // valid columns of the wave
       b_cols[i] = (int32_t)cv;
       b_k[i] = 8 * (q0 / C::bn);
-      b_at[i] = cv > 0 ? b_k[i] * p.ldb + c0 : 0;
+      b_first[i] = cv > 0 ? &matrix(p.B, p.K, p.ldb).at(b_k[i], c0) : p.B;
     }
   }
 
@@ -266,8 +269,8 @@ struct SplitSource {
 #pragma unroll
     for (int i = 0; i < AO; ++i) {
       const BufferWindow<4> win{(uint32_t)p.lda, a_rows[i], cols};
-      // an empty range reads nothing, whatever its base
-      const auto rs = buffer_rsrc(p.A + a_at[i] + (a_rows[i] > 0 ? k0 : 0), win.bytes());
+      // k0 < K: the base stays inside the group's first row (or A's)
+      const auto rs = buffer_rsrc(&array(a_first[i], p.K).at(k0), win.bytes());
       const uint32_t row = win.row(lr);
       if constexpr (kVec) {
 #pragma unroll
@@ -281,14 +284,14 @@ struct SplitSource {
               __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(row + win.col(ka + j)), 0, 0));
       }
     }
-    const idx_t k0_rows = k0 * p.ldb;                             // B's offset of row k0
 #pragma unroll
     for (int i = 0; i < BO; ++i) {
-      // valid k of the octet (all 8 in a full stage)
+      // valid k of the octet (all 8 in a full stage); an octet past K reads
+      // nothing, and its base stays at the group's first row
       const int32_t rv = kFull ? 8 : (int32_t)max_i(min_i(p.K - k0 - b_k[i], 8), 0);
       const BufferWindow<4> win{(uint32_t)p.ldb, rv, b_cols[i]};
-      const auto rs =
-          buffer_rsrc(p.B + b_at[i] + (rv > 0 && b_cols[i] > 0 ? k0_rows : 0), win.bytes());
+      const idx_t kr = kFull || rv > 0 ? k0 : 0;
+      const auto rs = buffer_rsrc(&matrix(b_first[i], p.K, p.ldb).at(kr, 0), win.bytes());
       const uint32_t col = win.col(layout::split_b_col(lane));
 #pragma unroll
       for (int j = 0; j < 8; ++j)
