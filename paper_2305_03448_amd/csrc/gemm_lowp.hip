@@ -163,7 +163,6 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 // phases, so the row is read once; longer rows are read again to encode.
 // q is rows_out x k_out (stride ldq); rows >= M and columns >= K get zero.
 constexpr int kRowCache = 8;   // float4 per thread
-constexpr int kColTiles = 1;   // k tiles of 64 per block of quant_cols_t_kernel (4: slower)
 
 // Row r of rows_out (the block's row; the caller's grid may hold other work).
 __device__ __forceinline__ void quant_row(const float* __restrict__ A, int64_t M, int64_t K,
@@ -318,13 +317,13 @@ __global__ __launch_bounds__(kBlock) void fp8_prepass_kernel(
 }
 
 // Encode 64 x 64 tiles of B with their column scales and write them
-// transposed: qt is n_out x k_out (stride ldq).  A block takes kColTiles
-// consecutive k tiles of one column block, the column maxima it gathers from
-// the slice partials serving all of them (one tile per block measured
-// fastest at 4096^2: more blocks in flight); the first block of each column
-// block also writes the column scales.  Reads run along n (thread =
-// 4 columns of one row), writes along k (thread = 4 consecutive k, one
-// 4-byte store).
+// transposed: qt is n_out x k_out (stride ldq).  A block takes one k tile of
+// one column block (four k tiles per block, sharing the gathered maxima,
+// measured slower: fewer blocks in flight); the first block of each column
+// block also writes the column scales.  The tile's loads are issued before
+// the column maxima are gathered from the slice partials, so the two sets
+// of loads are in flight together.  Reads run along n (thread = 4 columns
+// of one row), writes along k (thread = 4 consecutive k, one 4-byte store).
 __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __restrict__ B,
                                                               int64_t K, int64_t N, int64_t ldb,
                                                               const float* __restrict__ part,
@@ -344,7 +343,20 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
   auto b = matrix(B, K, ldb);
   auto pm = matrix(part, nslices, ldp);
   auto out = matrix(qt, n_out, ldq);
-  const idx_t n0 = nt.index() * 64;
+  const idx_t n0 = nt.index() * 64, k0 = kt.index() * 64;
+  const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
+  f32x4 v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
+    const idx_t r = ty + 16 * i, c = 4 * tx;
+    if (vec_in && k0 + r < K && n0 + c + 4 <= N) {
+      v[i] = *(const f32x4*)&b.at(k0 + r, n0 + c);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[i][j] = (k0 + r < K && n0 + c + j < N) ? b.at(k0 + r, n0 + c + j) : 0.f;
+    }
+  }
   {
     // column maxima of the 64 columns from the slice partials: thread
     // (g, c) takes slices g, g + 4, ... of column c (loads coalesced along
@@ -366,27 +378,14 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
     if (kt.index() == 0 && n < n_out) array(scale, n_out)[n] = m / 448.0f;
   }
   sync(thread);
-  const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
-  for (int t = 0; t < kColTiles; ++t) {
-  const idx_t k0 = (kt.index() * kColTiles + t) * 64;
-  if (k0 >= k_out) break;
-  if (t > 0) sync(thread);                      // the previous tile's codes are read
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
+  for (int i = 0; i < 4; ++i) {
     const idx_t r = ty + 16 * i, c = 4 * tx;
-    f32x4 v;
-    if (vec_in && k0 + r < K && n0 + c + 4 <= N) {
-      v = *(const f32x4*)&b.at(k0 + r, n0 + c);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        v[j] = (k0 + r < K && n0 + c + j < N) ? b.at(k0 + r, n0 + c + j) : 0.f;
-    }
     uint32_t keep = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) keep |= (k0 + r < K && n0 + c + j < N) ? (0xffu << (8 * j)) : 0u;
-    const uint32_t w = lowp::e4m3x4(v[0] * inv_s[c], v[1] * inv_s[c + 1], v[2] * inv_s[c + 2],
-                                    v[3] * inv_s[c + 3]) & keep;
+    const uint32_t w = lowp::e4m3x4(v[i][0] * inv_s[c], v[i][1] * inv_s[c + 1],
+                                    v[i][2] * inv_s[c + 2], v[i][3] * inv_s[c + 3]) & keep;
     *(u8x4*)&tile.at(r, c) = __builtin_bit_cast(u8x4, w);
   }
   sync(thread);
@@ -404,7 +403,6 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
       for (int j = 0; j < 4; ++j)
         if (k0 + r + j < k_out) out.at(n0 + c, k0 + r + j) = e[j];
     }
-  }
   }
 }
 
@@ -557,7 +555,7 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
                      dim3((unsigned)((N + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
                      dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N, f4_ok(B, ldb));
   hipLaunchKernelGGL(quant_cols_t_kernel,
-                     dim3((unsigned)((K + 64 * kColTiles - 1) / (64 * kColTiles)),
+                     dim3((unsigned)((K + 63) / 64),
                           (unsigned)((N + 63) / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale,
                      f4_ok(B, ldb), w_ok(qt, ldq, 1));
@@ -609,7 +607,7 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
                      A, M, K, lda, qa, L.Mp, L.Kp, L.Kp, sa, f4_ok(A, lda), B, N, ldb, rows_per,
                      part, L.Np, f4_ok(B, ldb), cblocks, S);
   hipLaunchKernelGGL(quant_cols_t_kernel,
-                     dim3((unsigned)((L.Kp + 64 * kColTiles - 1) / (64 * kColTiles)),
+                     dim3((unsigned)(L.Kp / 64),
                           (unsigned)(L.Np / 64)),
                      dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb,
                      f4_ok(B, ldb), true);
