@@ -198,9 +198,12 @@ def op_views(desc, torch, workloads, reps: int = 100):
             for _ in range(3):
                 fv(); fh()
             tv, th = Timer(torch), Timer(torch)
-            for _ in range(reps):
-                e = tv.start(); fv(); tv.stop(e)
-                e = th.start(); fh(); th.stop(e)
+            for i in range(reps):
+                # alternate which of the pair runs first, so neither gains
+                # from the other's warm-up of clocks and caches
+                order = ((tv, fv), (th, fh)) if i % 2 == 0 else ((th, fh), (tv, fv))
+                for tm, fn in order:
+                    e = tm.start(); fn(); tm.stop(e)
             torch.cuda.synchronize()
             mv, mh = median_ms(tv), median_ms(th)
             r = {"op": name, "memory_MB": mb, "view_us": round(mv * 1e3, 2),

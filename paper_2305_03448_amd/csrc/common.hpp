@@ -36,6 +36,15 @@ __device__ __forceinline__ void store_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A buffer resource over `bytes` bytes from `base` (raw, 32-bit elements):
+// a buffer load at a byte offset >= bytes returns zero without touching
+// memory.  The GEMM tiles address their stages through such ranges, with
+// the offsets given by the BufferWindow view over each range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  constexpr int kRawDword3 = 0x00020000;   // gfx9 word 3: 32-bit data format, no swizzle
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kRawDword3);
+}
+
 // Wait until every global memory access this wave issued has completed
 // (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).  After it a
 // device-scope atomic store is visible to every agent-scope reader.

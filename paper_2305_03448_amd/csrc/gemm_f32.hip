@@ -44,7 +44,11 @@ void gemm_f32w_kernel(
   const GemmProblemF32 p{A, lda, B, ldb, Cm, ldc, M, N, K};
   const idx_t tiles_n = (N + C::bn - 1) / C::bn;
   const idx_t t = gemm_f32::xcd_tile(block_x(), (M + C::bm - 1) / C::bm, tiles_n);
-  gemm_f32::tile_rowmajor<C, kVec>(p, t / tiles_n, t % tiles_n, lds);
+  const idx_t tm = t / tiles_n, tn = t % tiles_n;
+  if (kVec && gemm_f32::interior_tile<C>(p, tm, tn))
+    gemm_f32::tile_rowmajor<C, true, true>(p, tm, tn, lds);
+  else
+    gemm_f32::tile_rowmajor<C, kVec>(p, tm, tn, lds);
 }
 
 template <class C>

@@ -204,7 +204,25 @@ struct GemmCfgF32W {
   static_assert(kBK % 8 == 0 && kBN % 4 == 0, "whole 16-byte groups per half stage");
 };
 
-template <class C, bool kVec>
+// An interior tile of the row-major form: the whole tile inside C, K a
+// multiple of BK, and each operand's span of the tile below 2^31 bytes
+// (A's BM rows, B's BN columns over all K), operands 16-byte aligned with
+// leading dimensions that are multiples of 4.  Then every stage's loads are
+// whole 16-byte groups inside the operands.
+template <class C>
+__device__ __forceinline__ bool interior_tile(const GemmProblemF32& p, idx_t tm, idx_t tn) {
+  constexpr int64_t kSpan = int64_t(1) << 29;   // elements: 2^31 bytes
+  return (tm + 1) * C::bm <= p.M && (tn + 1) * C::bn <= p.N && p.K > 0 && p.K % C::bk == 0 &&
+         (C::bm - 1) * p.lda + p.K < kSpan && (p.K - 1) * p.ldb + C::bn < kSpan &&
+         vec_ok(p.A, p.lda, p.B, p.ldb);
+}
+
+// kInterior (interior_tile holds): each lane's positions inside a stage are
+// the same in every stage, so its loads are fixed byte offsets in one buffer
+// range over the tile's rows of A (or columns of B) for the whole K loop,
+// and a stage moves only the scalar offset -- no address arithmetic and no
+// bounds handling per load.
+template <class C, bool kVec, bool kInterior = false>
 __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm, idx_t tn,
                                               float* lds) {
   constexpr int BM = C::bm, BN = C::bn, BK = C::bk, T = C::threads, HK = BK / 2;
@@ -230,8 +248,40 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
   // clamped position and zeroed when outside -- no branch per load, which
   // would keep a second set of registers live.  Otherwise single guarded
   // loads.
+  // the interior form's ranges and each lane's offsets in them
+  const BufferWindow<4> win_a{(uint32_t)p.lda, BM, (int32_t)p.K};
+  const BufferWindow<4> win_b{(uint32_t)p.ldb, (int32_t)p.K, BN};
+  __amdgpu_buffer_rsrc_t rs_a, rs_b;
+  uint32_t off_a[C::a_vec], off_b[C::b_vec];
+  if constexpr (kInterior) {
+    rs_a = buffer_rsrc(&a_g.at(m0, 0), win_a.bytes());
+    rs_b = buffer_rsrc(&b_g.at(0, n0), win_b.bytes());
+#pragma unroll
+    for (int i = 0; i < C::a_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      off_a[i] = win_a.offset(q / (BK / 4), 4 * (q % (BK / 4)));
+    }
+#pragma unroll
+    for (int i = 0; i < C::b_vec; ++i) {
+      const int q = (int)thread.index() + T * i;
+      off_b[i] = win_b.offset(q / (BN / 4), 4 * (q % (BN / 4)));
+    }
+  }
   auto load = [&](idx_t kt, Regs& R) {
     const idx_t k0 = kt * BK;
+    if constexpr (kInterior) {
+      // stage kt: k0 columns into A's range, k0 rows into B's
+      const int sa = (int)win_a.offset(0, (int32_t)k0), sb = (int)win_b.offset((int32_t)k0, 0);
+#pragma unroll
+      for (int i = 0; i < C::a_vec; ++i)
+        R.a[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_a, (int)off_a[i],
+                                                                                  sa, 0));
+#pragma unroll
+      for (int i = 0; i < C::b_vec; ++i)
+        R.b[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_b, (int)off_b[i],
+                                                                                  sb, 0));
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < C::a_vec; ++i) {
       const int q = (int)thread.index() + T * i;

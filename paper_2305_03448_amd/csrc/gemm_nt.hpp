@@ -173,15 +173,6 @@ struct F32Operands {
   int64_t M, N, K;
 };
 
-// A buffer resource over `bytes` bytes from `base` (raw, 32-bit elements):
-// a buffer load at a byte offset >= bytes returns zero without touching
-// memory, which is how the split source below handles every edge (its
-// offsets come from the BufferWindow view over each range).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
-  constexpr int kRawDword3 = 0x00020000;   // gfx9 word 3: 32-bit data format, no swizzle
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kRawDword3);
-}
-
 // The strides the split source accepts: its buffer offsets, at most 16 rows
 // of A or 8 rows of B from a range's base, stay below 2^31.
 constexpr int64_t kSplitMaxLd = int64_t(1) << 24;

@@ -11,9 +11,9 @@
 //              non-temporal loads and stores, 256-word look-back window
 //              (the configuration the library runs from 2^24 elements);
 //   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32];
-//   FP32 GEMM  256 x 128 x 16 tiles, 2 x 2 waves, A row-major in LDS, loads
-//              two stages ahead (the configuration the library runs from
-//              2^30 M N K on).
+//   FP32 GEMM  128 x 128 x 16 tiles, 2 x 2 waves, A row-major in LDS, loads
+//              two stages ahead, interior tiles through buffer ranges (the
+//              configuration the library runs from 2^30 M N K on).
 // Only the index expressions differ: here they are written out by hand
 // instead of being derived from a composition of views.  The helpers shared
 // with the library (relaxed status-word atomics, DPP wave sums) hold no index
@@ -328,12 +328,12 @@ __global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------- FP32 GEMM
-// Twin of gemm_f32w_kernel<GemmCfgF32W<256, 128, 16, 2, 2, 2>> (the library's
-// FP32 GEMM from 2^30 M N K on): 256 threads as 2 x 2 waves of 128 x 64, A
+// Twin of gemm_f32w_kernel<GemmCfgF32W<128, 128, 16, 2, 2, 2>> (the library's
+// FP32 GEMM from 2^30 M N K on): 256 threads as 2 x 2 waves of 64 x 64, A
 // staged in LDS as [m][k] (pitch 20 words) and B as [k][n] (pitch 132), two
 // LDS buffers, loads two stages ahead through two register sets, the
 // matrix instruction's two k slots taking the two halves of a stage.
-constexpr int kGM = 256, kGN = 128, kGK = 16, kGT = 256, kGWN = 2;
+constexpr int kGM = 128, kGN = 128, kGK = 16, kGT = 256, kGWN = 2;
 constexpr int kGWTM = kGM / 2, kGWTN = kGN / 2, kGFM = kGWTM / 32, kGFN = kGWTN / 32;
 constexpr int kGPA = kGK + 4, kGPB = kGN + 4;
 constexpr int kGAV = kGM * kGK / 4 / kGT, kGBV = kGK * kGN / 4 / kGT;
@@ -350,25 +350,55 @@ __device__ __forceinline__ int64_t gemm_tile_of(int64_t u, int64_t tiles_m, int6
   return (first_m + r % gsize) * tiles_n + r / gsize;
 }
 
-template <bool kVec>
-__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(2)))
-void gemm_f32_hand(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
-                   int64_t ldb, float* __restrict__ Cm, int64_t ldc, int64_t M, int64_t N,
-                   int64_t K) {
-  __shared__ __attribute__((aligned(16))) float lds[kGLds];
-  float* const a_lds = lds;                          // [2][256][20]
+// Interior tiles (the whole tile inside C, K a multiple of 16, each
+// operand's span below 2^31 bytes, 16-byte aligned operands with leading
+// dimensions that are multiples of 4): the loads are buffer loads at fixed
+// per-lane byte offsets, the stage moving only the scalar offset.
+template <bool kVec, bool kInterior>
+__device__ __forceinline__ void gemm_f32_hand_tile(
+    const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
+    float* __restrict__ Cm, int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t m0, int64_t n0,
+    float* lds) {
+  float* const a_lds = lds;                          // [2][128][20]
   float* const b_lds = lds + 2 * kGM * kGPA;         // [2][16][132]
-  const int64_t tiles_n = (N + kGN - 1) / kGN;
-  const int64_t t = gemm_tile_of(blockIdx.x, (M + kGM - 1) / kGM, tiles_n);
-  const int64_t m0 = t / tiles_n * kGM, n0 = t % tiles_n * kGN;
   const int tid = (int)threadIdx.x, lane = tid % 64, w = tid / 64;
   const int half = lane / 32, col32 = lane % 32, wm = w / kGWN, wn = w % kGWN;
   struct Regs {
     f32x4 a[kGAV], b[kGBV];
   };
   Regs R0, R1;
+  __amdgpu_buffer_rsrc_t rs_a, rs_b;
+  uint32_t off_a[kGAV], off_b[kGBV];
+  if constexpr (kInterior) {
+    rs_a = __builtin_amdgcn_make_buffer_rsrc((void*)(A + m0 * lda), 0,
+                                             (int)(((kGM - 1) * lda + K) * 4), 0x00020000);
+    rs_b = __builtin_amdgcn_make_buffer_rsrc((void*)(B + n0), 0,
+                                             (int)(((K - 1) * ldb + kGN) * 4), 0x00020000);
+#pragma unroll
+    for (int i = 0; i < kGAV; ++i) {
+      const int q = tid + kGT * i;
+      off_a[i] = (uint32_t)(q / (kGK / 4)) * (uint32_t)lda * 4u + 16u * (uint32_t)(q % (kGK / 4));
+    }
+#pragma unroll
+    for (int i = 0; i < kGBV; ++i) {
+      const int q = tid + kGT * i;
+      off_b[i] = (uint32_t)(q / (kGN / 4)) * (uint32_t)ldb * 4u + 16u * (uint32_t)(q % (kGN / 4));
+    }
+  }
   auto load = [&](int64_t kt, Regs& R) {
     const int64_t k0 = kt * kGK;
+    if constexpr (kInterior) {
+      const int sa = (int)(k0 * 4), sb = (int)((uint32_t)k0 * (uint32_t)ldb * 4u);
+#pragma unroll
+      for (int i = 0; i < kGAV; ++i)
+        R.a[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_a, (int)off_a[i],
+                                                                                  sa, 0));
+#pragma unroll
+      for (int i = 0; i < kGBV; ++i)
+        R.b[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_b, (int)off_b[i],
+                                                                                  sb, 0));
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < kGAV; ++i) {
       const int q = tid + kGT * i;
@@ -494,6 +524,26 @@ void gemm_f32_hand(const float* __restrict__ A, int64_t lda, const float* __rest
           if (row < M && col < N) Cm[row * ldc + col] = acc[i][j][r];
         }
   }
+}
+
+template <bool kVec>
+__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(2)))
+void gemm_f32_hand(const float* __restrict__ A, int64_t lda, const float* __restrict__ B,
+                   int64_t ldb, float* __restrict__ Cm, int64_t ldc, int64_t M, int64_t N,
+                   int64_t K) {
+  __shared__ __attribute__((aligned(16))) float lds[kGLds];
+  const int64_t tiles_n = (N + kGN - 1) / kGN;
+  const int64_t t = gemm_tile_of(blockIdx.x, (M + kGM - 1) / kGM, tiles_n);
+  const int64_t m0 = t / tiles_n * kGM, n0 = t % tiles_n * kGN;
+  constexpr int64_t kSpan = int64_t(1) << 29;
+  const bool interior = m0 + kGM <= M && n0 + kGN <= N && K > 0 && K % kGK == 0 &&
+                        (kGM - 1) * lda + K < kSpan && (K - 1) * ldb + kGN < kSpan &&
+                        ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0 && lda % 4 == 0 &&
+                        ldb % 4 == 0;
+  if (kVec && interior)
+    gemm_f32_hand_tile<true, true>(A, lda, B, ldb, Cm, ldc, M, N, K, m0, n0, lds);
+  else
+    gemm_f32_hand_tile<kVec, false>(A, lda, B, ldb, Cm, ldc, M, N, K, m0, n0, lds);
 }
 
 // ---------------------------------------------------------------- e4m3 check
