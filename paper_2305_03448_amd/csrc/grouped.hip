@@ -205,11 +205,13 @@ void grouped_gemm_kernel(const desc_gemm_problem* probs,
     const idx_t local = t - ts[slot];
     const bool vec = gemm_f32::vec_ok(p.A, p.lda, p.B, p.ldb);
     if constexpr (kRm) {
-      const idx_t tn = (p.N + 63) / 64;
-      if (vec && p.K % 4 == 0 && p.N % 4 == 0 && p.K > 0)
-        gemm_f32::tile_rowmajor<SmallTileRm, true>(q, local / tn, local % tn, lds);
+      const idx_t tn = (p.N + 63) / 64, tm_ = local / tn, tn_ = local % tn;
+      if (vec && gemm_f32::interior_tile<SmallTileRm>(q, tm_, tn_))
+        gemm_f32::tile_rowmajor<SmallTileRm, true, true>(q, tm_, tn_, lds);
+      else if (vec && p.K % 4 == 0 && p.N % 4 == 0 && p.K > 0)
+        gemm_f32::tile_rowmajor<SmallTileRm, true>(q, tm_, tn_, lds);
       else
-        gemm_f32::tile_rowmajor<SmallTileRm, false>(q, local / tn, local % tn, lds);
+        gemm_f32::tile_rowmajor<SmallTileRm, false>(q, tm_, tn_, lds);
     } else if (kBig && b) {
       const idx_t tn = (p.N + 127) / 128;
       if (vec) gemm_f32::tile<BigTile, true>(q, local / tn, local % tn, lds);
