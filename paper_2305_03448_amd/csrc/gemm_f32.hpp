@@ -271,7 +271,7 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
     const idx_t k0 = kt * BK;
     if constexpr (kInterior) {
       // stage kt: k0 columns into A's range, k0 rows into B's
-      const int sa = (int)win_a.offset(0, (int32_t)k0), sb = (int)win_b.offset((int32_t)k0, 0);
+      const int sa = (int)win_a.col_valid((int32_t)k0), sb = (int)win_b.row((int32_t)k0);
 #pragma unroll
       for (int i = 0; i < C::a_vec; ++i)
         R.a[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_a, (int)off_a[i],

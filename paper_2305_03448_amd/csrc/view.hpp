@@ -359,6 +359,9 @@ struct BufferWindow {
   DESC_HD uint32_t row(int32_t r) const { return (uint32_t)r * ld * kBytes; }
   DESC_HD uint32_t col(int32_t c) const { return c < cols ? (uint32_t)c * kBytes : kOutside; }
   DESC_HD uint32_t offset(int32_t r, int32_t c) const { return row(r) + col(c); }
+  // The column part of a column the caller knows to be valid (c < cols),
+  // without the test.
+  DESC_HD uint32_t col_valid(int32_t c) const { return (uint32_t)c * kBytes; }
 };
 
 // An array of n elements of type T at p (rank 1) or a rows x cols matrix.
