@@ -415,12 +415,12 @@ int64_t colmax_slices(int64_t K, int64_t N) {
 }
 
 // ------------------------------------------------------------------ GEMM launch
-template <class C>
+template <class C, bool kBuf>
 __global__ __launch_bounds__(C::threads) void gemm_nt_kernel(NtOperands p, int64_t tiles_m,
                                                              int64_t tiles_n) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[C::lds_bytes];
   const idx_t t = gemm_f32::xcd_tile(block_x(), tiles_m, tiles_n);
-  gemm_nt::tile<C>(p, t / tiles_n, t % tiles_n, lds);
+  gemm_nt::tile<C, kBuf>(p, t / tiles_n, t % tiles_n, lds);
 }
 
 // Split-BF16 tiles straight from the FP32 operands (no pre-pass).
@@ -446,11 +446,18 @@ hipError_t launch_split(const gemm_nt::F32Operands& f, float* Cm, int64_t ldc, h
   return hipGetLastError();
 }
 
+// The buffer-range loads need a tile's rows of a plane to span less than
+// 2^31 bytes (K up to about 8M FP8 or 4M BF16 values at 256-row tiles).
 template <class C>
 hipError_t launch_nt(const NtOperands& p, int64_t Mp, int64_t Np, hipStream_t s) {
   const int64_t tm = Mp / C::bm, tn = Np / C::bn;
-  hipLaunchKernelGGL((gemm_nt_kernel<C>), dim3((unsigned)(tm * tn)), dim3(C::threads), 0, s, p, tm,
-                     tn);
+  const int64_t rows = C::bm > C::bn ? C::bm : C::bn;
+  if (rows * p.row_bytes < (int64_t(1) << 31))
+    hipLaunchKernelGGL((gemm_nt_kernel<C, true>), dim3((unsigned)(tm * tn)), dim3(C::threads), 0,
+                       s, p, tm, tn);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<C, false>), dim3((unsigned)(tm * tn)), dim3(C::threads), 0,
+                       s, p, tm, tn);
   return hipGetLastError();
 }
 

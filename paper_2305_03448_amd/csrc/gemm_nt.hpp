@@ -110,7 +110,11 @@ struct Frag<32> {
 // plane(pl).  stages() is the number of stages of the K loop.
 //
 // PlaneSource: padded planes prepared by an operand pre-pass (no guards).
-template <class C>
+// kBuf (a tile's rows of each plane span less than 2^31 bytes): the loads go
+// through one buffer range per plane over the tile's rows, at per-lane byte
+// offsets that are the same in every stage, the stage moving only the
+// scalar offset.
+template <class C, bool kBuf = false>
 struct PlaneSource {
   using Mode = typename C::mode;
   static constexpr int P = Mode::planes, T = C::threads, CPR = C::chunks;
@@ -127,6 +131,30 @@ struct PlaneSource {
   __device__ __forceinline__ void load(idx_t kt, Regs& R) const {
     const idx_t k0b = kt * C::bkb;
     const int t = (int)thread_x<T>().index();
+    if constexpr (kBuf) {
+      const BufferWindow<1> wa{(uint32_t)p.row_bytes, C::bm, (int32_t)p.row_bytes};
+      const BufferWindow<1> wb{(uint32_t)p.row_bytes, C::bn, (int32_t)p.row_bytes};
+#pragma unroll
+      for (int pl = 0; pl < P; ++pl) {
+        const auto ra = buffer_rsrc(&matrix(p.a[pl], 0, p.row_bytes).at(m0, 0), wa.bytes());
+        const auto rb = buffer_rsrc(&matrix(p.b[pl], 0, p.row_bytes).at(n0, 0), wb.bytes());
+#pragma unroll
+        for (int i = 0; i < C::a_chunks; ++i) {
+          const int q = t + T * i;
+          R.a[pl][i] = __builtin_bit_cast(
+              u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                         ra, (int)(wa.row(q / CPR) + wa.col_valid(16 * (q % CPR))), (int)k0b, 0));
+        }
+#pragma unroll
+        for (int i = 0; i < C::b_chunks; ++i) {
+          const int q = t + T * i;
+          R.b[pl][i] = __builtin_bit_cast(
+              u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                         rb, (int)(wb.row(q / CPR) + wb.col_valid(16 * (q % CPR))), (int)k0b, 0));
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int pl = 0; pl < P; ++pl) {
       auto ag = matrix(p.a[pl], 0, p.row_bytes);
@@ -415,13 +443,28 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
   auto compute_pipe = [&](auto stage) {
     using F = gemm_nt::Frag<32>;
     auto s = plane(stage, 0);
-    auto read = [&](int st, idx_t row, F& f) {
-      const int ch = (st * Mode::step_bytes + half * LB) / 16;
-      f.v0 = s.at(row, ch);
-      f.v1 = s.at(row, ch + 1);
+    // Rows 32 apart share the swizzle (its period, rows_per_256 x chunks
+    // rows, divides 32), so a lane's fragments of one step lie whole 32-row
+    // blocks apart: the chunk addresses of its first fragment come from the
+    // view, the others are constant offsets from them (LDS read immediates
+    // instead of an address computation per read).
+    static_assert(32 % (C::rows_per_256 * C::chunks) == 0, "the swizzle repeats every 32 rows");
+    constexpr int kFragStride = 32 * C::chunks;   // 16-byte chunks between fragments
+    const u32x4* first[2][C::steps][2];
+#pragma unroll
+    for (int st = 0; st < C::steps; ++st)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ch = (st * Mode::step_bytes + half * LB) / 16 + e;
+        first[0][st][e] = &s.at(wm * C::wtm + col32, ch);
+        first[1][st][e] = &s.at(C::bm + wn * C::wtn + col32, ch);
+      }
+    auto read = [&](int op, int st, int k, F& f) {
+      f.v0 = first[op][st][0][k * kFragStride];
+      f.v1 = first[op][st][1][k * kFragStride];
     };
-    auto read_a = [&](int st, int i, F& f) { read(st, wm * C::wtm + i * 32 + col32, f); };
-    auto read_b = [&](int st, int j, F& f) { read(st, C::bm + wn * C::wtn + j * 32 + col32, f); };
+    auto read_a = [&](int st, int i, F& f) { read(0, st, i, f); };
+    auto read_b = [&](int st, int j, F& f) { read(1, st, j, f); };
     constexpr unsigned kDsRead = 0x100, kMatrix = 0x008;   // sched_group_barrier masks
     F fa[2], fb[2][C::fn];
 #pragma unroll
@@ -584,9 +627,9 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
 }
 
 // A tile of C from padded planes (the operand pre-pass layout).
-template <class C>
+template <class C, bool kBuf = false>
 __device__ __forceinline__ void tile(const NtOperands& p, idx_t tm, idx_t tn, uint8_t* lds) {
-  const PlaneSource<C> src{p, tm * C::bm, tn * C::bn};
+  const PlaneSource<C, kBuf> src{p, tm * C::bm, tn * C::bn};
   tile_from<C>(src, NtEpilogue{p.C, p.ldc, p.M, p.N, p.sa, p.sb}, tm, tn, lds);
 }
 

@@ -142,9 +142,14 @@ struct XorMap {
   static_assert(D + 1 < P::rank, "xor_swizzle needs two dimensions");
   P p;
   DESC_HD idx_t ext(int d) const { return p.ext(d); }
+  // Positions are never negative, so the row term is taken in unsigned
+  // arithmetic: with power-of-two kDiv and kMod it is then a shift and a
+  // mask, and rows that differ by a multiple of kDiv * kMod visibly share it
+  // (the compiler can then reuse one address for all of them).
   DESC_HD Idx<rank> to_parent(const Idx<rank>& i) const {
     Idx<rank> j = i;
-    j[D + 1] = i[D + 1] ^ (((i[D] / kDiv) % kMod) * kMul);
+    const uint64_t r = (uint64_t)i[D];
+    j[D + 1] = i[D + 1] ^ (idx_t)(((r / (uint64_t)kDiv) % (uint64_t)kMod) * (uint64_t)kMul);
     return j;
   }
 };

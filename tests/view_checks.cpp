@@ -267,8 +267,13 @@ int main(int argc, char** argv) {
       for (int q = q0; q < q0 + 16; ++q) g.insert((&v.at(q / CPR, q % CPR) - lds.data()) % 16);
       writes_ok &= g.size() == 16;
     }
+    // the pipelined FP8 reads step from a lane's first fragment to the next
+    // by whole 32-row blocks: the swizzle must repeat every 32 rows
+    bool period_ok = true;
+    for (int r = 0; r + 32 < rows; ++r)
+      for (int c = 0; c < CPR; ++c) period_ok &= &v.at(r + 32, c) == &v.at(r, c) + 32 * CPR;
     const std::string name = "gemm_lds_xor_swizzle_bkb" + std::to_string(BKB);
-    check(all.bijection() && reads_ok && writes_ok, name.c_str());
+    check(all.bijection() && reads_ok && writes_ok && period_ok, name.c_str());
   };
   swizzle_case(std::integral_constant<int, 32>{});
   swizzle_case(std::integral_constant<int, 64>{});
