@@ -146,10 +146,12 @@ def test_gemm_strided_rows(mode):
     _check_sampled(A, B, C, TOL[mode], samples=77 * 53)
 
 
-@pytest.mark.parametrize("M,N,K,pad", [(300, 200, 136, 0), (77, 53, 45, 3), (260, 516, 68, 0)])
+@pytest.mark.parametrize("M,N,K,pad", [(300, 200, 136, 0), (77, 53, 45, 3), (260, 516, 68, 0),
+                                       (300, 200, 128, 0), (520, 392, 96, 4)])
 def test_gemm_f32_every_config(M, N, K, pad):
     # aligned groups of four with ragged tiles, then single loads (odd K, N,
-    # unaligned rows)
+    # unaligned rows); with K a multiple of 16 the tiles wholly inside C take
+    # the buffer-range loads and the others the guarded ones, in one call
     A = _int_matrix(M, K, 11); B = _int_matrix(K, N, 12)
     exact = (A.astype(np.int64) @ B.astype(np.int64)).astype(np.float32)
     cls = desc.desc_size_class("gemm_f32", M * N * K)
