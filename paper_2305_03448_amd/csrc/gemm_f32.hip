@@ -82,10 +82,11 @@ hipError_t launch_gemm(const float* A, int64_t lda, const float* B, int64_t ldb,
 // "_rm": the row-major-A tile form; "_w8": eight waves (2 x 4).
 constexpr const char* kNames[] = {"m128n128k16", "m256n128k16", "m128n128k32", "m64n64k16",
                                   "m256n256k16_rm_w8_d2", "m256n128k16_rm", "m256n128k16_rm_d2",
-                                  "m128n128k16_rm", "m128n128k16_rm_d2"};
+                                  "m128n128k16_rm", "m128n128k16_rm_d2", "m128n128k16_rm_d2_x16",
+                                  "m256n128k16_rm_d2_x16"};
 constexpr int kDefaults[tune::kClasses] = {3, 0, 0, 0};
 const bool kRegistered =
-    (tune::register_op(tune::kGemmF32, "gemm_f32", 9, kNames, kDefaults), true);
+    (tune::register_op(tune::kGemmF32, "gemm_f32", 11, kNames, kDefaults), true);
 
 }  // namespace
 
@@ -109,6 +110,10 @@ hipError_t gemm_f32(const float* A, int64_t lda, const float* B, int64_t ldb, fl
       return launch_gemm_w<gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2>>(A, lda, B, ldb, Cm, ldc, M, N, K, s);
     case 8:
       return launch_gemm_w<gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2>>(A, lda, B, ldb, Cm, ldc, M, N, K, s);
+    case 9:
+      return launch_gemm_w<gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2, true>>(A, lda, B, ldb, Cm, ldc, M, N, K, s);
+    case 10:
+      return launch_gemm_w<gemm_f32::GemmCfgF32W<256, 128, 16, 2, 2, 2, true>>(A, lda, B, ldb, Cm, ldc, M, N, K, s);
     default: return launch_gemm<GemmCfgF32<128, 128, 16>>(A, lda, B, ldb, Cm, ldc, M, N, K, s);
   }
 }

@@ -1,6 +1,8 @@
 // gemm_f32.hpp -- the FP32 matrix-core tile routine shared by the plain and
 // the grouped GEMM.  See gemm_f32.hip for the scheme.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 #include "layouts.hpp"
 #include "mfma.hpp"
@@ -188,12 +190,22 @@ __device__ __forceinline__ void tile(const GemmProblemF32& p, idx_t tm, idx_t tn
 // lanes 0-31 carry k = kk and lanes 32-63 k = BK/2 + kk at step kk, so a
 // lane's A values for a stage are contiguous (the same assignment for A and
 // B keeps the product exact).  B stays [k][n] with pitch BN + 4.
-template <int kBM, int kBN, int kBK, int kWM, int kWN, int kDepth = 1>
+//
+// k16: 16 x 16 x 4 instructions instead of 32 x 32 x 2 (the stage's four k
+// quarters on the instruction's four k slots).  Same work per stage and the
+// same LDS traffic; the smaller instruction sustains a higher rate on this
+// part (measured: 139 against 125 TFLOP/s in a loop of independent
+// instructions on every CU).
+template <int kBM, int kBN, int kBK, int kWM, int kWN, int kDepth = 1, bool kK16 = false>
 struct GemmCfgF32W {
   static constexpr int bm = kBM, bn = kBN, bk = kBK, threads = 64 * kWM * kWN, depth = kDepth;
   static constexpr int wm = kWM, wn = kWN;
+  static constexpr bool k16 = kK16;
+  static constexpr int frag = kK16 ? 16 : 32;             // fragment edge
   static constexpr int wtm = kBM / kWM, wtn = kBN / kWN;
-  static constexpr int fm = wtm / 32, fn = wtn / 32;
+  static constexpr int fm = wtm / frag, fn = wtn / frag;
+  using acc_t = typename std::conditional<kK16, f32x4, mfma::f32x16>::type;
+  static constexpr int acc_regs = kK16 ? 4 : 16;
   static constexpr int pa = kBK + 4, pb = kBN + 4;        // LDS pitches (words)
   static constexpr int a_vec = kBM * kBK / 4 / threads;    // float4 per thread per stage
   static constexpr int b_vec = kBK * kBN / 4 / threads;
@@ -202,6 +214,7 @@ struct GemmCfgF32W {
   static_assert(a_vec * threads * 4 == kBM * kBK && b_vec * threads * 4 == kBK * kBN,
                 "stage divides evenly among the threads");
   static_assert(kBK % 8 == 0 && kBN % 4 == 0, "whole 16-byte groups per half stage");
+  static_assert(!kK16 || kBK == 16, "16 x 16 x 4 form: a lane's quarter is one 16-byte read");
 };
 
 // An interior tile of the row-major form: the whole tile inside C, K a
@@ -326,18 +339,38 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
     }
   };
 
-  mfma::f32x16 acc[C::fm][C::fn];
+  typename C::acc_t acc[C::fm][C::fn];
 #pragma unroll
   for (int i = 0; i < C::fm; ++i)
 #pragma unroll
     for (int j = 0; j < C::fn; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      for (int r = 0; r < C::acc_regs; ++r) acc[i][j][r] = 0.f;
 
   // matrix ops of the stage in LDS buffer `buf`
   auto compute = [&](int buf) {
     auto as = a_lds.idx(buf);
     auto bs = b_lds.idx(buf);
+    if constexpr (C::k16) {
+      const int quarter = lane / 16, c16 = lane % 16;
+      f32x4 a[C::fm];
+#pragma unroll
+      for (int i = 0; i < C::fm; ++i)
+        a[i] = *(const f32x4*)&as.at(layout::gemm16_a_frag_row<C::wtm>(wm, i, c16),
+                                      layout::gemm16_frag_k<BK>(quarter));
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        float b[C::fn];
+#pragma unroll
+        for (int j = 0; j < C::fn; ++j)
+          b[j] = bs.at(layout::gemm16_frag_k<BK>(quarter) + kk,
+                       layout::gemm16_b_frag_word<C::wtn>(wn, j, c16));
+#pragma unroll
+        for (int i = 0; i < C::fm; ++i)
+#pragma unroll
+          for (int j = 0; j < C::fn; ++j) acc[i][j] = mfma::f32_16x16x4(a[i][kk], b[j], acc[i][j]);
+      }
+    } else {
 #pragma unroll
     for (int k4 = 0; k4 < HK; k4 += 4) {
       // this lane's four k values of the step group: k = half * HK + k4 + 0..3
@@ -358,6 +391,7 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
 #pragma unroll
           for (int j = 0; j < C::fn; ++j) acc[i][j] = mfma::f32_32x32x2(a[i][kk], b[j], acc[i][j]);
       }
+    }
     }
   };
 
@@ -420,24 +454,30 @@ __device__ __forceinline__ void tile_rowmajor(const GemmProblemF32& p, idx_t tm,
   // its fragment (the row written out in 64-bit arithmetic, so the compiler
   // folds the constant parts into the store offsets).
   auto c_g = matrix(p.C, p.M, p.ldc);
+  // row and column of accumulator register r of fragment (i, j)
+  auto acc_row = [&](int i, int r) -> idx_t {
+    if constexpr (C::k16) return m0 + wm * C::wtm + i * 16 + 4 * (lane / 16) + r;
+    else return m0 + wm * C::wtm + i * 32 + 8 * (r / 4) + 4 * half + r % 4;
+  };
+  auto acc_col = [&](int j) -> idx_t {
+    if constexpr (C::k16) return n0 + wn * C::wtn + j * 16 + lane % 16;
+    else return n0 + wn * C::wtn + j * 32 + col32;
+  };
   if (m0 + BM <= p.M && n0 + BN <= p.N) {
 #pragma unroll
     for (int i = 0; i < C::fm; ++i)
 #pragma unroll
       for (int j = 0; j < C::fn; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          c_g.at(m0 + wm * C::wtm + i * 32 + 8 * (r / 4) + 4 * half + r % 4,
-                 n0 + wn * C::wtn + j * 32 + col32) = acc[i][j][r];
+        for (int r = 0; r < C::acc_regs; ++r) c_g.at(acc_row(i, r), acc_col(j)) = acc[i][j][r];
   } else {
 #pragma unroll
     for (int i = 0; i < C::fm; ++i)
 #pragma unroll
       for (int j = 0; j < C::fn; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const idx_t row = m0 + wm * C::wtm + i * 32 + 8 * (r / 4) + 4 * half + r % 4;
-          const idx_t col = n0 + wn * C::wtn + j * 32 + col32;
+        for (int r = 0; r < C::acc_regs; ++r) {
+          const idx_t row = acc_row(i, r), col = acc_col(j);
           if (row < p.M && col < p.N) c_g.at(row, col) = acc[i][j][r];
         }
   }

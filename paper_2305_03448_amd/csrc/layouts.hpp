@@ -86,6 +86,16 @@ template <int kBK>
 DESC_HD int gemm_frag_k(int half, int k4) { return half * (kBK / 2) + k4; }
 template <int kWTN>
 DESC_HD int gemm_b_frag_word(int wn, int j, int c32) { return wn * kWTN + 32 * j + c32; }
+// The same tile form with 16 x 16 x 4 instructions: the four k slots take
+// the four quarters of the stage (lane l: row or column l % 16 of its
+// fragment, k = (BK / 4) (l / 16) + kk at step kk), so a lane's A values of
+// a stage are again one 16-byte read.
+template <int kWTM>
+DESC_HD int gemm16_a_frag_row(int wm, int i, int c16) { return wm * kWTM + 16 * i + c16; }
+template <int kBK>
+DESC_HD int gemm16_frag_k(int quarter) { return quarter * (kBK / 4); }
+template <int kWTN>
+DESC_HD int gemm16_b_frag_word(int wn, int j, int c16) { return wn * kWTN + 16 * j + c16; }
 
 // Segmented forms (segmented.hip): segment s of length L_s gives
 // ceil(L_s / U) units of at most U consecutive elements; unit_start is the

@@ -11,9 +11,10 @@
 //              non-temporal loads and stores, 256-word look-back window
 //              (the configuration the library runs from 2^24 elements);
 //   transpose  128 x 128 tiles, LDS pitch 129, 256 threads as [8][32];
-//   FP32 GEMM  128 x 128 x 16 tiles, 2 x 2 waves, A row-major in LDS, loads
-//              two stages ahead, interior tiles through buffer ranges (the
-//              configuration the library runs from 2^30 M N K on).
+//   FP32 GEMM  128 x 128 x 16 tiles, 2 x 2 waves of 16 x 16 x 4
+//              instructions, A row-major in LDS, loads two stages ahead,
+//              interior tiles through buffer ranges (the configuration the
+//              library runs from 2^30 M N K on).
 // Only the index expressions differ: here they are written out by hand
 // instead of being derived from a composition of views.  The helpers shared
 // with the library (relaxed status-word atomics, DPP wave sums) hold no index
@@ -328,13 +329,14 @@ __global__ __launch_bounds__(256) void transpose32_hand(const uint32_t* __restri
 }
 
 // ---------------------------------------------------------------- FP32 GEMM
-// Twin of gemm_f32w_kernel<GemmCfgF32W<128, 128, 16, 2, 2, 2>> (the library's
-// FP32 GEMM from 2^30 M N K on): 256 threads as 2 x 2 waves of 64 x 64, A
-// staged in LDS as [m][k] (pitch 20 words) and B as [k][n] (pitch 132), two
-// LDS buffers, loads two stages ahead through two register sets, the
-// matrix instruction's two k slots taking the two halves of a stage.
+// Twin of gemm_f32w_kernel<GemmCfgF32W<128, 128, 16, 2, 2, 2, true>> (the
+// library's FP32 GEMM from 2^30 M N K on): 256 threads as 2 x 2 waves of
+// 64 x 64 in 16 x 16 fragments, A staged in LDS as [m][k] (pitch 20 words)
+// and B as [k][n] (pitch 132), two LDS buffers, loads two stages ahead
+// through two register sets, the 16 x 16 x 4 instruction's four k slots
+// taking the four quarters of a stage.
 constexpr int kGM = 128, kGN = 128, kGK = 16, kGT = 256, kGWN = 2;
-constexpr int kGWTM = kGM / 2, kGWTN = kGN / 2, kGFM = kGWTM / 32, kGFN = kGWTN / 32;
+constexpr int kGWTM = kGM / 2, kGWTN = kGN / 2, kGFM = kGWTM / 16, kGFN = kGWTN / 16;
 constexpr int kGPA = kGK + 4, kGPB = kGN + 4;
 constexpr int kGAV = kGM * kGK / 4 / kGT, kGBV = kGK * kGN / 4 / kGT;
 constexpr int kGLds = 2 * kGM * kGPA + 2 * kGK * kGPB;
@@ -440,33 +442,31 @@ __device__ __forceinline__ void gemm_f32_hand_tile(
       *(f32x4*)(b_lds + (buf * kGK + q / (kGN / 4)) * kGPB + 4 * (q % (kGN / 4))) = R.b[i];
     }
   };
-  f32x16 acc[kGFM][kGFN];
+  f32x4 acc[kGFM][kGFN];
 #pragma unroll
   for (int i = 0; i < kGFM; ++i)
 #pragma unroll
     for (int j = 0; j < kGFN; ++j)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.f;
+  const int quarter = lane / 16, c16 = lane % 16;
   auto compute = [&](int buf) {
+    f32x4 a[kGFM];
 #pragma unroll
-    for (int k4 = 0; k4 < kGK / 2; k4 += 4) {
-      f32x4 a[kGFM];
+    for (int i = 0; i < kGFM; ++i)
+      a[i] = *(const f32x4*)(a_lds + (buf * kGM + wm * kGWTM + i * 16 + c16) * kGPA +
+                             quarter * (kGK / 4));
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      float b[kGFN];
+#pragma unroll
+      for (int j = 0; j < kGFN; ++j)
+        b[j] = b_lds[(buf * kGK + quarter * (kGK / 4) + kk) * kGPB + wn * kGWTN + j * 16 + c16];
 #pragma unroll
       for (int i = 0; i < kGFM; ++i)
-        a[i] = *(const f32x4*)(a_lds + (buf * kGM + wm * kGWTM + i * 32 + col32) * kGPA +
-                               half * (kGK / 2) + k4);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        float b[kGFN];
 #pragma unroll
         for (int j = 0; j < kGFN; ++j)
-          b[j] = b_lds[(buf * kGK + half * (kGK / 2) + k4 + kk) * kGPB + wn * kGWTN + j * 32 + col32];
-#pragma unroll
-        for (int i = 0; i < kGFM; ++i)
-#pragma unroll
-          for (int j = 0; j < kGFN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][kk], b[j], acc[i][j], 0, 0, 0);
-      }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][kk], b[j], acc[i][j], 0, 0, 0);
     }
   };
   const int64_t nk = (K + kGK - 1) / kGK;
@@ -502,25 +502,25 @@ __device__ __forceinline__ void gemm_f32_hand_tile(
     compute(0);
     __syncthreads();
   }
-  // accumulator register r of lane l: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+  // accumulator register r of lane l: row 4 (l / 16) + r, column l % 16
   if (m0 + kGM <= M && n0 + kGN <= N) {
 #pragma unroll
     for (int i = 0; i < kGFM; ++i)
 #pragma unroll
       for (int j = 0; j < kGFN; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          Cm[(m0 + wm * kGWTM + i * 32 + 8 * (r / 4) + 4 * half + r % 4) * ldc + n0 + wn * kGWTN +
-             j * 32 + col32] = acc[i][j][r];
+        for (int r = 0; r < 4; ++r)
+          Cm[(m0 + wm * kGWTM + i * 16 + 4 * quarter + r) * ldc + n0 + wn * kGWTN + j * 16 + c16] =
+              acc[i][j][r];
   } else {
 #pragma unroll
     for (int i = 0; i < kGFM; ++i)
 #pragma unroll
       for (int j = 0; j < kGFN; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int64_t row = m0 + wm * kGWTM + i * 32 + 8 * (r / 4) + 4 * half + r % 4;
-          const int64_t col = n0 + wn * kGWTN + j * 32 + col32;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wm * kGWTM + i * 16 + 4 * quarter + r;
+          const int64_t col = n0 + wn * kGWTN + j * 16 + c16;
           if (row < M && col < N) Cm[row * ldc + col] = acc[i][j][r];
         }
   }

@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(HERE, "libdesc_hand.so")
 # The one configuration of each library kernel that the twins mirror; the
 # comparison sets the library to these.
 VIEW_CONFIGS = {"reduce_i32": "b256_u4_nt", "scan_i32": "b1024_r16_nt", "transpose_32": "t128",
-                "gemm_f32": "m128n128k16_rm_d2"}
+                "gemm_f32": "m128n128k16_rm_d2_x16"}
 
 
 def build() -> str:

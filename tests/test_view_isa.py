@@ -55,9 +55,9 @@ PAIRS = [
     ("transpose.hip",
      "transpose32_kernel<desc::(anonymous namespace)::TransposeCfg<128, false>, false>",
      "hand::transpose32_hand<false>", 1.0),
-    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2>, true>",
+    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2, true>, true>",
      "hand::gemm_f32_hand<true>", 1.05),
-    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2>, false>",
+    ("gemm_f32.hip", "gemm_f32w_kernel<desc::gemm_f32::GemmCfgF32W<128, 128, 16, 2, 2, 2, true>, false>",
      "hand::gemm_f32_hand<false>", 1.12),
 ]
 
