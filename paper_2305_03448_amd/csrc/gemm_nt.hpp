@@ -395,7 +395,13 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  // Matrix ops of one stage from LDS buffer `stage`.
+  // Matrix ops of one stage from LDS buffer `stage`.  A lane's fragments of
+  // one step lie whole 32-row blocks apart, where the swizzle repeats (its
+  // period, rows_per_256 x chunks rows, divides 32): the view gives the
+  // chunk addresses of the first fragment, the others are constant offsets
+  // from them (LDS read immediates).
+  static_assert(32 % (C::rows_per_256 * C::chunks) == 0, "the swizzle repeats every 32 rows");
+  constexpr int kFragStride = 32 * C::chunks;   // 16-byte chunks between fragments
   auto compute = [&](int stage) {
 #pragma unroll
     for (int st = 0; st < C::steps; ++st) {
@@ -405,17 +411,19 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
 #pragma unroll
       for (int pl = 0; pl < P; ++pl) {
         auto s = plane(stage, pl);
+        const u32x4* a0 = &s.at(wm * C::wtm + col32, ch);
+        const u32x4* b0 = &s.at(C::bm + wn * C::wtn + col32, ch);
+        const u32x4* a1 = &s.at(wm * C::wtm + col32, ch + (LB == 32 ? 1 : 0));
+        const u32x4* b1 = &s.at(C::bm + wn * C::wtn + col32, ch + (LB == 32 ? 1 : 0));
 #pragma unroll
         for (int i = 0; i < C::fm; ++i) {
-          const idx_t row = wm * C::wtm + i * 32 + col32;
-          if constexpr (LB == 16) fa[pl][i].v = s.at(row, ch);
-          else { fa[pl][i].v0 = s.at(row, ch); fa[pl][i].v1 = s.at(row, ch + 1); }
+          if constexpr (LB == 16) fa[pl][i].v = a0[i * kFragStride];
+          else { fa[pl][i].v0 = a0[i * kFragStride]; fa[pl][i].v1 = a1[i * kFragStride]; }
         }
 #pragma unroll
         for (int j = 0; j < C::fn; ++j) {
-          const idx_t row = C::bm + wn * C::wtn + j * 32 + col32;
-          if constexpr (LB == 16) fb[pl][j].v = s.at(row, ch);
-          else { fb[pl][j].v0 = s.at(row, ch); fb[pl][j].v1 = s.at(row, ch + 1); }
+          if constexpr (LB == 16) fb[pl][j].v = b0[j * kFragStride];
+          else { fb[pl][j].v0 = b0[j * kFragStride]; fb[pl][j].v1 = b1[j * kFragStride]; }
         }
       }
 #pragma unroll
@@ -448,8 +456,6 @@ __device__ __forceinline__ void tile_from(const Src& src, const NtEpilogue& p, i
     // blocks apart: the chunk addresses of its first fragment come from the
     // view, the others are constant offsets from them (LDS read immediates
     // instead of an address computation per read).
-    static_assert(32 % (C::rows_per_256 * C::chunks) == 0, "the swizzle repeats every 32 rows");
-    constexpr int kFragStride = 32 * C::chunks;   // 16-byte chunks between fragments
     const u32x4* first[2][C::steps][2];
 #pragma unroll
     for (int st = 0; st < C::steps; ++st)
