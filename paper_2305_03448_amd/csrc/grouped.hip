@@ -34,7 +34,7 @@ namespace {
 constexpr int kBlock = 256;
 using BigTile = GemmCfgF32<128, 128, 16>;
 using SmallTile = GemmCfgF32<64, 64, 16>;
-using SmallTileRm = gemm_f32::GemmCfgF32W<64, 64, 16, 2, 2, 2>;   // row-major A, two stages ahead
+using SmallTileRm = gemm_f32::GemmCfgF32W<64, 64, 16, 2, 2, 2, true>;   // row-major A, two stages ahead, 16x16x4
 
 struct GroupedWs {
   int64_t* total;        // tiles over all problems
