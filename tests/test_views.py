@@ -37,6 +37,8 @@ EXPECTED = [
     # the FP32 GEMM's LDS double buffer under its two-stages-ahead schedule
     "access_check_gemm_double_buffer_clean",
     "access_check_gemm_double_buffer_without_a_barrier_races",
+    "access_check_gemm16_double_buffer_clean",
+    "access_check_gemm16_double_buffer_without_a_barrier_races",
     "segmented_units_cover_every_segment_once",
     "segmented_lookback_windows_stay_in_segment",
     "access_check_segmented_scan_clean",

@@ -662,6 +662,88 @@ int main(int argc, char** argv) {
     }
     check(all_racy, "access_check_gemm_double_buffer_without_a_barrier_races");
   }
+  // --- the same with the shipped 16 x 16 x 4 form (gemm_f32.hpp tile_rowmajor, k16):
+  // 128 x 128 x 16, 2 x 2 waves of 64 x 64, the four k quarters on the instruction's
+  // four k slots.  Every
+  // stage's fragment reads find words written by an earlier phase, and no read meets
+  // a write of the same buffer between the same two barriers; dropping any one of
+  // the loop's barriers makes the next phase's stores race its reads.
+  {
+    constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2, T = 64 * WM * WN;
+    constexpr int WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
+    constexpr int PA = BK + 4, PB = BN + 4, AV = BM * BK / 4 / T, BV = BK * BN / 4 / T;
+    auto replay = [&](int nk, int drop_barrier, long* uninit) {
+      std::vector<float> lds(2 * BM * PA + 2 * BK * PB);
+      std::vector<char> written(lds.size(), 0);
+      auto a_lds = matrices(lds.data(), 2, BM, PA);
+      auto b_lds = matrices(lds.data() + 2 * BM * PA, 2, BK, PB);
+      access_check::Checker c;
+      int barrier_no = 0;
+      auto sync_ = [&]() { if (barrier_no++ != drop_barrier) c.sync(0); };
+      auto store = [&](int buf) {
+        for (int t = 0; t < T; ++t) {
+          for (int i = 0; i < AV; ++i) {
+            const int q = t + T * i;
+            for (int e = 0; e < 4; ++e) {
+              float* w = &a_lds.idx(buf).at(layout::gemm_store_row<BK>(q), layout::gemm_store_word<BK>(q) + e);
+              c.write(0, t, w); written[w - lds.data()] = 1;
+            }
+          }
+          for (int i = 0; i < BV; ++i) {
+            const int q = t + T * i;
+            for (int e = 0; e < 4; ++e) {
+              float* w = &b_lds.idx(buf).at(layout::gemm_store_row<BN>(q), layout::gemm_store_word<BN>(q) + e);
+              c.write(0, t, w); written[w - lds.data()] = 1;
+            }
+          }
+        }
+      };
+      auto compute = [&](int buf) {
+        for (int t = 0; t < T; ++t) {
+          const int w = t / 64, l = t % 64, quarter = l / 16, c16 = l % 16, wm = w / WN, wn = w % WN;
+          for (int i = 0; i < FM; ++i)
+            for (int e = 0; e < 4; ++e) {
+              float* r = &a_lds.idx(buf).at(layout::gemm16_a_frag_row<WTM>(wm, i, c16),
+                                            layout::gemm16_frag_k<BK>(quarter) + e);
+              c.read(0, t, r); *uninit += !written[r - lds.data()];
+            }
+          for (int kk = 0; kk < 4; ++kk)
+            for (int j = 0; j < FN; ++j) {
+              float* r = &b_lds.idx(buf).at(layout::gemm16_frag_k<BK>(quarter) + kk,
+                                            layout::gemm16_b_frag_word<WTN>(wn, j, c16));
+              c.read(0, t, r); *uninit += !written[r - lds.data()];
+            }
+        }
+      };
+      // the schedule of tile_rowmajor with kDepth = 2
+      store(0);
+      sync_();
+      int kt = 0;
+      for (; kt + 3 < nk; kt += 2) {
+        compute(0); store(1); sync_();
+        compute(1); store(0); sync_();
+      }
+      if (kt < nk) { compute(0); if (kt + 1 < nk) store(1); sync_(); }
+      if (kt + 1 < nk) { compute(1); if (kt + 2 < nk) store(0); sync_(); }
+      if (kt + 2 < nk) { compute(0); sync_(); }
+      return std::make_pair(c.conflicts(64).size(), barrier_no);
+    };
+    bool ok = true;
+    long uninit = 0;
+    int barriers = 0;
+    for (int nk : {1, 2, 3, 4, 5, 6, 7}) {
+      auto r = replay(nk, -1, &uninit);
+      ok &= r.first == 0;
+      barriers = r.second;
+    }
+    check(ok && uninit == 0, "access_check_gemm16_double_buffer_clean");
+    bool all_racy = true;
+    for (int drop = 0; drop < barriers - 1; ++drop) {
+      long u = 0;
+      all_racy &= replay(7, drop, &u).first > 0;
+    }
+    check(all_racy, "access_check_gemm16_double_buffer_without_a_barrier_races");
+  }
 
   // --- segmented forms (segmented.hip): the unit map, the look-back windows and the
   // stores, with a unit of 2 waves x 2 rounds x 256 = 1024 elements (the kernels'
