@@ -316,14 +316,15 @@ __global__ __launch_bounds__(kBlock) void fp8_prepass_kernel(
     quant_row(A, M, K, lda, qa, rows_out, k_out, ldqa, sa, a_vec_in, true, blk - col_blocks);
 }
 
-// Encode 64 x 64 tiles of B with their column scales and write them
-// transposed: qt is n_out x k_out (stride ldq).  A block takes one k tile of
-// one column block (four k tiles per block, sharing the gathered maxima,
-// measured slower: fewer blocks in flight); the first block of each column
+// Encode tiles of kKT k x 64 columns of B with their column scales and
+// write them transposed: qt is n_out x k_out (stride ldq), so a tile's
+// output rows are kKT bytes: whole 128-byte lines at kKT = 128.  A block
+// takes one k tile of one column block; the first block of each column
 // block also writes the column scales.  The tile's loads are issued before
 // the column maxima are gathered from the slice partials, so the two sets
 // of loads are in flight together.  Reads run along n (thread = 4 columns
 // of one row), writes along k (thread = 4 consecutive k, one 4-byte store).
+template <int kKT>
 __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __restrict__ B,
                                                               int64_t K, int64_t N, int64_t ldb,
                                                               const float* __restrict__ part,
@@ -333,21 +334,25 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
                                                               int64_t ldq,
                                                               float* __restrict__ scale,
                                                               bool vec_in, bool vec_out) {
-  __shared__ uint8_t codes[64 * 68];
+  static_assert(kKT % 16 == 0 && kKT / 4 <= kBlock && kBlock % (kKT / 4) == 0, "tile shape");
+  constexpr int kRows = kKT / 16;               // rows of the tile per thread
+  constexpr int kLanesPerRow = kKT / 4;         // threads per output row
+  constexpr int kOutRows = kBlock / kLanesPerRow;
+  __shared__ uint8_t codes[kKT * 68];
   __shared__ float inv_s[64];
   __shared__ float pmax[4][64];
   auto kt = block_x();
   auto nt = block_y();
   auto thread = thread_x<kBlock>();
-  auto tile = matrix(codes, 64, 68);
+  auto tile = matrix(codes, kKT, 68);
   auto b = matrix(B, K, ldb);
   auto pm = matrix(part, nslices, ldp);
   auto out = matrix(qt, n_out, ldq);
-  const idx_t n0 = nt.index() * 64, k0 = kt.index() * 64;
+  const idx_t n0 = nt.index() * 64, k0 = kt.index() * kKT;
   const int tx = (int)thread.index() % 16, ty = (int)thread.index() / 16;
-  f32x4 v[4];
+  f32x4 v[kRows];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {                 // rows ty + 16 i, columns 4 tx ..
+  for (int i = 0; i < kRows; ++i) {             // rows ty + 16 i, columns 4 tx ..
     const idx_t r = ty + 16 * i, c = 4 * tx;
     if (vec_in && k0 + r < K && n0 + c + 4 <= N) {
       v[i] = *(const f32x4*)&b.at(k0 + r, n0 + c);
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
   }
   sync(thread);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kRows; ++i) {
     const idx_t r = ty + 16 * i, c = 4 * tx;
     uint32_t keep = 0;
 #pragma unroll
@@ -389,9 +394,10 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
     *(u8x4*)&tile.at(r, c) = __builtin_bit_cast(u8x4, w);
   }
   sync(thread);
+  const int ox = (int)thread.index() % kLanesPerRow, oy = (int)thread.index() / kLanesPerRow;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {                 // output rows ty + 16 i, k = 4 tx ..
-    const idx_t c = ty + 16 * i, r = 4 * tx;
+  for (int i = 0; i < 64 / kOutRows; ++i) {     // output rows oy + kOutRows i, k = 4 ox ..
+    const idx_t c = oy + kOutRows * i, r = 4 * ox;
     if (n0 + c >= n_out) continue;
     u8x4 e;
 #pragma unroll
@@ -404,6 +410,27 @@ __global__ __launch_bounds__(kBlock) void quant_cols_t_kernel(const float* __res
         if (k0 + r + j < k_out) out.at(n0 + c, k0 + r + j) = e[j];
     }
   }
+}
+// The encode's k tile: 64 up to 8192 tiles of 64 x 64, 128 beyond (whole
+// 128-byte output lines; measured at 8192^2: 75 against 90 us; at 4096^2 the
+// 64-k tiles keep twice the blocks in flight: 18.5 against 20.7 us).
+template <class F>
+hipError_t launch_cols_t(int64_t K, int64_t N, hipStream_t s, F&& args) {
+  const int64_t t64 = ((K + 63) / 64) * ((N + 63) / 64);
+  if (t64 > 8192) {
+    args([&](auto... a) {
+      hipLaunchKernelGGL(quant_cols_t_kernel<128>,
+                         dim3((unsigned)((K + 127) / 128), (unsigned)((N + 63) / 64)),
+                         dim3(kBlock), 0, s, a...);
+    });
+  } else {
+    args([&](auto... a) {
+      hipLaunchKernelGGL(quant_cols_t_kernel<64>,
+                         dim3((unsigned)((K + 63) / 64), (unsigned)((N + 63) / 64)),
+                         dim3(kBlock), 0, s, a...);
+    });
+  }
+  return hipGetLastError();
 }
 
 int64_t colmax_slices(int64_t K, int64_t N) {
@@ -561,11 +588,10 @@ hipError_t quant_e4m3_cols(const float* B, int64_t K, int64_t N, int64_t ldb, ui
   hipLaunchKernelGGL(colmax_partial_kernel,
                      dim3((unsigned)((N + 4 * kBlock - 1) / (4 * kBlock)), (unsigned)S),
                      dim3(kBlock), 0, s, B, K, N, ldb, rows_per, part, N, f4_ok(B, ldb));
-  hipLaunchKernelGGL(quant_cols_t_kernel,
-                     dim3((unsigned)((K + 63) / 64),
-                          (unsigned)((N + 63) / 64)),
-                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, N, qt, N, K, ldq, scale,
-                     f4_ok(B, ldb), w_ok(qt, ldq, 1));
+  const bool vin = f4_ok(B, ldb), vout = w_ok(qt, ldq, 1);
+  launch_cols_t(K, N, s, [&](auto&& go) {
+    go(B, K, N, ldb, (const float*)part, S, N, qt, N, K, ldq, scale, vin, vout);
+  });
   return hipGetLastError();
 }
 
@@ -613,11 +639,10 @@ hipError_t gemm_fp8(const float* A, int64_t lda, const float* B, int64_t ldb, fl
   hipLaunchKernelGGL(fp8_prepass_kernel, dim3((unsigned)(cblocks * S + L.Mp)), dim3(kBlock), 0, s,
                      A, M, K, lda, qa, L.Mp, L.Kp, L.Kp, sa, f4_ok(A, lda), B, N, ldb, rows_per,
                      part, L.Np, f4_ok(B, ldb), cblocks, S);
-  hipLaunchKernelGGL(quant_cols_t_kernel,
-                     dim3((unsigned)(L.Kp / 64),
-                          (unsigned)(L.Np / 64)),
-                     dim3(kBlock), 0, s, B, K, N, ldb, part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb,
-                     f4_ok(B, ldb), true);
+  const bool vin = f4_ok(B, ldb);
+  launch_cols_t(L.Kp, L.Np, s, [&](auto&& go) {
+    go(B, K, N, ldb, (const float*)part, S, L.Np, qb, L.Np, L.Kp, L.Kp, sb, vin, true);
+  });
   NtOperands p{{qa, nullptr}, {qb, nullptr}, L.Kp, Cm, ldc, M, N, sa, sb};
   switch (tune::get(tune::kGemmFp8, tune::size_class(tune::kGemmFp8, M * N * K))) {
     case 1: return launch_nt<NtCfg<128, 128, 64, Fp8Mode>>(p, L.Mp, L.Np, s);

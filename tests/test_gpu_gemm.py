@@ -311,7 +311,9 @@ def test_split_bf16_rows_cols_bit_exact(M, K):
     assert np.array_equal(lt.cpu().numpy().view(np.uint16), lo)
 
 
-@pytest.mark.parametrize("M,K", [(1, 1), (5, 70), (129, 300), (600, 2048)])
+# (8200, 4100): the column encode of a 4100 x 8200 B has more than 8192 tiles of
+# 64 x 64, so it runs in 128-k tiles, with a ragged last k tile and column block
+@pytest.mark.parametrize("M,K", [(1, 1), (5, 70), (129, 300), (600, 2048), (8200, 4100)])
 def test_quant_e4m3_rows_cols_bit_exact(M, K):
     case(f"quant e4m3 rows/cols {M}x{K}")
     A = workloads.matrix_f32(M, K, seed=12) * np.float32(3.0)
